@@ -1,0 +1,190 @@
+/*
+ * mdr.h -- C ABI of the MI355X (gfx950) bitplane refactor / progressive retrieve
+ * library, after HP-MDR (arXiv 2505.00227).
+ *
+ * Plain C: opaque handles, plain pointers and sizes, no C++ exceptions cross
+ * this boundary.  Device pointers are HIP device memory on the context's
+ * device; `stream` arguments are hipStream_t values passed as void* (NULL =
+ * the device's default stream).  Every function returns an mdr_status; on any
+ * error an output handle is set to NULL, retriever state is left unchanged,
+ * and mdr_last_error() returns a message for the calling thread.
+ *
+ * What the operations compute (paper sections):
+ *   refactor  = per level: alignment to the level's largest exponent and
+ *               sign/magnitude fixed point (Sec. 3, Alg. 1 step 1), bitplanes
+ *               most significant first (Sec. 3, Alg. 1 loop), an exact per-plane
+ *               L-infinity error table (MDR's error estimate, Sec. 2.2), then
+ *               hybrid lossless coding of merged plane groups (Sec. 4, Alg. 2:
+ *               Huffman / run-length / direct copy with placeholders).
+ *   retrieve  = progressive, incremental reconstruction to an error bound
+ *               (Sec. 1 and 5: fetch just enough precision segments), the
+ *               inverse of the above.
+ *   QoI       = retrieval until the V_total = vx^2+vy^2+vz^2 error estimate
+ *               meets a tolerance (Sec. 5.2, Alg. 3 with the MAPE estimator).
+ */
+#ifndef MDR_H
+#define MDR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MDR_MAX_PLANES 64
+
+typedef enum {
+    MDR_OK = 0,
+    MDR_ERR_INVALID_ARG = 1,    /* bad argument, or NaN / Inf in the input       */
+    MDR_ERR_UNSUPPORTED = 2,    /* valid request this build does not handle      */
+    MDR_ERR_OUT_OF_MEMORY = 3,  /* device or host allocation failed              */
+    MDR_ERR_HIP = 4,            /* a HIP runtime call failed                     */
+    MDR_ERR_CORRUPT_STREAM = 5, /* serialized data failed a header/size/CRC check */
+    MDR_ERR_BUSY = 6            /* resource limit reached; retry later            */
+} mdr_status;
+
+typedef enum { MDR_F32 = 0, MDR_F64 = 1 } mdr_dtype;
+
+/* lossless method of one stream (Sec. 4; placeholders are Alg. 2's empty slots) */
+typedef enum { MDR_DC = 0, MDR_RLE = 1, MDR_HUF = 2, MDR_PLACEHOLDER = 3 } mdr_method;
+
+/* MDR_REL: tolerance x (max - min over every coefficient of the variable) */
+typedef enum { MDR_ABS = 0, MDR_REL = 1 } mdr_bound;
+
+/* Codec parameters of Alg. 2.  Every field is recorded in the serialized form. */
+typedef struct {
+    uint32_t group_planes; /* m: planes per lossless group (default 4; >= 1, capped at nplanes) */
+    uint32_t t_cr_milli;   /* T_cr x 1000: ratio threshold (default 2000)                       */
+    uint64_t t_s_bytes;    /* T_s: groups of at most this many bytes are copied (default 4096)   */
+    uint32_t huf_chunk;    /* byte symbols per Huffman chunk (default 1024; 256..4096, x256)    */
+    uint32_t huf_lmax;     /* longest Huffman code (default 12; 8..12)                           */
+    int32_t force_method;  /* -1: Alg. 2 decides (default); MDR_DC/RLE/HUF: used for every unit  */
+} mdr_codec_params;
+
+/* One coefficient level: n values of the variable's dtype in device memory.
+ * Borrowed: must stay valid until the work queued on the call's stream ends. */
+typedef struct {
+    const void* data;
+    uint64_t n;
+} mdr_level_view;
+
+typedef struct {
+    double tol_abs;          /* absolute tolerance this call planned for                    */
+    double bound;            /* L-inf bound reached: sum over levels of E_l[k_l]            */
+    uint64_t bytes_fetched;  /* stream bytes this call decoded (new groups only)            */
+    uint64_t bytes_held;     /* stream bytes held by the retriever after the call           */
+    uint32_t groups_fetched; /* lossless units this call decoded                           */
+    int32_t met;             /* 1 if bound <= tol_abs, 0 if every plane is held and it is not */
+} mdr_retrieve_info;
+
+typedef struct mdr_context mdr_context;
+typedef struct mdr_refactored mdr_refactored;
+typedef struct mdr_retriever mdr_retriever;
+
+/* ---------------------------------------------------------------- library */
+const char* mdr_version(void);
+/* Message of the last failed call on this thread ("" if none).  Valid until the
+ * thread's next mdr_* call. */
+const char* mdr_last_error(void);
+/* Fills the defaults listed in mdr_codec_params. */
+mdr_status mdr_codec_params_default(mdr_codec_params* out);
+
+/* ---------------------------------------------------------------- context */
+/* A context binds one HIP device and owns reusable device workspaces.
+ * Calls on one context must not run concurrently from several host threads. */
+mdr_status mdr_context_create(int hip_device, mdr_context** out);
+void mdr_context_destroy(mdr_context* ctx);
+
+/* Per-stage device timing.  When enabled, every kernel launch of the library is
+ * bracketed by HIP events on the stream it runs on; mdr_context_timing waits for
+ * them and returns, per stage, the summed kernel milliseconds and launch counts
+ * (arrays of MDR_STAGE_COUNT entries; reset != 0 clears the totals afterwards).
+ * Timing adds a few microseconds per launch; off by default. */
+typedef enum {
+    MDR_STAGE_STATS = 0,       /* level statistics (alignment exponent)          */
+    MDR_STAGE_ENCODE = 1,      /* bitplane encoder + error table + group stats    */
+    MDR_STAGE_SELECT = 2,      /* Alg. 2 selection and Huffman codebooks          */
+    MDR_STAGE_HUF_ENCODE = 3,
+    MDR_STAGE_RLE_ENCODE = 4,
+    MDR_STAGE_HUF_DECODE = 5,
+    MDR_STAGE_RLE_DECODE = 6,
+    MDR_STAGE_RECONSTRUCT = 7, /* bitplane decoder + reconstruction               */
+    MDR_STAGE_COUNT = 8
+} mdr_stage;
+mdr_status mdr_context_set_timing(mdr_context* ctx, int enable);
+mdr_status mdr_context_timing(mdr_context* ctx, double* ms, uint64_t* launches, int reset);
+
+/* ---------------------------------------------------------------- refactor */
+/*
+ * Refactor one variable given as nlevels coefficient levels (coarsest first).
+ * Per level (Sec. 3, Alg. 1; Sec. 4, Alg. 2):
+ *   e      = largest frexp exponent of its nonzero values (|x| < 2^e; 0 if all zero);
+ *   mag    = floor(|x| * 2^(nplanes - e)), sign = sign bit;
+ *   planes = plane p holds bit nplanes-1-p of every value; value i is bit i of the
+ *            plane's little-endian byte string, padded to a whole W-bit word
+ *            (W = 32 for f32, 64 for f64);
+ *   E[k]   = max |x - xhat^(k)| after k planes, k = 0..nplanes (exact);
+ *   units  = the sign plane, then groups of m planes, each coded DC/RLE/HUF.
+ * nplanes: 1..32 for f32, 1..64 for f64 (else MDR_ERR_UNSUPPORTED).
+ * NaN or Inf anywhere -> MDR_ERR_INVALID_ARG.  A level may be empty (n = 0).
+ * `params` may be NULL (defaults).  Work is queued on `stream`; the call returns
+ * after the small metadata (sizes, methods, error tables) is on the host.
+ * The result owns its device streams; free with mdr_refactored_destroy.
+ */
+mdr_status mdr_refactor(mdr_context* ctx, const mdr_level_view* levels, uint32_t nlevels,
+                        mdr_dtype dtype, uint32_t nplanes, const mdr_codec_params* params,
+                        void* stream, mdr_refactored** out);
+void mdr_refactored_destroy(mdr_refactored* r);
+
+mdr_status mdr_refactored_shape(const mdr_refactored* r, uint32_t* nlevels, mdr_dtype* dtype,
+                                uint32_t* nplanes, mdr_codec_params* params);
+/* Level metadata: e, n, min, max (a zero of either sign reads +0.0), and
+ * error_table[0..nplanes] (exact values of the dtype, widened to double).
+ * Any output pointer may be NULL. */
+mdr_status mdr_refactored_info(const mdr_refactored* r, uint32_t level, int32_t* e, uint64_t* n,
+                               double* vmin, double* vmax, double* error_table);
+/* One stream of a level: stream -1 = sign plane, 0..nplanes-1 = magnitude plane p
+ * (a group's payload sits at its leading plane; the group's other planes are
+ * MDR_PLACEHOLDER with 0 bytes).  *dev_ptr points into memory owned by r. */
+mdr_status mdr_refactored_stream(const mdr_refactored* r, uint32_t level, int32_t stream,
+                                 const void** dev_ptr, uint64_t* bytes, mdr_method* method);
+
+/* Container (Sec. 5.1 serialization): little-endian header, per-level records
+ * with error tables, stream table with CRC-32 per payload, payloads.
+ * cap = 0 (host may be NULL) -> *used = required size, MDR_OK. */
+mdr_status mdr_serialize(const mdr_refactored* r, void* host, uint64_t cap, uint64_t* used);
+/* Validates magic, version, sizes and every CRC (MDR_ERR_CORRUPT_STREAM on any
+ * mismatch), then uploads the streams to the context's device. */
+mdr_status mdr_deserialize(mdr_context* ctx, const void* host, uint64_t bytes,
+                           mdr_refactored** out);
+
+/* ---------------------------------------------------------------- retrieve */
+/* A retriever holds, for one refactored variable, the planes fetched so far
+ * (per level) and the decoded form of its compressed groups.  `r` must outlive it. */
+mdr_status mdr_retriever_create(mdr_context* ctx, const mdr_refactored* r, mdr_retriever** out);
+void mdr_retriever_destroy(mdr_retriever* rt);
+
+/*
+ * Progressive, incremental retrieval: plan (greedy, from the planes already held)
+ * the planes per level whose bound sum_l E_l[k_l] <= tol (absolute, or relative
+ * to the variable's value range), decode only groups not held yet, and write
+ * every level's reconstruction x = (-1)^sign * (top k_l bits of mag) * 2^(e - nplanes)
+ * to level_out[l] (device, n_l values of the dtype; k_l = 0 writes +0.0).
+ * The result equals a fresh retrieval to the same planes, bit for bit.
+ * A tolerance below the all-planes bound returns MDR_OK with info->met = 0.
+ * Queued on `stream`; `info` (may be NULL) is filled on return.
+ */
+mdr_status mdr_retrieve(mdr_retriever* rt, mdr_bound kind, double tol, void* const* level_out,
+                        void* stream, mdr_retrieve_info* info);
+/* Same, with the planes per level given explicitly (each k_l is rounded up to a
+ * whole group and may not go below what is already held). */
+mdr_status mdr_retrieve_planes(mdr_retriever* rt, const uint32_t* k, void* const* level_out,
+                               void* stream, mdr_retrieve_info* info);
+/* Planes currently held per level (nlevels entries). */
+mdr_status mdr_retriever_planes(const mdr_retriever* rt, uint32_t* k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDR_H */

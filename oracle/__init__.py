@@ -357,8 +357,11 @@ def serialize(levels, params: Params | None = None) -> bytes:
 # ---------------------------------------------------------------- planner
 def variable_range(levels) -> float:
     """max - min over every coefficient of the variable (for relative bounds)."""
-    lo = min(lv.vmin for lv in levels)
-    hi = max(lv.vmax for lv in levels)
+    nonempty = [lv for lv in levels if lv.n]
+    if not nonempty:
+        return 0.0
+    lo = min(lv.vmin for lv in nonempty)
+    hi = max(lv.vmax for lv in nonempty)
     return float(hi) - float(lo)
 
 

@@ -1,0 +1,303 @@
+"""Python binding of libmdr: bitplane refactor / progressive retrieve on MI355X.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libmdr.so`` behind the C ABI declared in ``include/mdr.h``.  The raw ABI
+functions are exposed under their C names (``mdr_refactor``, ``mdr_retrieve``,
+...); ``Context`` / ``Refactored`` / ``Retriever`` wrap the handles for torch
+tensors (device memory and streams come from PyTorch).
+
+Importing fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+# torch ships its own HIP runtime whose SONAME equals the system one
+# (libamdhip64.so.7).  Loading torch first makes libmdr.so bind to that same
+# runtime, so one process has one HIP runtime: torch's tensors, streams and
+# synchronizations and this library's launches share queues and state.
+import torch  # noqa: E402,F401  (must precede the CDLL below)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdr.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libmdr.so is not built; run `python paper_2505_00227_amd/build.py` "
+        "(or __graft_entry__.build()) first")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- ABI types
+MDR_OK, MDR_ERR_INVALID_ARG, MDR_ERR_UNSUPPORTED, MDR_ERR_OUT_OF_MEMORY = 0, 1, 2, 3
+MDR_ERR_HIP, MDR_ERR_CORRUPT_STREAM, MDR_ERR_BUSY = 4, 5, 6
+MDR_F32, MDR_F64 = 0, 1
+MDR_DC, MDR_RLE, MDR_HUF, MDR_PLACEHOLDER = 0, 1, 2, 3
+MDR_ABS, MDR_REL = 0, 1
+MDR_MAX_PLANES = 64
+STAGES = ["stats", "encode", "select", "huf_encode", "rle_encode", "huf_decode", "rle_decode",
+          "reconstruct"]
+STATUS_NAMES = {0: "MDR_OK", 1: "MDR_ERR_INVALID_ARG", 2: "MDR_ERR_UNSUPPORTED",
+                3: "MDR_ERR_OUT_OF_MEMORY", 4: "MDR_ERR_HIP", 5: "MDR_ERR_CORRUPT_STREAM",
+                6: "MDR_ERR_BUSY"}
+
+
+class mdr_codec_params(C.Structure):
+    _fields_ = [("group_planes", C.c_uint32), ("t_cr_milli", C.c_uint32),
+                ("t_s_bytes", C.c_uint64), ("huf_chunk", C.c_uint32), ("huf_lmax", C.c_uint32),
+                ("force_method", C.c_int32)]
+
+
+class mdr_level_view(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("n", C.c_uint64)]
+
+
+class mdr_retrieve_info(C.Structure):
+    _fields_ = [("tol_abs", C.c_double), ("bound", C.c_double), ("bytes_fetched", C.c_uint64),
+                ("bytes_held", C.c_uint64), ("groups_fetched", C.c_uint32), ("met", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp, _u32, _u64, _i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
+_P = C.POINTER
+_SIGS = {
+    "mdr_version": ([], C.c_char_p),
+    "mdr_last_error": ([], C.c_char_p),
+    "mdr_codec_params_default": ([_P(mdr_codec_params)], C.c_int),
+    "mdr_context_create": ([C.c_int, _P(_vp)], C.c_int),
+    "mdr_context_destroy": ([_vp], None),
+    "mdr_context_set_timing": ([_vp, C.c_int], C.c_int),
+    "mdr_context_timing": ([_vp, _P(C.c_double), _P(_u64), C.c_int], C.c_int),
+    "mdr_refactor": ([_vp, _P(mdr_level_view), _u32, C.c_int, _u32, _P(mdr_codec_params), _vp,
+                      _P(_vp)], C.c_int),
+    "mdr_refactored_destroy": ([_vp], None),
+    "mdr_refactored_shape": ([_vp, _P(_u32), _P(C.c_int), _P(_u32), _P(mdr_codec_params)], C.c_int),
+    "mdr_refactored_info": ([_vp, _u32, _P(_i32), _P(_u64), _P(C.c_double), _P(C.c_double),
+                             _P(C.c_double)], C.c_int),
+    "mdr_refactored_stream": ([_vp, _u32, _i32, _P(_vp), _P(_u64), _P(C.c_int)], C.c_int),
+    "mdr_serialize": ([_vp, _vp, _u64, _P(_u64)], C.c_int),
+    "mdr_deserialize": ([_vp, _vp, _u64, _P(_vp)], C.c_int),
+    "mdr_retriever_create": ([_vp, _vp, _P(_vp)], C.c_int),
+    "mdr_retriever_destroy": ([_vp], None),
+    "mdr_retrieve": ([_vp, C.c_int, C.c_double, _P(_vp), _vp, _P(mdr_retrieve_info)], C.c_int),
+    "mdr_retrieve_planes": ([_vp, _P(_u32), _P(_vp), _vp, _P(mdr_retrieve_info)], C.c_int),
+    "mdr_retriever_planes": ([_vp, _P(_u32)], C.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+    globals()[_name] = _f
+
+
+class MdrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _check(st: int) -> None:
+    if st != MDR_OK:
+        raise MdrError(st, _lib.mdr_last_error().decode(errors="replace"))
+
+
+def version() -> str:
+    return _lib.mdr_version().decode()
+
+
+def default_params(**overrides) -> mdr_codec_params:
+    p = mdr_codec_params()
+    _check(_lib.mdr_codec_params_default(C.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- HIP copies for inspection
+_hip = None
+
+
+def _hip_lib():
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so.7")  # resolves to the runtime already loaded
+        _hip.hipMemcpy.argtypes = [_vp, _vp, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+        _hip.hipDeviceSynchronize.restype = C.c_int
+    return _hip
+
+
+def device_bytes(ptr: int, n: int) -> bytes:
+    """Copy n bytes of device memory to the host (synchronizes the device)."""
+    if n == 0:
+        return b""
+    h = _hip_lib()
+    if h.hipDeviceSynchronize() != 0:
+        raise RuntimeError("hipDeviceSynchronize failed")
+    buf = C.create_string_buffer(n)
+    if h.hipMemcpy(C.cast(buf, _vp), C.c_void_p(ptr), n, 2) != 0:  # hipMemcpyDeviceToHost
+        raise RuntimeError("hipMemcpy failed")
+    return buf.raw
+
+
+# ---------------------------------------------------------------- handles
+class Context:
+    """One HIP device and its reusable workspaces (mdr_context)."""
+
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(_lib.mdr_context_create(device, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mdr_context_destroy(self.handle)
+            self.handle = None
+
+    def set_timing(self, enable: bool = True) -> None:
+        _check(_lib.mdr_context_set_timing(self.handle, 1 if enable else 0))
+
+    def timing(self, reset: bool = True) -> dict:
+        """{stage: (milliseconds, launches)} of the kernels timed since the last reset."""
+        ms = (C.c_double * len(STAGES))()
+        n = (_u64 * len(STAGES))()
+        _check(_lib.mdr_context_timing(self.handle, ms, n, 1 if reset else 0))
+        return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+    def __del__(self):
+        self.close()
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return MDR_F32
+    if t.dtype == torch.float64:
+        return MDR_F64
+    raise TypeError("levels must be float32 or float64 tensors")
+
+
+class Refactored:
+    """Refactored variable (mdr_refactored): plane streams + error tables on the device."""
+
+    def __init__(self, ctx: Context, handle):
+        self.ctx = ctx
+        self.handle = handle
+        nl, dt, B = _u32(), C.c_int(), _u32()
+        prm = mdr_codec_params()
+        _check(_lib.mdr_refactored_shape(handle, C.byref(nl), C.byref(dt), C.byref(B), C.byref(prm)))
+        self.nlevels, self.dtype, self.nplanes, self.params = nl.value, dt.value, B.value, prm
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mdr_refactored_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self, level: int) -> dict:
+        e, n = _i32(), _u64()
+        lo, hi = C.c_double(), C.c_double()
+        E = (C.c_double * (self.nplanes + 1))()
+        _check(_lib.mdr_refactored_info(self.handle, level, C.byref(e), C.byref(n), C.byref(lo),
+                                        C.byref(hi), E))
+        return {"e": e.value, "n": n.value, "vmin": lo.value, "vmax": hi.value, "E": list(E)}
+
+    def stream(self, level: int, stream: int):
+        """(device pointer, bytes, method) of stream -1 (sign) or plane 0..nplanes-1."""
+        p, nb, meth = _vp(), _u64(), C.c_int()
+        _check(_lib.mdr_refactored_stream(self.handle, level, stream, C.byref(p), C.byref(nb),
+                                          C.byref(meth)))
+        return (p.value or 0), nb.value, meth.value
+
+    def stream_bytes(self, level: int, stream: int) -> bytes:
+        p, nb, _ = self.stream(level, stream)
+        return device_bytes(p, nb)
+
+    def serialize(self) -> bytes:
+        used = _u64()
+        _check(_lib.mdr_serialize(self.handle, None, 0, C.byref(used)))
+        buf = C.create_string_buffer(used.value)
+        _check(_lib.mdr_serialize(self.handle, C.cast(buf, _vp), used.value, C.byref(used)))
+        return buf.raw[:used.value]
+
+    @classmethod
+    def deserialize(cls, ctx: Context, blob: bytes) -> "Refactored":
+        h = _vp()
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(_lib.mdr_deserialize(ctx.handle, C.cast(buf, _vp), len(blob), C.byref(h)))
+        return cls(ctx, h)
+
+
+def refactor(ctx: Context, levels, nplanes: int, params: mdr_codec_params | None = None,
+             stream=None) -> Refactored:
+    """mdr_refactor on a list of contiguous device tensors (one per level, coarsest first)."""
+    if not levels:
+        raise ValueError("no levels")
+    dt = _dtype_code(levels[0])
+    views = (mdr_level_view * len(levels))()
+    for i, t in enumerate(levels):
+        if _dtype_code(t) != dt or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("levels must be contiguous device tensors of one dtype")
+        views[i].data = t.data_ptr() if t.numel() else None
+        views[i].n = t.numel()
+    h = _vp()
+    _check(_lib.mdr_refactor(ctx.handle, views, len(levels), dt, nplanes,
+                             C.byref(params) if params is not None else None,
+                             _stream_ptr(stream), C.byref(h)))
+    return Refactored(ctx, h)
+
+
+class Retriever:
+    """Progressive / incremental retrieval state of one refactored variable (mdr_retriever)."""
+
+    def __init__(self, ctx: Context, r: Refactored):
+        h = _vp()
+        _check(_lib.mdr_retriever_create(ctx.handle, r.handle, C.byref(h)))
+        self.ctx, self.r, self.handle = ctx, r, h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mdr_retriever_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    @staticmethod
+    def _outs(outs):
+        arr = (_vp * len(outs))()
+        for i, t in enumerate(outs):
+            arr[i] = t.data_ptr() if t.numel() else None
+        return arr
+
+    def retrieve(self, tol: float, outs, relative: bool = True, stream=None) -> dict:
+        info = mdr_retrieve_info()
+        _check(_lib.mdr_retrieve(self.handle, MDR_REL if relative else MDR_ABS, float(tol),
+                                 self._outs(outs), _stream_ptr(stream), C.byref(info)))
+        return info.as_dict()
+
+    def retrieve_planes(self, k, outs, stream=None) -> dict:
+        kk = (_u32 * len(k))(*[int(v) for v in k])
+        info = mdr_retrieve_info()
+        _check(_lib.mdr_retrieve_planes(self.handle, kk, self._outs(outs), _stream_ptr(stream),
+                                        C.byref(info)))
+        return info.as_dict()
+
+    def planes(self):
+        k = (_u32 * self.r.nlevels)()
+        _check(_lib.mdr_retriever_planes(self.handle, k))
+        return list(k)
