@@ -424,8 +424,9 @@ def qoi_initial_eps(vars3, tau: float):
     Q_max = sum_c max(|min_c|, |max_c|)^2 (the largest V_total the ranges allow)."""
     qmax = 0.0
     for levels in vars3:
-        lo = min(lv.vmin for lv in levels)
-        hi = max(lv.vmax for lv in levels)
+        nonempty = [lv for lv in levels if lv.n]
+        lo = min((lv.vmin for lv in nonempty), default=0.0)
+        hi = max((lv.vmax for lv in nonempty), default=0.0)
         a = max(abs(lo), abs(hi))
         qmax = qmax + a * a
     if qmax == 0.0:
@@ -456,7 +457,7 @@ def retrieve_qoi_vtotal(vars3, tau: float, c: float = 10.0, k_in=None, max_iter:
         full = all(all(k == levels[0].B for k in ks[i]) for i, levels in enumerate(vars3))
         if tprime <= tau or full or it >= max_iter:
             return vals, ks, tprime, tprime <= tau, it
-        p = tprime / tau
+        p = tprime / tau if tau > 0 else math.inf
         moved = False
         if p > c:
             for i, levels in enumerate(vars3):

@@ -234,11 +234,10 @@ static int leaf_cmp(const void* a, const void* b)
  *    weight tie; merged nodes are queued in creation order;
  *  - a single distinct symbol gets a phantom partner (the smallest other
  *    symbol) so both have length 1.
- * Returns the longest length.
+ * Fills the sorted leaves and their depths; returns the number of leaves.
  */
-static int huffman_build(const uint64_t* f, uint8_t* len)
+static int huffman_tree(const uint64_t* f, leaf_t* leaves, int* depth_of_leaf)
 {
-    leaf_t leaves[256];
     int nl = 0;
     for (int s = 0; s < 256; ++s)
         if (f[s]) {
@@ -246,14 +245,7 @@ static int huffman_build(const uint64_t* f, uint8_t* len)
             leaves[nl].sym = s;
             ++nl;
         }
-    memset(len, 0, 256);
-    if (nl == 0) return 0;
-    if (nl == 1) {
-        int s0 = leaves[0].sym;
-        len[s0] = 1;
-        len[s0 == 0 ? 1 : 0] = 1;
-        return 1;
-    }
+    if (nl < 2) return nl;
     qsort(leaves, (size_t)nl, sizeof(leaf_t), leaf_cmp);
 
     uint64_t w[512];
@@ -279,33 +271,68 @@ static int huffman_build(const uint64_t* f, uint8_t* len)
     int root = next - 1;
     depth[root] = 0;
     for (int i = root - 1; i >= 0; --i) depth[i] = depth[parent[i]] + 1;
-    int maxlen = 0;
-    for (int i = 0; i < nl; ++i) {
-        len[leaves[i].sym] = (uint8_t)depth[i];
-        if (depth[i] > maxlen) maxlen = depth[i];
-    }
-    return maxlen;
+    for (int i = 0; i < nl; ++i) depth_of_leaf[i] = depth[i];
+    return nl;
 }
 
 /*
- * Length limit (reading): while the longest code exceeds lmax, halve every
- * nonzero count (rounding down, but never below 1) and rebuild.  Terminates:
- * with all counts 1 the tree is complete and balanced (depth <= 8 <= lmax).
+ * Code lengths limited to lmax.
+ * Reading (length limit): when the tree is deeper than lmax, the number of
+ * codes of each length, BITS[L], is adjusted as in ITU-T T.81 Annex K
+ * (Adjust_BITS): while some length i > lmax has codes, take two codes of
+ * length i, give one of them length i-1, and split the longest code shorter
+ * than i-1 (length j) into two codes of length j+1.  Each move keeps the code
+ * count and the Kraft sum (= 1).  The lengths are then handed out again in the
+ * leaves' (count, symbol) order: the heaviest leaves get the shortest lengths.
+ * Trees within the limit keep their own lengths.
  * Pins: Kraft equality; sum f*L equals the textbook heap Huffman cost when the
  * limit is not hit; brute-force optimal prefix code for <= 6 symbols;
- * Fibonacci counts force the limit.
+ * Fibonacci counts force the limit; limited lengths never increase with count.
  */
 int orc_huffman_lengths(const uint64_t* freq, uint32_t lmax, uint8_t* len)
 {
     if (lmax < 8 || lmax > 24) return ORC_EUNSUP;
-    uint64_t f[256];
-    memcpy(f, freq, sizeof(f));
-    for (;;) {
-        int ml = huffman_build(f, len);
-        if (ml <= (int)lmax) return ORC_OK;
-        for (int s = 0; s < 256; ++s)
-            if (f[s]) f[s] = (f[s] >> 1) ? (f[s] >> 1) : 1;
+    leaf_t leaves[256];
+    int depth[256];
+    memset(len, 0, 256);
+    int nl = huffman_tree(freq, leaves, depth);
+    if (nl == 0) return ORC_OK;
+    if (nl == 1) {
+        int s0 = leaves[0].sym;
+        len[s0] = 1;
+        len[s0 == 0 ? 1 : 0] = 1;
+        return ORC_OK;
     }
+    int maxlen = 0;
+    for (int i = 0; i < nl; ++i) maxlen = depth[i] > maxlen ? depth[i] : maxlen;
+    if (maxlen <= (int)lmax) {
+        for (int i = 0; i < nl; ++i) len[leaves[i].sym] = (uint8_t)depth[i];
+        return ORC_OK;
+    }
+    int bits[256 + 1];
+    memset(bits, 0, sizeof(bits));
+    for (int i = 0; i < nl; ++i) bits[depth[i]]++;
+    for (int i = maxlen; i > (int)lmax; --i) {
+        while (bits[i] > 0) {
+            int j = i - 2;
+            while (bits[j] == 0) --j;
+            bits[i] -= 2;
+            bits[i - 1] += 1;
+            bits[j + 1] += 2;
+            bits[j] -= 1;
+        }
+    }
+    /* heaviest leaf (last in the sorted order) gets the shortest length */
+    int L = 1, used = 0;
+    for (int i = nl - 1; i >= 0; --i) {
+        while (used == bits[L]) {
+            ++L;
+            used = 0;
+        }
+        len[leaves[i].sym] = (uint8_t)L;
+        ++used;
+    }
+    return ORC_OK;
 }
 
 /* canonical codes: symbols ordered by (length, symbol); consecutive codes */

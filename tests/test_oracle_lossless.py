@@ -103,6 +103,17 @@ def test_huffman_length_limit_fibonacci(orc):
     for lmax in (8, 10, 12, 16):
         ln = orc.huffman_lengths(freq, lmax)
         assert ln.max() <= lmax and kraft(ln) == 1
+        # a heavier symbol never gets a longer code
+        order = np.argsort(freq[:40], kind="stable")
+        assert all(ln[order[i]] >= ln[order[i + 1]] for i in range(39))
+    # random skewed counts that exceed the limit keep Kraft equality and the code count
+    rng = np.random.default_rng(12)
+    for _ in range(50):
+        f = np.zeros(256, np.uint64)
+        k = int(rng.integers(20, 257))
+        f[rng.choice(256, k, replace=False)] = (2.0 ** rng.uniform(0, 30, k)).astype(np.uint64) + 1
+        ln = orc.huffman_lengths(f, 10)
+        assert ln.max() <= 10 and kraft(ln) == 1 and int((ln > 0).sum()) == k
     msg = np.repeat(np.arange(40, dtype=np.uint8), [min(f, 500) for f in fib]).tobytes()
     for lmax in (9, 12):
         p = orc.huffman_encode(msg, 333, lmax)
