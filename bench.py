@@ -22,6 +22,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ENCODER_SRC = os.path.join(ROOT, "paper_2505_00227_amd", "csrc", "k_refactor.hip")
+TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_encode_field512_traffic.md")
+
+
+def encoder_hash() -> str:
+    import hashlib
+    return hashlib.sha256(open(ENCODER_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step of the encoder from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy of
+    known size), or None when the encoder source changed since they were taken."""
+    try:
+        vals = {}
+        for line in open(TRAFFIC_NOTE):
+            if line.startswith("machine: "):
+                for kv in line[len("machine: "):].split():
+                    k, v = kv.split("=")
+                    vals[k] = v
+        if vals.get("source_sha") != encoder_hash():
+            return None
+        return float(vals["traffic_bytes_per_step"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -117,6 +142,12 @@ def main():
     elapsed = time.perf_counter() - t0
     stages = ctx.timing(reset=True)
     ctx.set_timing(False)
+    # a plain device copy of known size (256 MiB): the reference that scales the
+    # FETCH_SIZE / WRITE_SIZE counters when this run is profiled
+    ref = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    ref_copy = ref.clone()
+    torch.cuda.synchronize()
+    del ref, ref_copy
 
     ms_step = elapsed / args.steps * 1e3
     moved = nbytes * (1 + len(w["tols"]))
@@ -167,7 +198,10 @@ def main():
         "latency_ms": {"p50": pct(50), "p99": pct(99), "count": len(lat_ms)},
         "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic() if args.config == 2 else None),
+                     "traffic_unit": "HBM bytes per step (all encoder launches)",
+                     "encoder_sha": encoder_hash(),
                      "kernel": "k_encode", "launches_per_step": enc_launches_per_step,
                      "algorithmic_bytes_per_step": enc_bytes_per_step},
         "reconstruct_kernel_gbps": ((nbytes * len(w["tols"]) * args.steps) / (rec_ms / 1e3) / 1e9

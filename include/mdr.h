@@ -105,8 +105,8 @@ typedef enum {
     MDR_STAGE_STATS = 0,       /* level statistics (alignment exponent)          */
     MDR_STAGE_ENCODE = 1,      /* bitplane encoder + error table + group stats    */
     MDR_STAGE_SELECT = 2,      /* Alg. 2 selection and Huffman codebooks          */
-    MDR_STAGE_HUF_ENCODE = 3,
-    MDR_STAGE_RLE_ENCODE = 4,
+    MDR_STAGE_LOSSLESS = 3,    /* Huffman + run-length encoding, sizes, offsets   */
+    MDR_STAGE_ASSEMBLE = 4,    /* metadata (tables, sizes, methods) to the host   */
     MDR_STAGE_HUF_DECODE = 5,
     MDR_STAGE_RLE_DECODE = 6,
     MDR_STAGE_RECONSTRUCT = 7, /* bitplane decoder + reconstruction               */
@@ -114,6 +114,16 @@ typedef enum {
 } mdr_stage;
 mdr_status mdr_context_set_timing(mdr_context* ctx, int enable);
 mdr_status mdr_context_timing(mdr_context* ctx, double* ms, uint64_t* launches, int reset);
+
+/* Launch shape of the refactor pass (the autotuner's knobs; results do not
+ * depend on them, bit for bit):
+ *   enc_target_wg   encoder workgroups a pass aims for (tiles of 256 blocks are
+ *                   split evenly among them); 64..65536, default 2304;
+ *   stats_wg_values values per statistics workgroup; 1024..2^24, default 16384.
+ * Zero leaves a knob unchanged.  `graphs` (0/1, -1 = unchanged): whether
+ * mdr_refactor_batch captures and replays HIP graphs (default 1). */
+mdr_status mdr_context_set_launch(mdr_context* ctx, uint32_t enc_target_wg, uint32_t stats_wg_values,
+                                  int graphs);
 
 /* ---------------------------------------------------------------- refactor */
 /*
@@ -130,12 +140,30 @@ mdr_status mdr_context_timing(mdr_context* ctx, double* ms, uint64_t* launches, 
  * NaN or Inf anywhere -> MDR_ERR_INVALID_ARG.  A level may be empty (n = 0).
  * `params` may be NULL (defaults).  Work is queued on `stream`; the call returns
  * after the small metadata (sizes, methods, error tables) is on the host.
+ * Stream sizes are decided on the device: payload memory is reserved for the
+ * largest stream each unit's method could produce (about S / T_cr under Alg. 2).
  * The result owns its device streams; free with mdr_refactored_destroy.
  */
 mdr_status mdr_refactor(mdr_context* ctx, const mdr_level_view* levels, uint32_t nlevels,
                         mdr_dtype dtype, uint32_t nplanes, const mdr_codec_params* params,
                         void* stream, mdr_refactored** out);
 void mdr_refactored_destroy(mdr_refactored* r);
+
+/*
+ * Refactor nvars variables at once (same dtype, nplanes and params; variable v
+ * has nlevels[v] levels at vars[v]).  Results equal nvars separate
+ * mdr_refactor calls, bit for bit.  The whole batch is one pass: one launch per
+ * stage over every level of every variable, with stream sizes decided on the
+ * device and one metadata copy at the end.  With graphs on (the default), the
+ * pass is captured as a HIP graph the first time a batch of this shape (level
+ * sizes, input alignment, params) is seen, and replayed afterwards; at most 8
+ * shapes are kept per context.  outs[v] receives variable v's handle (all NULL
+ * on error); the handles share device arenas, released with the last of them.
+ */
+mdr_status mdr_refactor_batch(mdr_context* ctx, const mdr_level_view* const* vars,
+                              const uint32_t* nlevels, uint32_t nvars, mdr_dtype dtype,
+                              uint32_t nplanes, const mdr_codec_params* params, void* stream,
+                              mdr_refactored** outs);
 
 mdr_status mdr_refactored_shape(const mdr_refactored* r, uint32_t* nlevels, mdr_dtype* dtype,
                                 uint32_t* nplanes, mdr_codec_params* params);
@@ -183,6 +211,35 @@ mdr_status mdr_retrieve_planes(mdr_retriever* rt, const uint32_t* k, void* const
                                void* stream, mdr_retrieve_info* info);
 /* Planes currently held per level (nlevels entries). */
 mdr_status mdr_retriever_planes(const mdr_retriever* rt, uint32_t* k);
+
+typedef struct {
+    double tau_abs;          /* absolute V_total tolerance the call worked to                  */
+    double tau_est;          /* final estimate tau' (every point's V_total error is <= it)     */
+    double eps[3];           /* final L-inf bounds of vx, vy, vz                               */
+    uint64_t bytes_fetched;  /* stream bytes decoded by this call, all three variables          */
+    uint32_t iterations;     /* estimate / re-plan rounds of Alg. 3                             */
+    int32_t met;             /* 1 if tau_est <= tau_abs, 0 if every plane is held and it is not */
+} mdr_qoi_info;
+
+/*
+ * Retrieval with error control on V_total = vx^2 + vy^2 + vz^2 (Sec. 5.2, Alg. 3,
+ * with the MAPE estimator).  The three retrievers must describe variables with the
+ * same dtype and the same number of values per level (points correspond one to
+ * one; recomposition is the identity).  Starting from the planes each holds:
+ *   eps_c = (tau / Q_max) * range_c, Q_max = sum_c max(|min_c|, |max_c|)^2, and each
+ *   variable is planned to eps_c; then repeat: reconstruct, eps_c = bound of the
+ *   planes held, tau' = (1 + 2^-40) * max_p sum_c eps_c (2|v_c(p)| + eps_c) (double,
+ *   x, y, z order); stop if tau' <= tau or every plane is held; else p = tau'/tau:
+ *   if p > mape_c, re-plan each variable to eps_c / p; if that adds nothing (or
+ *   p <= mape_c) fetch one more merged group per variable (minimal augmentation).
+ * kind: MDR_ABS (tau as given) or MDR_REL (tau x Q_max).  mape_c <= 0 means 10.
+ * Reconstructions are left in out_x / out_y / out_z (device, per level).
+ * On error the retrievers keep every group decoded so far (their state stays valid).
+ */
+mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_retriever* vz,
+                                   mdr_bound kind, double tau, double mape_c,
+                                   void* const* out_x, void* const* out_y, void* const* out_z,
+                                   void* stream, mdr_qoi_info* info);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ MDR_F32, MDR_F64 = 0, 1
 MDR_DC, MDR_RLE, MDR_HUF, MDR_PLACEHOLDER = 0, 1, 2, 3
 MDR_ABS, MDR_REL = 0, 1
 MDR_MAX_PLANES = 64
-STAGES = ["stats", "encode", "select", "huf_encode", "rle_encode", "huf_decode", "rle_decode",
+STAGES = ["stats", "encode", "select", "lossless", "assemble", "huf_decode", "rle_decode",
           "reconstruct"]
 STATUS_NAMES = {0: "MDR_OK", 1: "MDR_ERR_INVALID_ARG", 2: "MDR_ERR_UNSUPPORTED",
                 3: "MDR_ERR_OUT_OF_MEMORY", 4: "MDR_ERR_HIP", 5: "MDR_ERR_CORRUPT_STREAM",
@@ -50,6 +50,16 @@ class mdr_codec_params(C.Structure):
 
 class mdr_level_view(C.Structure):
     _fields_ = [("data", C.c_void_p), ("n", C.c_uint64)]
+
+
+class mdr_qoi_info(C.Structure):
+    _fields_ = [("tau_abs", C.c_double), ("tau_est", C.c_double), ("eps", C.c_double * 3),
+                ("bytes_fetched", C.c_uint64), ("iterations", C.c_uint32), ("met", C.c_int32)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["eps"] = list(self.eps)
+        return d
 
 
 class mdr_retrieve_info(C.Structure):
@@ -72,6 +82,9 @@ _SIGS = {
     "mdr_context_timing": ([_vp, _P(C.c_double), _P(_u64), C.c_int], C.c_int),
     "mdr_refactor": ([_vp, _P(mdr_level_view), _u32, C.c_int, _u32, _P(mdr_codec_params), _vp,
                       _P(_vp)], C.c_int),
+    "mdr_context_set_launch": ([_vp, _u32, _u32, C.c_int], C.c_int),
+    "mdr_refactor_batch": ([_vp, _P(_P(mdr_level_view)), _P(_u32), _u32, C.c_int, _u32,
+                            _P(mdr_codec_params), _vp, _P(_vp)], C.c_int),
     "mdr_refactored_destroy": ([_vp], None),
     "mdr_refactored_shape": ([_vp, _P(_u32), _P(C.c_int), _P(_u32), _P(mdr_codec_params)], C.c_int),
     "mdr_refactored_info": ([_vp, _u32, _P(_i32), _P(_u64), _P(C.c_double), _P(C.c_double),
@@ -84,6 +97,8 @@ _SIGS = {
     "mdr_retrieve": ([_vp, C.c_int, C.c_double, _P(_vp), _vp, _P(mdr_retrieve_info)], C.c_int),
     "mdr_retrieve_planes": ([_vp, _P(_u32), _P(_vp), _vp, _P(mdr_retrieve_info)], C.c_int),
     "mdr_retriever_planes": ([_vp, _P(_u32)], C.c_int),
+    "mdr_retrieve_qoi_vtotal": ([_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _P(_vp), _P(_vp),
+                                 _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -176,6 +191,11 @@ class Context:
         _check(_lib.mdr_context_timing(self.handle, ms, n, 1 if reset else 0))
         return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
 
+    def set_launch(self, enc_target_wg: int = 0, stats_wg_values: int = 0, graphs: int = -1) -> None:
+        """Refactor launch shape (0 / -1 leave a knob unchanged); see mdr_context_set_launch."""
+        _check(_lib.mdr_context_set_launch(self.handle, int(enc_target_wg), int(stats_wg_values),
+                                           int(graphs)))
+
     def __del__(self):
         self.close()
 
@@ -242,23 +262,45 @@ class Refactored:
         return cls(ctx, h)
 
 
-def refactor(ctx: Context, levels, nplanes: int, params: mdr_codec_params | None = None,
-             stream=None) -> Refactored:
-    """mdr_refactor on a list of contiguous device tensors (one per level, coarsest first)."""
+def _views(levels, dt=None):
     if not levels:
         raise ValueError("no levels")
-    dt = _dtype_code(levels[0])
+    dt = _dtype_code(levels[0]) if dt is None else dt
     views = (mdr_level_view * len(levels))()
     for i, t in enumerate(levels):
         if _dtype_code(t) != dt or not t.is_contiguous() or not t.is_cuda:
             raise ValueError("levels must be contiguous device tensors of one dtype")
         views[i].data = t.data_ptr() if t.numel() else None
         views[i].n = t.numel()
+    return views, dt
+
+
+def refactor(ctx: Context, levels, nplanes: int, params: mdr_codec_params | None = None,
+             stream=None) -> Refactored:
+    """mdr_refactor on a list of contiguous device tensors (one per level, coarsest first)."""
+    views, dt = _views(levels)
     h = _vp()
     _check(_lib.mdr_refactor(ctx.handle, views, len(levels), dt, nplanes,
                              C.byref(params) if params is not None else None,
                              _stream_ptr(stream), C.byref(h)))
     return Refactored(ctx, h)
+
+
+def refactor_batch(ctx: Context, variables, nplanes: int, params: mdr_codec_params | None = None,
+                   stream=None) -> list:
+    """mdr_refactor_batch: one pass over every level of every variable (each a
+    list of contiguous device tensors of one dtype); returns one Refactored each."""
+    if not variables:
+        raise ValueError("no variables")
+    dt = _dtype_code(variables[0][0])
+    keep = [_views(levels, dt)[0] for levels in variables]
+    vp = (_P(mdr_level_view) * len(keep))(*[C.cast(v, _P(mdr_level_view)) for v in keep])
+    nl = (_u32 * len(keep))(*[len(levels) for levels in variables])
+    hs = (_vp * len(keep))()
+    _check(_lib.mdr_refactor_batch(ctx.handle, vp, nl, len(keep), dt, nplanes,
+                                   C.byref(params) if params is not None else None,
+                                   _stream_ptr(stream), hs))
+    return [Refactored(ctx, _vp(h)) for h in hs]
 
 
 class Retriever:
@@ -301,3 +343,14 @@ class Retriever:
         k = (_u32 * self.r.nlevels)()
         _check(_lib.mdr_retriever_planes(self.handle, k))
         return list(k)
+
+
+def retrieve_qoi_vtotal(rx: Retriever, ry: Retriever, rz: Retriever, tau: float, outs3,
+                        relative: bool = False, mape_c: float = 10.0, stream=None) -> dict:
+    """mdr_retrieve_qoi_vtotal: refine vx, vy, vz until the V_total bound meets tau."""
+    info = mdr_qoi_info()
+    o = [Retriever._outs(outs) for outs in outs3]
+    _check(_lib.mdr_retrieve_qoi_vtotal(rx.handle, ry.handle, rz.handle,
+                                        MDR_REL if relative else MDR_ABS, float(tau), float(mape_c),
+                                        o[0], o[1], o[2], _stream_ptr(stream), C.byref(info)))
+    return info.as_dict()

@@ -26,11 +26,6 @@ mdr_status hip_fail(hipError_t e, const char* what)
     return fail(e == hipErrorOutOfMemory ? MDR_ERR_OUT_OF_MEMORY : MDR_ERR_HIP, m);
 }
 
-#define MDR_HIP(expr)                                            \
-    do {                                                         \
-        hipError_t _e = (expr);                                  \
-        if (_e != hipSuccess) return ::mdr::hip_fail(_e, #expr); \
-    } while (0)
 
 // ------------------------------------------------------------------ stage timing
 static hipEvent_t take_event(mdr_context* ctx)
@@ -68,9 +63,62 @@ StageTimer::~StageTimer()
     }
 }
 
-static uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
 
-static mdr_status ensure_dev(DevBuf& b, uint64_t need)
+// ------------------------------------------------------------------ device pool
+DevicePool::~DevicePool()
+{
+    for (auto& kv : free_) (void)hipFree(kv.second);
+}
+
+hipError_t DevicePool::alloc(uint64_t bytes, void** p, uint64_t* got)
+{
+    bytes = align256(bytes);
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = free_.lower_bound(bytes);
+        if (it != free_.end() && it->first <= 2 * bytes) {
+            *p = it->second;
+            *got = it->first;
+            cached_ -= it->first;
+            free_.erase(it);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        // give the cached blocks back to the device and try once more
+        (void)hipGetLastError();
+        std::multimap<uint64_t, void*> drop;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            drop.swap(free_);
+            cached_ = 0;
+        }
+        for (auto& kv : drop) (void)hipFree(kv.second);
+        e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+        *p = nullptr;
+        *got = 0;
+        return e;
+    }
+    *got = bytes;
+    return hipSuccess;
+}
+
+void DevicePool::release(void* p, uint64_t bytes)
+{
+    std::unique_lock<std::mutex> lk(mu_);
+    if (cached_ + bytes > cap_) {
+        lk.unlock();
+        (void)hipFree(p);
+        return;
+    }
+    free_.emplace(bytes, p);
+    cached_ += bytes;
+}
+
+mdr_status ensure_dev(DevBuf& b, uint64_t need)
 {
     if (b.bytes >= need) return MDR_OK;
     MDR_HIP(hipDeviceSynchronize());  // previous users of the buffer have finished
@@ -79,7 +127,7 @@ static mdr_status ensure_dev(DevBuf& b, uint64_t need)
     return MDR_OK;
 }
 
-static mdr_status ensure_stage(mdr_context* ctx, uint64_t need)
+mdr_status ensure_stage(mdr_context* ctx, uint64_t need)
 {
     if (ctx->stage_bytes >= need) return MDR_OK;
     if (ctx->stage) (void)hipHostFree(ctx->stage);
@@ -90,7 +138,7 @@ static mdr_status ensure_stage(mdr_context* ctx, uint64_t need)
     return MDR_OK;
 }
 
-static mdr_status check_params(const mdr_codec_params& p, uint32_t B)
+mdr_status check_params(const mdr_codec_params& p, uint32_t B)
 {
     if (p.group_planes < 1 || p.group_planes > B)
         return fail(MDR_ERR_INVALID_ARG, "group_planes must be in [1, nplanes]");
@@ -102,50 +150,6 @@ static mdr_status check_params(const mdr_codec_params& p, uint32_t B)
         return fail(MDR_ERR_INVALID_ARG, "force_method must be -1, MDR_DC, MDR_RLE or MDR_HUF");
     if (p.t_cr_milli == 0) return fail(MDR_ERR_INVALID_ARG, "t_cr_milli must be positive");
     return MDR_OK;
-}
-
-// value of an order-preserving key (see the statistics kernel)
-static double key_value(uint64_t key, bool f64)
-{
-    double v;
-    if (f64) {
-        uint64_t bits = (key >> 63) ? (key ^ 0x8000000000000000ull) : ~key;
-        std::memcpy(&v, &bits, 8);
-    } else {
-        uint32_t k32 = (uint32_t)key;
-        uint32_t bits = (k32 >> 31) ? (k32 ^ 0x80000000u) : ~k32;
-        float f;
-        std::memcpy(&f, &bits, 4);
-        v = f;
-    }
-    return v == 0.0 ? 0.0 : v;
-}
-
-static double bits_value(uint64_t bits, bool f64)
-{
-    if (f64) {
-        double d;
-        std::memcpy(&d, &bits, 8);
-        return d;
-    }
-    uint32_t b = (uint32_t)bits;
-    float f;
-    std::memcpy(&f, &b, 4);
-    return f;
-}
-
-// Huffman payload of an empty unit (0 symbols, no chunks) and RLE of no runs
-static std::vector<uint8_t> empty_payload(int method, uint32_t G)
-{
-    std::vector<uint8_t> p;
-    if (method == MDR_HUF) {
-        p.assign(8 + 256 + 4, 0);
-    } else if (method == MDR_RLE) {
-        p.assign(8, 0);
-        uint32_t wb = 4 * G;
-        std::memcpy(p.data() + 4, &wb, 4);
-    }
-    return p;
 }
 
 // ------------------------------------------------------------------ planner
@@ -222,275 +226,10 @@ double value_range(const mdr_refactored* r)
     return hi - lo;
 }
 
-// ------------------------------------------------------------------ refactor
-struct LevelPlan {
-    uint64_t n;
-    uint32_t nbd, ntiles, grid, tpw;
-    uint64_t rows_off, recs_off, hist_off;
-};
-
-mdr_status refactor_impl(mdr_context* ctx, const mdr_level_view* levels, uint32_t nlevels,
-                         mdr_dtype dtype, uint32_t B, const mdr_codec_params& prm, hipStream_t s,
-                         mdr_refactored** out)
-{
-    const bool f64 = dtype == MDR_F64;
-    const uint32_t G = f64 ? 2 : 1;
-    const uint32_t m = prm.group_planes;
-    const uint32_t nunits = 1 + (B + m - 1) / m;
-    MDR_HIP(hipSetDevice(ctx->device));
-
-    auto R = std::make_unique<mdr_refactored>();
-    R->ctx = ctx;
-    R->dtype = dtype;
-    R->B = B;
-    R->m = m;
-    R->G = G;
-    R->prm = prm;
-    R->levels.resize(nlevels);
-
-    // ---- sizes
-    std::vector<LevelPlan> lp(nlevels);
-    uint64_t rows_bytes = 0, recs_bytes = 0, hist_bytes = 0;
-    for (uint32_t l = 0; l < nlevels; ++l) {
-        LevelPlan& p = lp[l];
-        p.n = levels[l].n;
-        if (p.n > 0xFFFFFFFFull) return fail(MDR_ERR_UNSUPPORTED, "a level may hold at most 2^32-1 values");
-        if (p.n && !levels[l].data) return fail(MDR_ERR_INVALID_ARG, "level data is NULL");
-        p.nbd = f64 ? (uint32_t)(2 * ((p.n + 63) / 64)) : (uint32_t)((p.n + 31) / 32);
-        p.ntiles = (p.nbd + kTileBlocks - 1) / kTileBlocks;
-        p.grid = std::min<uint32_t>(std::max<uint32_t>(p.ntiles, 1), kMaxWgEncode);
-        p.tpw = std::max<uint32_t>(1, (p.ntiles + p.grid - 1) / p.grid);
-        p.grid = std::max<uint32_t>(1, (p.ntiles + p.tpw - 1) / p.tpw);
-        p.rows_off = rows_bytes;
-        rows_bytes += align256(4ull * (B + 1) * p.nbd);
-        p.recs_off = recs_bytes;
-        recs_bytes += align256(4ull * p.grid * kMaxRows * 2 * G);
-        p.hist_off = hist_bytes;
-        hist_bytes += align256(4ull * p.grid * nunits * 256);
-    }
-    {
-        hipError_t e = R->rows_arena.alloc(rows_bytes);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(planes)");
-    }
-    const uint64_t L = nlevels;
-    const uint64_t off_stats = 0;
-    const uint64_t off_ekeys = off_stats + align256(sizeof(LevelStats) * L);
-    const uint64_t off_trans = off_ekeys + align256(8ull * kMaxRows * L);
-    const uint64_t off_units = off_trans + align256(4ull * kMaxRows * L);
-    const uint64_t off_lens = off_units + align256(sizeof(UnitInfo) * kMaxRows * L);
-    const uint64_t off_codes = off_lens + align256(256ull * kMaxRows * L);
-    const uint64_t off_recs = off_codes + align256(1024ull * kMaxRows * L);
-    const uint64_t off_hist = off_recs + recs_bytes;
-    const uint64_t ws_total = off_hist + hist_bytes;
-    mdr_status st = ensure_dev(ctx->ws, ws_total);
-    if (st) return st;
-    uint8_t* ws = static_cast<uint8_t*>(ctx->ws.p);
-    LevelStats* d_stats = reinterpret_cast<LevelStats*>(ws + off_stats);
-    unsigned long long* d_ekeys = reinterpret_cast<unsigned long long*>(ws + off_ekeys);
-    uint32_t* d_trans = reinterpret_cast<uint32_t*>(ws + off_trans);
-    UnitInfo* d_units = reinterpret_cast<UnitInfo*>(ws + off_units);
-    uint8_t* d_lens = ws + off_lens;
-    uint32_t* d_codes = reinterpret_cast<uint32_t*>(ws + off_codes);
-
-    // ---- statistics, encoding, selection
-    MDR_HIP(launch_init_stats(d_stats, (int)L, s));
-    MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(d_ekeys), 2ull * kMaxRows * L, 0u, s));
-    MDR_HIP(launch_fill_u32(d_trans, (uint64_t)kMaxRows * L, 0u, s));
-    uint8_t* rows_base = static_cast<uint8_t*>(R->rows_arena.p);
-    for (uint32_t l = 0; l < nlevels; ++l) {
-        LevelRec& LR = R->levels[l];
-        LR.n = lp[l].n;
-        LR.nbd = lp[l].nbd;
-        LR.rows = reinterpret_cast<uint32_t*>(rows_base + lp[l].rows_off);
-        if (LR.n == 0) continue;
-        {
-            StageTimer tm(ctx, MDR_STAGE_STATS, s);
-            MDR_HIP(launch_stats(levels[l].data, LR.n, f64, d_stats + l, s));
-        }
-        EncodeJob job{};
-        job.x = levels[l].data;
-        job.n = LR.n;
-        job.nbd = LR.nbd;
-        job.B = B;
-        job.m = m;
-        job.nunits = nunits;
-        job.ntiles = lp[l].ntiles;
-        job.tiles_per_wg = lp[l].tpw;
-        job.grid = lp[l].grid;
-        job.rows = LR.rows;
-        job.stats = d_stats + l;
-        job.hist = reinterpret_cast<uint32_t*>(ws + off_hist + lp[l].hist_off);
-        job.trans = d_trans + (uint64_t)l * kMaxRows;
-        job.recs = reinterpret_cast<uint32_t*>(ws + off_recs + lp[l].recs_off);
-        job.ekeys = d_ekeys + (uint64_t)l * kMaxRows;
-        {
-            StageTimer tm(ctx, MDR_STAGE_ENCODE, s);
-            MDR_HIP(launch_encode(job, f64, s));
-        }
-        SelectJob sj{};
-        sj.nbd = LR.nbd;
-        sj.B = B;
-        sj.m = m;
-        sj.nunits = nunits;
-        sj.grid = lp[l].grid;
-        sj.G = G;
-        sj.t_cr_milli = prm.t_cr_milli;
-        sj.huf_chunk = prm.huf_chunk;
-        sj.huf_lmax = prm.huf_lmax;
-        sj.force_method = prm.force_method;
-        sj.t_s = prm.t_s_bytes;
-        sj.hist = job.hist;
-        sj.trans = job.trans;
-        sj.recs = job.recs;
-        sj.units = d_units + (uint64_t)l * kMaxRows;
-        sj.lens = d_lens + (uint64_t)l * kMaxRows * 256;
-        sj.codes = d_codes + (uint64_t)l * kMaxRows * 256;
-        {
-            StageTimer tm(ctx, MDR_STAGE_SELECT, s);
-            MDR_HIP(launch_select(sj, s));
-        }
-    }
-
-    // ---- small metadata to the host
-    const uint64_t h_stats = 0, h_ekeys = align256(sizeof(LevelStats) * L);
-    const uint64_t h_units = h_ekeys + align256(8ull * kMaxRows * L);
-    const uint64_t h_total = h_units + align256(sizeof(UnitInfo) * kMaxRows * L);
-    st = ensure_stage(ctx, h_total + 8ull * kMaxRows * L);
-    if (st) return st;
-    uint8_t* hs = static_cast<uint8_t*>(ctx->stage);
-    MDR_HIP(hipMemcpyAsync(hs + h_stats, d_stats, sizeof(LevelStats) * L, hipMemcpyDeviceToHost, s));
-    MDR_HIP(hipMemcpyAsync(hs + h_ekeys, d_ekeys, 8ull * kMaxRows * L, hipMemcpyDeviceToHost, s));
-    MDR_HIP(hipMemcpyAsync(hs + h_units, d_units, sizeof(UnitInfo) * kMaxRows * L,
-                           hipMemcpyDeviceToHost, s));
-    MDR_HIP(hipStreamSynchronize(s));
-    const LevelStats* hst = reinterpret_cast<const LevelStats*>(hs + h_stats);
-    const unsigned long long* hek = reinterpret_cast<const unsigned long long*>(hs + h_ekeys);
-    const UnitInfo* hun = reinterpret_cast<const UnitInfo*>(hs + h_units);
-
-    uint64_t payload_bytes = 0, temp_words = 0;
-    std::vector<uint64_t> payload_off(L * kMaxRows, 0);
-    for (uint32_t l = 0; l < nlevels; ++l) {
-        LevelRec& LR = R->levels[l];
-        LR.E.assign(B + 1, 0.0);
-        if (LR.n == 0) {
-            for (uint32_t slot = 0; slot <= B; slot = slot == 0 ? 1 : slot + m) {
-                UnitRec& u = LR.units[slot];
-                u.method = prm.force_method >= 0 ? prm.force_method : MDR_DC;
-                u.S = 0;
-                u.bytes = empty_payload(u.method, G).size();
-                u.est_huf = 8 + 256 + 4;
-                u.est_rle = 8;
-                payload_off[l * kMaxRows + slot] = payload_bytes;
-                payload_bytes += align256(u.bytes);
-            }
-            continue;
-        }
-        const LevelStats& ls = hst[l];
-        if (ls.nonfinite)
-            return fail(MDR_ERR_INVALID_ARG, "level " + std::to_string(l) + " holds NaN or Inf");
-        LR.e = ls.emax == INT_MIN ? 0 : ls.emax;
-        LR.vmin = key_value(ls.minkey, f64);
-        LR.vmax = key_value(ls.maxkey, f64);
-        LR.vmaxabs = bits_value(ls.maxabs_bits, f64);
-        const double small = bits_value(ls.small_bits, f64);
-        for (uint32_t k = 0; k <= B; ++k) {
-            double key = bits_value(hek[(uint64_t)l * kMaxRows + k], f64);
-            double ek = std::ldexp(key, LR.e - (int)k);
-            LR.E[k] = ek > small ? ek : small;
-        }
-        for (uint32_t u = 0; u < nunits; ++u) {
-            const UnitInfo& ui = hun[(uint64_t)l * kMaxRows + u];
-            uint32_t slot = u == 0 ? 0 : 1 + (u - 1) * m;
-            UnitRec& ur = LR.units[slot];
-            ur.method = (int32_t)ui.method;
-            ur.S = ui.S;
-            ur.nruns = ui.nruns;
-            ur.est_huf = ui.est_huf;
-            ur.est_rle = ui.est_rle;
-            ur.nchunks = ui.nchunks;
-            ur.maxlen = ui.maxlen;
-            if (ur.method == MDR_HUF) {
-                uint64_t words = ui.nchunks + (ui.S * (uint64_t)std::max<uint32_t>(ui.maxlen, 1) + 31) / 32;
-                uint64_t cap = 8 + 256 + 4ull * (ui.nchunks + 1) + 4 * words;
-                payload_off[l * kMaxRows + slot] = payload_bytes;
-                payload_bytes += align256(cap);
-                temp_words = std::max(temp_words, scan_temp_words((uint64_t)ui.nchunks + 1));
-            } else if (ur.method == MDR_RLE) {
-                ur.bytes = 8 + ui.nruns * (4ull * G + 4);
-                payload_off[l * kMaxRows + slot] = payload_bytes;
-                payload_bytes += align256(ur.bytes);
-                temp_words = std::max(temp_words, rle_temp_words(ui.S / 4 / G));
-            } else {
-                ur.bytes = ui.S;
-            }
-        }
-    }
-    {
-        hipError_t e = R->payload_arena.alloc(payload_bytes);
-        if (e != hipSuccess) return hip_fail(e, "hipMalloc(payloads)");
-    }
-    if (temp_words) {
-        st = ensure_dev(ctx->tmp, 4 * temp_words);
-        if (st) return st;
-    }
-    uint8_t* pay = static_cast<uint8_t*>(R->payload_arena.p);
-    uint32_t* tmp = static_cast<uint32_t*>(ctx->tmp.p);
-    std::vector<std::pair<uint32_t, uint32_t>> huf_units;  // (level, slot)
-    for (uint32_t l = 0; l < nlevels; ++l) {
-        LevelRec& LR = R->levels[l];
-        for (uint32_t slot = 0; slot <= B; slot = slot == 0 ? 1 : slot + m) {
-            UnitRec& ur = LR.units[slot];
-            uint32_t r0, r1;
-            slot_rows(slot, B, m, r0, r1);
-            if (LR.n == 0) {
-                ur.dev = pay + payload_off[l * kMaxRows + slot];
-                std::vector<uint8_t> ep = empty_payload(ur.method, G);
-                if (!ep.empty())
-                    MDR_HIP(hipMemcpy(ur.dev, ep.data(), ep.size(), hipMemcpyHostToDevice));
-                continue;
-            }
-            const uint8_t* g = reinterpret_cast<const uint8_t*>(LR.rows + (uint64_t)r0 * LR.nbd);
-            uint32_t u = slot == 0 ? 0 : 1 + (slot - 1) / m;
-            if (ur.method == MDR_DC) {
-                ur.dev = const_cast<uint8_t*>(g);
-            } else if (ur.method == MDR_HUF) {
-                ur.dev = pay + payload_off[l * kMaxRows + slot];
-                StageTimer tm(ctx, MDR_STAGE_HUF_ENCODE, s);
-                MDR_HIP(launch_huf_encode(g, ur.S, prm.huf_chunk,
-                                          d_lens + ((uint64_t)l * kMaxRows + u) * 256,
-                                          d_codes + ((uint64_t)l * kMaxRows + u) * 256, ur.dev, tmp,
-                                          s));
-                huf_units.push_back({l, slot});
-            } else {
-                ur.dev = pay + payload_off[l * kMaxRows + slot];
-                StageTimer tm(ctx, MDR_STAGE_RLE_ENCODE, s);
-                MDR_HIP(launch_rle_encode(g, ur.S / 4 / G, G, ur.nruns, ur.dev, tmp, s));
-            }
-        }
-    }
-    if (!huf_units.empty()) {
-        uint32_t* hw = reinterpret_cast<uint32_t*>(hs);
-        for (size_t i = 0; i < huf_units.size(); ++i) {
-            const UnitRec& ur = R->levels[huf_units[i].first].units[huf_units[i].second];
-            MDR_HIP(hipMemcpyAsync(hw + i, ur.dev + 8 + 256 + 4ull * ur.nchunks, 4,
-                                   hipMemcpyDeviceToHost, s));
-        }
-        MDR_HIP(hipStreamSynchronize(s));
-        for (size_t i = 0; i < huf_units.size(); ++i) {
-            UnitRec& ur = R->levels[huf_units[i].first].units[huf_units[i].second];
-            ur.bytes = 8 + 256 + 4ull * (ur.nchunks + 1) + 4ull * hw[i];
-        }
-    } else {
-        MDR_HIP(hipStreamSynchronize(s));
-    }
-    *out = R.release();
-    return MDR_OK;
-}
-
 // ------------------------------------------------------------------ retrieve
 mdr_status retrieve_impl(mdr_retriever* rt, const std::vector<uint32_t>& knew,
                          void* const* level_out, hipStream_t s, double tol_abs,
-                         mdr_retrieve_info* info)
+                         mdr_retrieve_info* info, bool all_levels = true)
 {
     const mdr_refactored* r = rt->r;
     const bool f64 = r->dtype == MDR_F64;
@@ -502,7 +241,12 @@ mdr_status retrieve_impl(mdr_retriever* rt, const std::vector<uint32_t>& knew,
 
     // decode the units entering [k_old, k_new); state is committed at the end
     std::vector<std::pair<size_t, uint32_t>> fresh;
-    std::vector<DevBuf> fresh_bufs;
+    std::vector<PoolBuf> fresh_bufs;
+    struct SyncOnFail {
+        hipStream_t s;
+        bool armed = true;
+        ~SyncOnFail() { if (armed) (void)hipStreamSynchronize(s); }
+    } sync_on_fail{s};
     uint64_t fetched = 0;
     uint32_t groups = 0;
     for (size_t l = 0; l < r->levels.size(); ++l) {
@@ -516,8 +260,8 @@ mdr_status retrieve_impl(mdr_retriever* rt, const std::vector<uint32_t>& knew,
             fetched += ur.bytes;
             ++groups;
             if (ur.method == MDR_DC || LR.n == 0) continue;
-            DevBuf buf;
-            hipError_t e = buf.alloc(std::max<uint64_t>(ur.S, 4));
+            PoolBuf buf;
+            hipError_t e = buf.alloc(rt->ctx->pool, std::max<uint64_t>(ur.S, 4));
             if (e != hipSuccess) return hip_fail(e, "hipMalloc(decoded group)");
             if (ur.method == MDR_HUF) {
                 StageTimer tm(rt->ctx, MDR_STAGE_HUF_DECODE, s);
@@ -527,7 +271,7 @@ mdr_status retrieve_impl(mdr_retriever* rt, const std::vector<uint32_t>& knew,
                 uint64_t need = 4 * (ur.nruns + 64 + scan_temp_words(ur.nruns));
                 if (rt->temp.bytes < need) {
                     MDR_HIP(hipStreamSynchronize(s));
-                    hipError_t e2 = rt->temp.alloc(need);
+                    hipError_t e2 = rt->temp.alloc(rt->ctx->pool, need);
                     if (e2 != hipSuccess) return hip_fail(e2, "hipMalloc(decode scratch)");
                 }
                 StageTimer tm(rt->ctx, MDR_STAGE_RLE_DECODE, s);
@@ -545,13 +289,14 @@ mdr_status retrieve_impl(mdr_retriever* rt, const std::vector<uint32_t>& knew,
         for (size_t i = 0; i < fresh.size(); ++i)
             if (fresh[i].first == l && fresh[i].second == slot)
                 return static_cast<const uint8_t*>(fresh_bufs[i].p);
-        const DevBuf& d = rt->dec[l][slot];
+        const PoolBuf& d = rt->dec[l][slot];
         if (d.p) return static_cast<const uint8_t*>(d.p);
         return r->levels[l].units[slot].dev;  // direct copy: the payload is the plane rows
     };
     for (size_t l = 0; l < r->levels.size(); ++l) {
         const LevelRec& LR = r->levels[l];
         if (LR.n == 0) continue;
+        if (!all_levels && knew[l] == rt->k[l]) continue;  // output already holds these planes
         ReconJob job{};
         job.out = level_out[l];
         job.n = LR.n;
@@ -573,6 +318,7 @@ mdr_status retrieve_impl(mdr_retriever* rt, const std::vector<uint32_t>& knew,
         MDR_HIP(launch_reconstruct(job, f64, s));
     }
     // commit
+    sync_on_fail.armed = false;
     for (size_t i = 0; i < fresh.size(); ++i)
         rt->dec[fresh[i].first][fresh[i].second] = std::move(fresh_bufs[i]);
     rt->k = knew;
@@ -623,6 +369,7 @@ mdr_status mdr_context_create(int hip_device, mdr_context** out)
     MDR_HIP(hipSetDevice(hip_device));
     auto* c = new mdr_context();
     c->device = hip_device;
+    c->pool = std::make_shared<DevicePool>(kPoolCacheBytes);
     *out = c;
     return MDR_OK;
 }
@@ -632,6 +379,7 @@ void mdr_context_destroy(mdr_context* ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    release_graphs(ctx);
     if (ctx->stage) (void)hipHostFree(ctx->stage);
     for (auto& mk : ctx->marks) {
         (void)hipEventDestroy(mk.start);
@@ -693,8 +441,54 @@ mdr_status mdr_refactor(mdr_context* ctx, const mdr_level_view* levels, uint32_t
     if (prm.group_planes > nplanes) prm.group_planes = nplanes;
     mdr_status st = check_params(prm, nplanes);
     if (st) return st;
-    return refactor_impl(ctx, levels, nlevels, dtype, nplanes, prm,
-                         static_cast<hipStream_t>(stream), out);
+    VarLevels v{levels, nlevels};
+    return refactor_batch(ctx, &v, 1, dtype, nplanes, prm, static_cast<hipStream_t>(stream), false, out);
+}
+
+mdr_status mdr_refactor_batch(mdr_context* ctx, const mdr_level_view* const* vars,
+                              const uint32_t* nlevels, uint32_t nvars, mdr_dtype dtype,
+                              uint32_t nplanes, const mdr_codec_params* params, void* stream,
+                              mdr_refactored** outs)
+{
+    g_err.clear();
+    if (!outs) return fail(MDR_ERR_INVALID_ARG, "outs is NULL");
+    for (uint32_t v = 0; v < nvars; ++v) outs[v] = nullptr;
+    if (!ctx) return fail(MDR_ERR_INVALID_ARG, "ctx is NULL");
+    if (nvars == 0 || !vars || !nlevels) return fail(MDR_ERR_INVALID_ARG, "no variables");
+    std::vector<VarLevels> vl(nvars);
+    for (uint32_t v = 0; v < nvars; ++v) {
+        if (nlevels[v] == 0 || !vars[v])
+            return fail(MDR_ERR_INVALID_ARG, "variable " + std::to_string(v) + " has no levels");
+        vl[v] = {vars[v], nlevels[v]};
+    }
+    if (dtype != MDR_F32 && dtype != MDR_F64) return fail(MDR_ERR_INVALID_ARG, "bad dtype");
+    const uint32_t W = dtype == MDR_F32 ? 32 : 64;
+    if (nplanes < 1 || nplanes > W)
+        return fail(MDR_ERR_UNSUPPORTED, "nplanes must be in [1, 32] for f32 and [1, 64] for f64");
+    mdr_codec_params prm;
+    mdr_codec_params_default(&prm);
+    if (params) prm = *params;
+    if (prm.group_planes > nplanes) prm.group_planes = nplanes;
+    mdr_status st = check_params(prm, nplanes);
+    if (st) return st;
+    return refactor_batch(ctx, vl.data(), nvars, dtype, nplanes, prm, static_cast<hipStream_t>(stream),
+                          ctx->graphs, outs);
+}
+
+mdr_status mdr_context_set_launch(mdr_context* ctx, uint32_t enc_target_wg, uint32_t stats_wg_values,
+                                  int graphs)
+{
+    g_err.clear();
+    if (!ctx) return fail(MDR_ERR_INVALID_ARG, "ctx is NULL");
+    if (enc_target_wg && (enc_target_wg < 64 || enc_target_wg > 65536))
+        return fail(MDR_ERR_INVALID_ARG, "enc_target_wg must be in [64, 65536]");
+    if (stats_wg_values && (stats_wg_values < 1024 || stats_wg_values > (1u << 24)))
+        return fail(MDR_ERR_INVALID_ARG, "stats_wg_values must be in [1024, 2^24]");
+    if (graphs < -1 || graphs > 1) return fail(MDR_ERR_INVALID_ARG, "graphs must be -1, 0 or 1");
+    if (enc_target_wg) ctx->enc_target_wg = enc_target_wg;
+    if (stats_wg_values) ctx->stats_wg_values = stats_wg_values;
+    if (graphs >= 0) ctx->graphs = graphs != 0;
+    return MDR_OK;
 }
 
 void mdr_refactored_destroy(mdr_refactored* r)
@@ -788,6 +582,113 @@ mdr_status mdr_retrieve(mdr_retriever* rt, mdr_bound kind, double tol, void* con
     std::vector<uint32_t> k = rt->k;
     plan_to(rt->r, tol_abs, k);
     return retrieve_impl(rt, k, level_out, static_cast<hipStream_t>(stream), tol_abs, info);
+}
+
+mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_retriever* vz,
+                                   mdr_bound kind, double tau, double mape_c,
+                                   void* const* out_x, void* const* out_y, void* const* out_z,
+                                   void* stream, mdr_qoi_info* info)
+{
+    g_err.clear();
+    mdr_retriever* rts[3] = {vx, vy, vz};
+    void* const* outs[3] = {out_x, out_y, out_z};
+    for (int c = 0; c < 3; ++c)
+        if (!rts[c] || !outs[c]) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
+    if (!(tau >= 0.0) || std::isinf(tau)) return fail(MDR_ERR_INVALID_ARG, "tolerance must be finite and >= 0");
+    if (kind != MDR_ABS && kind != MDR_REL) return fail(MDR_ERR_INVALID_ARG, "bad bound kind");
+    const mdr_refactored* r0 = vx->r;
+    for (int c = 1; c < 3; ++c) {
+        const mdr_refactored* rc = rts[c]->r;
+        if (rc->dtype != r0->dtype || rc->levels.size() != r0->levels.size())
+            return fail(MDR_ERR_INVALID_ARG, "vx, vy, vz must share dtype and level structure");
+        for (size_t l = 0; l < r0->levels.size(); ++l)
+            if (rc->levels[l].n != r0->levels[l].n)
+                return fail(MDR_ERR_INVALID_ARG, "vx, vy, vz must hold the same points per level");
+        if (rts[c]->ctx->device != vx->ctx->device) return fail(MDR_ERR_INVALID_ARG, "retrievers on different devices");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mdr_context* ctx = vx->ctx;
+    MDR_HIP(hipSetDevice(ctx->device));
+    mdr_status st = ensure_dev(ctx->qacc, 256);
+    if (st) return st;
+    st = ensure_stage(ctx, 64);
+    if (st) return st;
+    unsigned long long* acc = static_cast<unsigned long long*>(ctx->qacc.p);
+
+    // initial bounds: eps_c = (tau / Q_max) * range_c
+    double qmax = 0.0, range[3];
+    for (int c = 0; c < 3; ++c) {
+        const mdr_refactored* rc = rts[c]->r;
+        double lo = 0.0, hi = 0.0;
+        bool have = false;
+        for (const LevelRec& L : rc->levels) {
+            if (L.n == 0) continue;
+            if (!have || L.vmin < lo) lo = L.vmin;
+            if (!have || L.vmax > hi) hi = L.vmax;
+            have = true;
+        }
+        double a = std::max(std::fabs(lo), std::fabs(hi));
+        qmax = qmax + a * a;
+        range[c] = value_range(rc);
+    }
+    const double tau_abs = kind == MDR_REL ? tau * qmax : tau;
+    const double cmape = mape_c > 0.0 ? mape_c : 10.0;
+    std::vector<uint32_t> ks[3];
+    for (int c = 0; c < 3; ++c) {
+        ks[c] = rts[c]->k;
+        double e0 = qmax == 0.0 ? 0.0 : (tau_abs / qmax) * range[c];
+        plan_to(rts[c]->r, e0, ks[c]);
+    }
+    const bool f64 = r0->dtype == MDR_F64;
+    uint64_t fetched = 0;
+    uint32_t it = 0;
+    double tprime = 0.0, eps[3] = {0, 0, 0};
+    for (;;) {
+        ++it;
+        for (int c = 0; c < 3; ++c) {
+            mdr_retrieve_info ri{};
+            st = retrieve_impl(rts[c], ks[c], outs[c], s, 0.0, &ri, it == 1);
+            if (st) return st;
+            fetched += ri.bytes_fetched;
+            eps[c] = plan_bound(rts[c]->r, ks[c]);
+        }
+        MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 2, 0u, s));
+        for (size_t l = 0; l < r0->levels.size(); ++l) {
+            if (r0->levels[l].n == 0) continue;
+            MDR_HIP(launch_qoi_vtotal(out_x[l], out_y[l], out_z[l], r0->levels[l].n, f64, eps, acc, s));
+        }
+        unsigned long long* hb = static_cast<unsigned long long*>(ctx->stage);
+        MDR_HIP(hipMemcpyAsync(hb, acc, 8, hipMemcpyDeviceToHost, s));
+        MDR_HIP(hipStreamSynchronize(s));
+        double worst;
+        std::memcpy(&worst, hb, 8);
+        tprime = worst * (1.0 + std::ldexp(1.0, -40));
+        bool full = true;
+        for (int c = 0; c < 3; ++c)
+            for (uint32_t kl : ks[c]) full = full && kl == rts[c]->r->B;
+        if (tprime <= tau_abs || full) break;
+        const double p = tau_abs > 0.0 ? tprime / tau_abs : INFINITY;
+        bool moved = false;
+        if (p > cmape) {
+            for (int c = 0; c < 3; ++c) {
+                std::vector<uint32_t> knew = ks[c];
+                plan_to(rts[c]->r, eps[c] / p, knew);
+                moved = moved || knew != ks[c];
+                ks[c] = knew;
+            }
+        }
+        if (!moved)
+            for (int c = 0; c < 3; ++c) plan_step(rts[c]->r, ks[c]);
+    }
+    if (info) {
+        info->tau_abs = tau_abs;
+        info->tau_est = tprime;
+        for (int c = 0; c < 3; ++c) info->eps[c] = eps[c];
+        info->bytes_fetched = fetched;
+        info->iterations = it;
+        info->met = tprime <= tau_abs ? 1 : 0;
+    }
+    return MDR_OK;
 }
 
 mdr_status mdr_retrieve_planes(mdr_retriever* rt, const uint32_t* kreq, void* const* level_out,

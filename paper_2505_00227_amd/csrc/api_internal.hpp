@@ -2,6 +2,9 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +44,57 @@ struct DevBuf {
         if (e == hipSuccess) bytes = n;
         else p = nullptr;
         return e;
+    }
+};
+
+// Freed device blocks a context keeps for reuse, at most.
+constexpr uint64_t kPoolCacheBytes = 8ull << 30;
+
+// Caching device allocator of one context.  Blocks come back to a size-sorted
+// free list and are reused by later requests that fit them (within 2x); the
+// list keeps at most `cap` bytes.  Callers return a block only after the work
+// using it has completed (the handles' destroy calls synchronize the device).
+class DevicePool {
+public:
+    explicit DevicePool(uint64_t cap) : cap_(cap) {}
+    ~DevicePool();
+    hipError_t alloc(uint64_t bytes, void** p, uint64_t* got);
+    void release(void* p, uint64_t bytes);
+    uint64_t cached() const { return cached_; }
+private:
+    std::mutex mu_;
+    std::multimap<uint64_t, void*> free_;
+    uint64_t cached_ = 0, cap_;
+};
+
+// A block from a DevicePool (returned to it on destruction).
+struct PoolBuf {
+    std::shared_ptr<DevicePool> pool;
+    void* p = nullptr;
+    uint64_t bytes = 0;
+    PoolBuf() = default;
+    PoolBuf(const PoolBuf&) = delete;
+    PoolBuf& operator=(const PoolBuf&) = delete;
+    PoolBuf(PoolBuf&& o) noexcept : pool(std::move(o.pool)), p(o.p), bytes(o.bytes) { o.p = nullptr, o.bytes = 0; }
+    PoolBuf& operator=(PoolBuf&& o) noexcept
+    {
+        reset();
+        pool = std::move(o.pool), p = o.p, bytes = o.bytes;
+        o.p = nullptr, o.bytes = 0;
+        return *this;
+    }
+    ~PoolBuf() { reset(); }
+    void reset()
+    {
+        if (p && pool) pool->release(p, bytes);
+        p = nullptr, bytes = 0;
+    }
+    hipError_t alloc(const std::shared_ptr<DevicePool>& pl, uint64_t n)
+    {
+        reset();
+        pool = pl;
+        if (n == 0) return hipSuccess;
+        return pool->alloc(n, &p, &bytes);
     }
 };
 
@@ -92,10 +146,54 @@ private:
 mdr_status fail(mdr_status st, const std::string& msg);
 mdr_status hip_fail(hipError_t e, const char* what);
 
+#define MDR_HIP(expr)                                            \
+    do {                                                         \
+        hipError_t _e = (expr);                                  \
+        if (_e != hipSuccess) return ::mdr::hip_fail(_e, #expr); \
+    } while (0)
+
+inline uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+// grow-only buffers of a context (synchronize the device before a regrowth)
+mdr_status ensure_dev(DevBuf& b, uint64_t need);
+mdr_status ensure_stage(mdr_context* ctx, uint64_t need);
+mdr_status check_params(const mdr_codec_params& p, uint32_t B);
+
+// The levels of one variable of a batch.
+struct VarLevels {
+    const mdr_level_view* levels;
+    uint32_t nlevels;
+};
+
+// Refactor every variable in one flattened pass: one launch per stage over all
+// levels of all variables, sizes decided on the device, one host round trip at
+// the end.  With `graph`, the pass is captured once per shape and replayed.
+mdr_status refactor_batch(mdr_context* ctx, const VarLevels* vars, uint32_t nvars, mdr_dtype dtype,
+                          uint32_t B, const mdr_codec_params& prm, hipStream_t s, bool graph,
+                          mdr_refactored** outs);
+void release_graphs(mdr_context* ctx);
+
+}  // namespace mdr
+
+namespace mdr {
+// A captured batch refactor: replayed whenever a batch of the same shape comes
+// again.  Its kernels address `ws`; input and output pointers reach them
+// through the descriptor the host rewrites in `stage` before each replay.
+struct BatchGraph {
+    std::string key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    PoolBuf ws;
+    void* stage = nullptr;  // pinned: descriptor, then the metadata read back
+    uint64_t stage_bytes = 0;
+    uint64_t last_use = 0;
+    ~BatchGraph();
+};
 }  // namespace mdr
 
 struct mdr_context {
     int device = 0;
+    std::shared_ptr<mdr::DevicePool> pool;  // device memory of refactored data and retrievers
     // per-stage timing (mdr_context_set_timing)
     bool timing = false;
     struct Mark {
@@ -107,7 +205,14 @@ struct mdr_context {
     double stage_ms[MDR_STAGE_COUNT] = {};
     uint64_t stage_launches[MDR_STAGE_COUNT] = {};
     mdr::DevBuf ws;    // refactor workspace (statistics, histograms, codebooks)
-    mdr::DevBuf tmp;   // refactor scratch for the lossless encoders
+    mdr::DevBuf qacc;  // V_total estimate accumulator
+    // batch refactor: launch shape and captured graphs
+    uint32_t enc_target_wg = 2304;   // encoder workgroups a batch aims for
+    uint32_t stats_wg_values = 16384;  // values per statistics workgroup
+    bool graphs = true;
+    hipStream_t capture_stream = nullptr;
+    std::vector<std::unique_ptr<mdr::BatchGraph>> graph_cache;
+    uint64_t graph_clock = 0;
     void* stage = nullptr;  // pinned host staging
     uint64_t stage_bytes = 0;
 };
@@ -118,15 +223,16 @@ struct mdr_refactored {
     uint32_t B = 0, m = 0, G = 1;
     mdr_codec_params prm{};
     std::vector<mdr::LevelRec> levels;
-    mdr::DevBuf rows_arena;
-    mdr::DevBuf payload_arena;
+    // plane rows and lossless payloads; shared by the variables of one batch
+    std::shared_ptr<mdr::PoolBuf> rows_arena;
+    std::shared_ptr<mdr::PoolBuf> payload_arena;
 };
 
 struct mdr_retriever {
     mdr_context* ctx = nullptr;
     const mdr_refactored* r = nullptr;
     std::vector<uint32_t> k;                      // planes held per level
-    std::vector<std::vector<mdr::DevBuf>> dec;    // [level][slot] decoded non-DC units
-    mdr::DevBuf temp;                             // RLE decode scratch
+    std::vector<std::vector<mdr::PoolBuf>> dec;   // [level][slot] decoded non-DC units
+    mdr::PoolBuf temp;                            // RLE decode scratch
     uint64_t bytes_held = 0;
 };

@@ -315,16 +315,18 @@ mdr_status mdr_deserialize(mdr_context* ctx, const void* host, uint64_t bytes, m
     // ---- upload: direct-copy payloads become plane rows, others go to the payload arena
     hipError_t he = hipSetDevice(ctx->device);
     if (he != hipSuccess) return hip_fail(he, "hipSetDevice");
-    he = R->rows_arena.alloc(rows_bytes);
+    R->rows_arena = std::make_shared<PoolBuf>();
+    R->payload_arena = std::make_shared<PoolBuf>();
+    he = R->rows_arena->alloc(ctx->pool, rows_bytes);
     if (he != hipSuccess) return hip_fail(he, "hipMalloc(planes)");
-    he = R->payload_arena.alloc(pay_bytes);
+    he = R->payload_arena->alloc(ctx->pool, pay_bytes);
     if (he != hipSuccess) return hip_fail(he, "hipMalloc(payloads)");
-    uint8_t* rb = static_cast<uint8_t*>(R->rows_arena.p);
+    uint8_t* rb = static_cast<uint8_t*>(R->rows_arena->p);
     for (uint32_t l = 0; l < nlevels; ++l) {
         R->levels[l].rows = reinterpret_cast<uint32_t*>(rb);
         rb += (4ull * (B + 1) * R->levels[l].nbd + 255) & ~255ull;
     }
-    uint8_t* pb = static_cast<uint8_t*>(R->payload_arena.p);
+    uint8_t* pb = static_cast<uint8_t*>(R->payload_arena->p);
     for (const Src& sr : srcs) {
         LevelRec& L = R->levels[sr.level];
         UnitRec& u = L.units[sr.slot];

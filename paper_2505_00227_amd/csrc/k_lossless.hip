@@ -67,92 +67,431 @@ __global__ __launch_bounds__(kThreads) void k_scan_add(uint32_t* out, uint64_t n
         if (base + j < n) out[base + j] += add;
 }
 
-// ------------------------------------------------------------------ Huffman encode
-// Payload: u64 nsym | u8 len[256] | u32 off[nchunks+1] | u32 words[].
-// Chunk c (chunk symbols) starts at word off[c]; code bits are packed most
-// significant first.  One wavefront per chunk; each lane owns chunk/64
-// consecutive symbols (a multiple of 4 bytes).
+// ------------------------------------------------------------------ batch encode
+// Huffman payload: u64 nsym | u8 len[256] | u32 off[nchunks+1] | u32 words[].
+// Chunk c (huf_chunk symbols) starts at word off[c]; code bits are packed most
+// significant first.  Run-length payload: u32 nruns | u32 wbytes |
+// symbols[nruns] (W-bit) | u32 lengths[nruns].
+//
+// Every kernel below has a fixed grid and reads its amount of work from device
+// memory (counts[]), so the whole stage runs without the host learning which
+// units chose which method.
 constexpr uint64_t kHufHeader = 8 + 256;
 
-__global__ __launch_bounds__(kThreads) void k_huf_count(const uint8_t* g, uint64_t S,
-                                                        uint32_t chunk, const uint8_t* lens,
-                                                        uint8_t* payload, uint32_t nchunks)
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v, uint32_t lane)
 {
-    __shared__ uint32_t s_len[256];
-    const uint32_t tid = threadIdx.x, lane = tid & 63;
-    s_len[tid] = lens[tid];
-    if (blockIdx.x == 0) {
-        payload[8 + tid] = lens[tid];
-        if (tid == 0) *reinterpret_cast<uint64_t*>(payload) = S;
-    }
-    __syncthreads();
-    uint32_t* off = reinterpret_cast<uint32_t*>(payload + kHufHeader);
-    const uint32_t c = blockIdx.x * (kThreads / 64) + (tid >> 6);
-    if (c > nchunks) return;
-    if (c == nchunks) {
-        if (lane == 0) off[c] = 0;
-        return;
-    }
-    const uint32_t per = chunk / 64;
-    const uint64_t lo = (uint64_t)c * chunk + (uint64_t)lane * per;
-    uint32_t bits = 0;
-    for (uint32_t q = 0; q < per; q += 4) {
-        if (lo + q >= S) break;
-        uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
-        bits += s_len[w & 0xFF] + s_len[(w >> 8) & 0xFF] + s_len[(w >> 16) & 0xFF] + s_len[w >> 24];
-    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) bits += __shfl_xor(bits, o, 64);
-    if (lane == 0) off[c] = (bits + 31) / 32;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t o = __shfl_up(v, off, 64);
+        if (lane >= (uint32_t)off) v += o;
+    }
+    return v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_huf_write(const uint8_t* g, uint64_t S,
-                                                        uint32_t chunk, const uint8_t* lens,
-                                                        const uint32_t* codes, uint8_t* payload,
-                                                        uint32_t nchunks, uint32_t buf_words)
+// exclusive scan across a workgroup of NT threads (64-bit); returns the total
+template <int NT>
+__device__ uint64_t block_scan64(uint64_t v, uint64_t* s_wave, uint64_t& excl)
 {
-    extern __shared__ uint32_t s_buf[];  // [4][buf_words]
-    __shared__ uint32_t s_len[256], s_code[256];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    s_len[tid] = lens[tid];
-    s_code[tid] = codes[tid];
-    uint32_t* buf = s_buf + wave * buf_words;
-    for (uint32_t i = lane; i < buf_words; i += 64) buf[i] = 0;
+    uint64_t inc = wave_incl_scan64(v, lane);
+    if (lane == 63) s_wave[wave] = inc;
     __syncthreads();
-    const uint32_t c = blockIdx.x * (kThreads / 64) + wave;
-    if (c >= nchunks) return;
-    const uint32_t* off = reinterpret_cast<const uint32_t*>(payload + kHufHeader);
-    uint32_t* words = reinterpret_cast<uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1));
-    const uint32_t per = chunk / 64;
-    const uint64_t lo = (uint64_t)c * chunk + (uint64_t)lane * per;
-    uint32_t bits = 0;
-    for (uint32_t q = 0; q < per; q += 4) {
-        if (lo + q >= S) break;
-        uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
-        bits += s_len[w & 0xFF] + s_len[(w >> 8) & 0xFF] + s_len[(w >> 16) & 0xFF] + s_len[w >> 24];
+    uint64_t wbase = 0, total = 0;
+    for (uint32_t w = 0; w < NT / 64; ++w) {
+        wbase += w < wave ? s_wave[w] : 0;
+        total += s_wave[w];
     }
-    uint32_t pos = wave_incl_scan(bits, lane) - bits;
-    for (uint32_t q = 0; q < per; q += 4) {
-        if (lo + q >= S) break;
-        uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
+    excl = wbase + inc - v;
+    __syncthreads();
+    return total;
+}
+
+// largest u in [0, U) with base[u] <= c, for a non-decreasing base with base[0] = 0
+__device__ __forceinline__ uint32_t find_unit(const uint32_t* base, uint32_t U, uint32_t c)
+{
+    uint32_t lo = 0, hi = U;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= c)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// first plane row of unit u (its rows are contiguous in the level's row array)
+__device__ __forceinline__ const uint32_t* unit_rows(const LosslessArgs& A, uint32_t u)
+{
+    const uint32_t i = u % A.nunits;
+    const EncodeJob& job = A.jobs[u / A.nunits];
+    const uint32_t r0 = i == 0 ? 0 : 1 + (i - 1) * A.m;
+    return job.rows + (uint64_t)r0 * job.nbd;
+}
+
+__global__ __launch_bounds__(1024) void k_unit_plan(const LosslessArgs* __restrict__ Ap)
+{
+    __shared__ uint64_t s_wave[16];
+    const LosslessArgs& A = *Ap;
+    uint64_t carry_c = 0, carry_t = 0;
+    for (uint32_t b = 0; b < A.U; b += 1024) {
+        const uint32_t u = b + threadIdx.x;
+        uint64_t hc = 0, rt = 0;
+        if (u < A.U) {
+            const UnitInfo& ui = A.units[u];
+            if (ui.method == 2) hc = ui.nchunks;
+            if (ui.method == 1) rt = (ui.S / (4ull * A.G) + kRleTileWords - 1) / kRleTileWords;
+        }
+        uint64_t ec, et;
+        const uint64_t tc = block_scan64<1024>(hc, s_wave, ec);
+        const uint64_t tt = block_scan64<1024>(rt, s_wave, et);
+        if (u < A.U) {
+            A.chunk_base[u] = (uint32_t)(carry_c + ec);
+            A.tile_base[u] = (uint32_t)(carry_t + et);
+        }
+        carry_c += tc;
+        carry_t += tt;
+    }
+    if (threadIdx.x == 0) {
+        A.chunk_base[A.U] = (uint32_t)carry_c;
+        A.tile_base[A.U] = (uint32_t)carry_t;
+        A.counts[0] = (uint32_t)carry_c;
+        A.counts[1] = (uint32_t)carry_t;
+        A.counts[2] = 0;
+    }
+}
+
+// code bits of every Huffman chunk -> chunk_words[c] (words), one wavefront per
+// chunk; each lane owns huf_chunk / 64 consecutive symbols (a multiple of 4 bytes)
+__global__ __launch_bounds__(kThreads) void k_huf_count(const LosslessArgs* __restrict__ Ap)
+{
+    __shared__ uint32_t s_len[kThreads / 64][256];
+    const LosslessArgs& A = *Ap;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t total = A.counts[0];
+    if (blockIdx.x == 0 && tid == 0) A.chunk_words[total] = 0;
+    uint32_t* L = s_len[wave];
+    uint32_t cached = 0xFFFFFFFFu;
+    const uint32_t chunk = A.huf_chunk, per = chunk / 64;
+    for (uint32_t c = blockIdx.x * (kThreads / 64) + wave; c < total; c += gridDim.x * (kThreads / 64)) {
+        const uint32_t u = find_unit(A.chunk_base, A.U, c);
+        if (u != cached) {
+            for (uint32_t k = lane; k < 256; k += 64) L[k] = A.lens[(uint64_t)u * 256 + k];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            cached = u;
+        }
+        const uint8_t* g = reinterpret_cast<const uint8_t*>(unit_rows(A, u));
+        const uint64_t S = A.units[u].S;
+        const uint64_t lo = (uint64_t)(c - A.chunk_base[u]) * chunk + (uint64_t)lane * per;
+        uint32_t bits = 0;
+        for (uint32_t q = 0; q < per; q += 4) {
+            if (lo + q >= S) break;
+            uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
+            bits += L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
+        }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            uint32_t sym = (w >> (8 * b)) & 0xFF;
-            uint32_t L = s_len[sym], cd = s_code[sym];
-            uint32_t wi = pos >> 5, o = pos & 31;
-            if (o + L <= 32) {
-                atomicOr(&buf[wi], cd << (32 - o - L));
+        for (int o = 32; o > 0; o >>= 1) bits += __shfl_xor(bits, o, 64);
+        if (lane == 0) A.chunk_words[c] = (bits + 31) / 32;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// runs starting inside each run-length tile -> tile_runs[t]; one workgroup per tile
+__device__ __forceinline__ bool word_ne(const uint32_t* g, uint64_t i, uint64_t j, uint32_t G)
+{
+    bool ne = g[i * G] != g[j * G];
+    if (G == 2) ne = ne || g[i * G + 1] != g[j * G + 1];
+    return ne;
+}
+
+__global__ __launch_bounds__(kThreads) void k_rle_count(const LosslessArgs* __restrict__ Ap)
+{
+    __shared__ uint32_t s_red[kThreads / 64];
+    const LosslessArgs& A = *Ap;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t total = A.counts[1];
+    if (blockIdx.x == 0 && tid == 0) A.tile_runs[total] = 0;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t u = find_unit(A.tile_base, A.U, t);
+        const uint32_t* g = unit_rows(A, u);
+        const uint64_t nw = A.units[u].S / (4ull * A.G);
+        const uint64_t i0 = (uint64_t)(t - A.tile_base[u]) * kRleTileWords;
+        const uint64_t i1 = min(nw, i0 + kRleTileWords);
+        uint32_t cnt = 0;
+        for (uint64_t i = i0 + tid; i < i1; i += kThreads) cnt += (i == 0 || word_ne(g, i, i - 1, A.G)) ? 1u : 0u;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0) s_red[wave] = cnt;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t sum = 0;
+            for (int w = 0; w < kThreads / 64; ++w) sum += s_red[w];
+            A.tile_runs[t] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+// Exclusive scan, in place, of the first counts[which] + 1 entries of data, with
+// a fixed grid: per-workgroup range sums, one scan of the sums, then each range
+// rescanned from its base.
+constexpr int kScanDevTile = kThreads * 4;
+
+__device__ __forceinline__ void dev_range(uint32_t n, uint32_t& lo, uint32_t& hi)
+{
+    const uint32_t per = ((n + gridDim.x - 1) / gridDim.x + 3) & ~3u;
+    lo = min(n, blockIdx.x * per);
+    hi = min(n, lo + per);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_dev_part(const uint32_t* __restrict__ data,
+                                                            const uint32_t* __restrict__ count,
+                                                            uint32_t* __restrict__ part)
+{
+    __shared__ uint32_t s_red[kThreads / 64];
+    const uint32_t n = *count + 1;
+    uint32_t lo, hi;
+    dev_range(n, lo, hi);
+    uint32_t sum = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kThreads) sum += data[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+}
+
+__global__ __launch_bounds__(1024) void k_scan_dev_mid(uint32_t* part, uint32_t np)
+{
+    __shared__ uint64_t s_wave[16];
+    uint64_t carry = 0;
+    for (uint32_t b = 0; b < np; b += 1024) {
+        const uint32_t i = b + threadIdx.x;
+        const uint64_t v = i < np ? part[i] : 0;
+        uint64_t ex;
+        const uint64_t t = block_scan64<1024>(v, s_wave, ex);
+        if (i < np) part[i] = (uint32_t)(carry + ex);
+        carry += t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_dev_fin(uint32_t* __restrict__ data,
+                                                           const uint32_t* __restrict__ count,
+                                                           const uint32_t* __restrict__ part)
+{
+    __shared__ uint32_t s_wave[kThreads / 64];
+    const uint32_t n = *count + 1;
+    uint32_t lo, hi;
+    dev_range(n, lo, hi);
+    uint32_t carry = part[blockIdx.x];
+    for (uint32_t b = lo; b < hi; b += kScanDevTile) {
+        const uint32_t i0 = b + threadIdx.x * 4;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = i0 + j < hi ? data[i0 + j] : 0;
+            sum += v[j];
+        }
+        uint32_t excl;
+        const uint32_t total = block_excl_scan(sum, s_wave, excl);
+        excl += carry;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < hi) data[i0 + j] = excl;
+            excl += v[j];
+        }
+        carry += total;
+    }
+}
+
+// stream bytes of every unit and its arena offset (exclusive scan of the
+// 256-byte-aligned sizes); headers of empty streams
+__global__ __launch_bounds__(1024) void k_unit_sizes(const LosslessArgs* __restrict__ Ap)
+{
+    __shared__ uint64_t s_wave[16];
+    const LosslessArgs& A = *Ap;
+    uint64_t carry = 0;
+    for (uint32_t b = 0; b < A.U; b += 1024) {
+        const uint32_t u = b + threadIdx.x;
+        uint64_t bytes = 0, asz = 0;
+        if (u < A.U) {
+            const UnitInfo& ui = A.units[u];
+            if (ui.method == 2) {
+                const uint64_t words = A.chunk_words[A.chunk_base[u + 1]] - A.chunk_words[A.chunk_base[u]];
+                bytes = kHufHeader + 4ull * (ui.nchunks + 1) + 4 * words;
+            } else if (ui.method == 1) {
+                bytes = 8 + ui.nruns * (4ull * A.G + 4);
             } else {
-                atomicOr(&buf[wi], cd >> (o + L - 32));
-                atomicOr(&buf[wi + 1], cd << (64 - o - L));
+                bytes = ui.S;
             }
-            pos += L;
+            asz = ui.method == 0 ? 0 : (bytes + 255) & ~255ull;
+        }
+        uint64_t ex;
+        const uint64_t t = block_scan64<1024>(asz, s_wave, ex);
+        if (u < A.U) {
+            A.pay_off[u] = carry + ex;
+            A.unit_bytes[u] = bytes;
+        }
+        carry += t;
+    }
+    __syncthreads();
+    const bool over = carry > A.cap;
+    if (threadIdx.x == 0) {
+        A.counts[2] = over ? 1u : 0u;
+        A.counts[4] = (uint32_t)carry;
+        A.counts[5] = (uint32_t)(carry >> 32);
+    }
+    if (over) return;
+    for (uint32_t u = threadIdx.x; u < A.U; u += 1024) {
+        const UnitInfo& ui = A.units[u];
+        if (ui.S != 0) continue;
+        uint32_t* p = reinterpret_cast<uint32_t*>(A.arena + A.pay_off[u]);
+        if (ui.method == 2) {  // nsym 0, no code lengths, off[0] = 0
+            for (uint32_t k = 0; k < (kHufHeader + 4) / 4; ++k) p[k] = 0;
+        } else if (ui.method == 1) {
+            p[0] = 0;
+            p[1] = 4 * A.G;
         }
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    const uint32_t w0 = off[c], nw = off[c + 1] - w0;
-    for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = buf[i];
+}
+
+// Huffman payloads: one wavefront per chunk packs its codes in an LDS buffer
+// with atomic ORs, then stores the chunk's words; the first chunk's wave writes
+// the header and the last one the closing offset
+__global__ __launch_bounds__(kThreads) void k_huf_write(const LosslessArgs* __restrict__ Ap,
+                                                        uint32_t buf_words)
+{
+    extern __shared__ uint32_t s_buf[];  // [4][buf_words]
+    __shared__ uint32_t s_len[kThreads / 64][256], s_code[kThreads / 64][256];
+    const LosslessArgs& A = *Ap;
+    if (A.counts[2]) return;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t total = A.counts[0];
+    uint32_t* buf = s_buf + wave * buf_words;
+    uint32_t* L = s_len[wave];
+    uint32_t* C = s_code[wave];
+    uint32_t cached = 0xFFFFFFFFu;
+    const uint32_t chunk = A.huf_chunk, per = chunk / 64;
+    for (uint32_t c = blockIdx.x * (kThreads / 64) + wave; c < total; c += gridDim.x * (kThreads / 64)) {
+        const uint32_t u = find_unit(A.chunk_base, A.U, c);
+        if (u != cached) {
+            for (uint32_t k = lane; k < 256; k += 64) {
+                L[k] = A.lens[(uint64_t)u * 256 + k];
+                C[k] = A.codes[(uint64_t)u * 256 + k];
+            }
+            cached = u;
+        }
+        for (uint32_t i = lane; i < buf_words; i += 64) buf[i] = 0;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+        const UnitInfo& ui = A.units[u];
+        const uint64_t S = ui.S;
+        const uint32_t nch = ui.nchunks, first = A.chunk_base[u], lc = c - first;
+        uint8_t* pay = A.arena + A.pay_off[u];
+        uint32_t* off = reinterpret_cast<uint32_t*>(pay + kHufHeader);
+        uint32_t* words = off + nch + 1;
+        const uint32_t base = A.chunk_words[first];
+        const uint32_t w0 = A.chunk_words[c] - base, nw = A.chunk_words[c + 1] - A.chunk_words[c];
+        const uint8_t* g = reinterpret_cast<const uint8_t*>(unit_rows(A, u));
+        const uint64_t lo = (uint64_t)lc * chunk + (uint64_t)lane * per;
+        uint32_t bits = 0;
+        for (uint32_t q = 0; q < per; q += 4) {
+            if (lo + q >= S) break;
+            uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
+            bits += L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
+        }
+        uint32_t pos = wave_incl_scan(bits, lane) - bits;
+        for (uint32_t q = 0; q < per; q += 4) {
+            if (lo + q >= S) break;
+            uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t sym = (w >> (8 * b)) & 0xFF;
+                const uint32_t Ls = L[sym], cd = C[sym];
+                const uint32_t wi = pos >> 5, o = pos & 31;
+                if (o + Ls <= 32) {
+                    atomicOr(&buf[wi], cd << (32 - o - Ls));
+                } else {
+                    atomicOr(&buf[wi], cd >> (o + Ls - 32));
+                    atomicOr(&buf[wi + 1], cd << (64 - o - Ls));
+                }
+                pos += Ls;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = buf[i];
+        if (lane == 0) off[lc] = w0;
+        if (lc + 1 == nch && lane == 0) off[nch] = A.chunk_words[first + nch] - base;
+        if (lc == 0) {
+            if (lane == 0) *reinterpret_cast<uint64_t*>(pay) = S;
+            const uint32_t b4 = lane * 4;
+            reinterpret_cast<uint32_t*>(pay + 8)[lane] =
+                L[b4] | (L[b4 + 1] << 8) | (L[b4 + 2] << 16) | (L[b4 + 3] << 24);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
+// run-length payloads.  Pass 1 (write): every run start stores its symbol and,
+// in the lengths slot, its start position.  Pass 2 (len): every run's last
+// word turns that slot into the length.  Run r of a unit = runs starting in
+// its earlier tiles + starts before the word inside the tile.
+constexpr int kRlePer = kRleTileWords / kThreads;  // consecutive words per thread
+
+template <bool LEN>
+__global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __restrict__ Ap)
+{
+    __shared__ uint32_t s_wave[kThreads / 64];
+    const LosslessArgs& A = *Ap;
+    if (A.counts[2]) return;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t total = A.counts[1], G = A.G;
+    for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const uint32_t u = find_unit(A.tile_base, A.U, t);
+        const UnitInfo& ui = A.units[u];
+        const uint32_t* g = unit_rows(A, u);
+        const uint64_t nw = ui.S / (4ull * G), nruns = ui.nruns;
+        uint8_t* pay = A.arena + A.pay_off[u];
+        uint32_t* sym = reinterpret_cast<uint32_t*>(pay + 8);
+        uint32_t* lslot = reinterpret_cast<uint32_t*>(pay + 8 + 4ull * G * nruns);
+        const uint32_t lt = t - A.tile_base[u];
+        const uint64_t i0 = (uint64_t)lt * kRleTileWords + (uint64_t)tid * kRlePer;
+        uint32_t flags = 0, cnt = 0;
+        for (int k = 0; k < kRlePer; ++k) {
+            const uint64_t i = i0 + k;
+            const bool f = i < nw && (i == 0 || word_ne(g, i, i - 1, G));
+            flags |= f ? (1u << k) : 0u;
+            cnt += f ? 1u : 0u;
+        }
+        uint32_t excl;
+        block_excl_scan(cnt, s_wave, excl);
+        uint64_t r = (uint64_t)(A.tile_runs[t] - A.tile_runs[A.tile_base[u]]) + excl;
+        if (!LEN && lt == 0 && tid == 0) {
+            reinterpret_cast<uint32_t*>(pay)[0] = (uint32_t)nruns;
+            reinterpret_cast<uint32_t*>(pay)[1] = 4 * G;
+        }
+        for (int k = 0; k < kRlePer; ++k) {
+            const uint64_t i = i0 + k;
+            if (i >= nw) break;
+            const bool start = (flags >> k) & 1u;
+            if (!LEN) {
+                if (start && r < nruns) {
+                    sym[r * G] = g[i * G];
+                    if (G == 2) sym[r * G + 1] = g[i * G + 1];
+                    lslot[r] = (uint32_t)i;
+                }
+                r += start ? 1 : 0;
+            } else {
+                r += start ? 1 : 0;  // now one past the run holding word i
+                const bool end = i + 1 == nw || word_ne(g, i + 1, i, G);
+                if (end && r - 1 < nruns) lslot[r - 1] = (uint32_t)(i + 1) - lslot[r - 1];
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ Huffman decode
@@ -207,6 +546,11 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const uint8_t* payload,
     const uint32_t* words = reinterpret_cast<const uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1));
     uint32_t wp = off[c];
     const uint32_t wend = off[c + 1];
+    // four compressed words in flight: a refill consumes the oldest and issues
+    // the load of the word four refills ahead (the loads' latency overlaps decoding)
+    auto fetch = [&](uint32_t i) -> uint32_t { return i < wend ? words[i] : 0u; };
+    uint32_t q0 = fetch(wp), q1 = fetch(wp + 1), q2 = fetch(wp + 2), q3 = fetch(wp + 3);
+    wp += 4;
     uint64_t buf = 0;
     int nb = 0;
     const uint64_t lo = (uint64_t)c * chunk;
@@ -217,10 +561,13 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const uint8_t* payload,
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             if (nb <= 32) {
-                uint32_t w = wp < wend ? words[wp] : 0u;
-                ++wp;
-                buf |= (uint64_t)w << (32 - nb);
+                buf |= (uint64_t)q0 << (32 - nb);
                 nb += 32;
+                q0 = q1;
+                q1 = q2;
+                q2 = q3;
+                q3 = fetch(wp);
+                ++wp;
             }
             uint32_t ent = s_lut[buf >> (64 - lmax)];
             uint32_t l = ent >> 8;
@@ -232,53 +579,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const uint8_t* payload,
     }
 }
 
-// ------------------------------------------------------------------ RLE
-// Payload: u32 nruns | u32 wbytes | symbols[nruns] (W-bit) | u32 lengths[nruns].
-__device__ __forceinline__ bool word_ne(const uint32_t* g, uint64_t i, uint64_t j, uint32_t G)
-{
-    bool ne = false;
-    for (uint32_t q = 0; q < G; ++q) ne = ne || g[i * G + q] != g[j * G + q];
-    return ne;
-}
-
-__global__ void k_rle_flags(const uint32_t* g, uint64_t nwords, uint32_t G, uint32_t* flags)
-{
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride)
-        flags[i] = (i == 0 || word_ne(g, i, i - 1, G)) ? 1u : 0u;
-}
-
-__global__ void k_rle_scatter(const uint32_t* g, uint64_t nwords, uint32_t G, const uint32_t* idx,
-                              uint8_t* payload, uint32_t* starts, uint64_t nruns)
-{
-    uint32_t* sym = reinterpret_cast<uint32_t*>(payload + 8);
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) {
-        if (i == 0 || word_ne(g, i, i - 1, G)) {
-            uint64_t r = idx[i];
-            if (r < nruns) {
-                for (uint32_t q = 0; q < G; ++q) sym[r * G + q] = g[i * G + q];
-                starts[r] = (uint32_t)i;
-            }
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        reinterpret_cast<uint32_t*>(payload)[0] = (uint32_t)nruns;
-        reinterpret_cast<uint32_t*>(payload)[1] = 4 * G;
-    }
-}
-
-__global__ void k_rle_lengths(const uint32_t* starts, uint64_t nruns, uint64_t nwords, uint32_t G,
-                              uint8_t* payload)
-{
-    uint32_t* lens = reinterpret_cast<uint32_t*>(payload + 8 + 4ull * G * nruns);
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nruns; r += stride) {
-        uint64_t end = r + 1 < nruns ? starts[r + 1] : nwords;
-        lens[r] = (uint32_t)(end - starts[r]);
-    }
-}
-
+// ------------------------------------------------------------------ RLE decode
 __global__ void k_rle_expand(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
                              const uint32_t* starts, uint32_t* g)
 {
@@ -333,24 +634,27 @@ hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_huf_encode(const uint8_t* g, uint64_t S, uint32_t chunk, const uint8_t* lens,
-                             const uint32_t* codes, uint8_t* payload, uint32_t* temp,
-                             hipStream_t s)
+hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_dev, uint32_t* scan_part,
+                                 hipStream_t s)
 {
-    const uint32_t nchunks = (uint32_t)((S + chunk - 1) / chunk);
-    const unsigned wgs = blocks_for((uint64_t)nchunks + 1, kThreads / 64, 1u << 30);
-    hipLaunchKernelGGL(k_huf_count, dim3(wgs), dim3(kThreads), 0, s, g, S, chunk, lens, payload,
-                       nchunks);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    uint32_t* off = reinterpret_cast<uint32_t*>(payload + kHufHeader);
-    err = launch_scan_exclusive(off, off, (uint64_t)nchunks + 1, temp, s);
-    if (err != hipSuccess || nchunks == 0) return err;
-    const uint32_t buf_words = (chunk * kLutBitsMax + 31) / 32 + 2;
+    if (a.U == 0) return hipSuccess;
+    const dim3 P(kPersistWg), T(kThreads);
+    hipLaunchKernelGGL(k_unit_plan, dim3(1), dim3(1024), 0, s, a_dev);
+    hipLaunchKernelGGL(k_huf_count, P, T, 0, s, a_dev);
+    hipLaunchKernelGGL(k_scan_dev_part, P, T, 0, s, a.chunk_words, a.counts + 0, scan_part);
+    hipLaunchKernelGGL(k_scan_dev_mid, dim3(1), dim3(1024), 0, s, scan_part, kPersistWg);
+    hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, a.chunk_words, a.counts + 0, scan_part);
+    hipLaunchKernelGGL(k_rle_count, P, T, 0, s, a_dev);
+    uint32_t* part2 = scan_part + kPersistWg + 32;
+    hipLaunchKernelGGL(k_scan_dev_part, P, T, 0, s, a.tile_runs, a.counts + 1, part2);
+    hipLaunchKernelGGL(k_scan_dev_mid, dim3(1), dim3(1024), 0, s, part2, kPersistWg);
+    hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, a.tile_runs, a.counts + 1, part2);
+    hipLaunchKernelGGL(k_unit_sizes, dim3(1), dim3(1024), 0, s, a_dev);
+    const uint32_t buf_words = (a.huf_chunk * kLutBitsMax + 31) / 32 + 2;
     const size_t shmem = 4ull * buf_words * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_huf_write, dim3(blocks_for(nchunks, kThreads / 64, 1u << 30)),
-                       dim3(kThreads), shmem, s, g, S, chunk, lens, codes, payload, nchunks,
-                       buf_words);
+    hipLaunchKernelGGL(k_huf_write, P, T, shmem, s, a_dev, buf_words);
+    hipLaunchKernelGGL((k_rle_pass<false>), P, T, 0, s, a_dev);
+    hipLaunchKernelGGL((k_rle_pass<true>), P, T, 0, s, a_dev);
     return hipGetLastError();
 }
 
@@ -361,32 +665,6 @@ hipError_t launch_huf_decode(const uint8_t* payload, uint64_t S, uint32_t chunk,
     if (nchunks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_huf_decode, dim3(blocks_for(nchunks, kThreads, 1u << 30)), dim3(kThreads),
                        0, s, payload, S, chunk, lmax, g, nchunks);
-    return hipGetLastError();
-}
-
-uint64_t rle_temp_words(uint64_t nwords)
-{
-    return 2 * nwords + scan_temp_words(nwords) + 64;
-}
-
-hipError_t launch_rle_encode(const uint8_t* g, uint64_t nwords, uint32_t G, uint64_t nruns,
-                             uint8_t* payload, uint32_t* temp, hipStream_t s)
-{
-    const uint32_t* gw = reinterpret_cast<const uint32_t*>(g);
-    uint32_t* flags = temp;
-    uint32_t* starts = temp + nwords;
-    uint32_t* scratch = temp + 2 * nwords + 64;
-    unsigned b = blocks_for(nwords, kThreads, 8192);
-    if (nwords) {
-        hipLaunchKernelGGL(k_rle_flags, dim3(b), dim3(kThreads), 0, s, gw, nwords, G, flags);
-        hipError_t err = launch_scan_exclusive(flags, flags, nwords, scratch, s);
-        if (err != hipSuccess) return err;
-    }
-    hipLaunchKernelGGL(k_rle_scatter, dim3(b), dim3(kThreads), 0, s, gw, nwords, G, flags, payload,
-                       starts, nruns);
-    if (nruns)
-        hipLaunchKernelGGL(k_rle_lengths, dim3(blocks_for(nruns, kThreads, 8192)), dim3(kThreads),
-                           0, s, starts, nruns, nwords, G, payload);
     return hipGetLastError();
 }
 

@@ -74,24 +74,22 @@ __global__ void k_init_stats(LevelStats* st, int count)
     st[i].minkey = ~0ull;
     st[i].maxkey = 0;
     st[i].maxabs_bits = 0;
-    st[i].small_bits = 0;
 }
 
 // ------------------------------------------------------------------ level statistics
 // One streaming pass: largest frexp exponent of the nonzero values (Alg. 1's
-// alignment exponent), min / max / max|x|, and a non-finite flag.
+// alignment exponent), min / max / max|x|, and a non-finite flag.  Each thread
+// folds 16-byte vectors, the workgroup reduces in LDS, and one lane per
+// workgroup publishes with device atomics (few workgroups -> little contention).
 template <bool F64>
-__global__ __launch_bounds__(kThreads) void k_stats(const void* xv, uint64_t n, LevelStats* st)
-{
+struct StatAcc {
     using U = std::conditional_t<F64, uint64_t, uint32_t>;
-    const U* x = static_cast<const U*>(xv);
     int emax = INT_MIN;
     uint32_t bad = 0;
     uint64_t kmin = ~0ull, kmax = 0;
     U amax = 0;
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        U b = x[i];
+    __device__ __forceinline__ void add(U b)
+    {
         U ab;
         int ex;
         uint64_t key;
@@ -109,20 +107,75 @@ __global__ __launch_bounds__(kThreads) void k_stats(const void* xv, uint64_t n, 
         }
         if (!finite) {
             bad = 1;
-            continue;
+            return;
         }
         emax = ex > emax ? ex : emax;
         kmin = key < kmin ? key : kmin;
         kmax = key > kmax ? key : kmax;
         amax = ab > amax ? ab : amax;
     }
-    emax = wave_max(emax);
-    kmin = wave_min(kmin);
-    kmax = wave_max(kmax);
-    amax = wave_max(amax);
-    bad = __any(bad) ? 1u : 0u;
-    if ((threadIdx.x & 63) == 0) {
-        if (emax != INT_MIN) atomicMax(&st->emax, emax);
+};
+
+// One launch covers every level of a batch: workgroup -> job through wg_job,
+// then a grid-stride loop over that level with the job's own workgroup count.
+template <bool F64, bool VEC>
+__global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__ jobs,
+                                                    const uint32_t* __restrict__ wg_job)
+{
+    using U = typename StatAcc<F64>::U;
+    constexpr int PER = 16 / sizeof(U);  // values per 16-byte vector
+    const StatsJob& job = jobs[wg_job[blockIdx.x]];
+    const U* x = static_cast<const U*>(job.x);
+    const uint64_t n = job.n;
+    LevelStats* st = job.stats;
+    StatAcc<F64> acc;
+    const uint64_t stride = (uint64_t)job.grid * blockDim.x;
+    const uint64_t tid0 = (uint64_t)(blockIdx.x - job.wg_base) * blockDim.x + threadIdx.x;
+    uint64_t done = 0;
+    if (VEC) {
+        const uint64_t nvec = n / PER;
+        const uint4* xv4 = reinterpret_cast<const uint4*>(x);
+        for (uint64_t i = tid0; i < nvec; i += stride) {
+            uint4 q = xv4[i];
+            if constexpr (F64) {
+                acc.add(((uint64_t)q.y << 32) | q.x);
+                acc.add(((uint64_t)q.w << 32) | q.z);
+            } else {
+                acc.add(q.x);
+                acc.add(q.y);
+                acc.add(q.z);
+                acc.add(q.w);
+            }
+        }
+        done = nvec * PER;
+    }
+    for (uint64_t i = done + tid0; i < n; i += stride) acc.add(x[i]);
+
+    __shared__ int s_e[kThreads / 64];
+    __shared__ uint32_t s_bad[kThreads / 64];
+    __shared__ unsigned long long s_kmin[kThreads / 64], s_kmax[kThreads / 64], s_amax[kThreads / 64];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int e = wave_max(acc.emax);
+    uint64_t kmin = wave_min(acc.kmin), kmax = wave_max(acc.kmax);
+    uint64_t amax = wave_max((uint64_t)acc.amax);
+    uint32_t bad = __any(acc.bad) ? 1u : 0u;
+    if (lane == 0) {
+        s_e[wave] = e;
+        s_bad[wave] = bad;
+        s_kmin[wave] = kmin;
+        s_kmax[wave] = kmax;
+        s_amax[wave] = amax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / 64; ++w) {
+            e = s_e[w] > e ? s_e[w] : e;
+            bad |= s_bad[w];
+            kmin = s_kmin[w] < kmin ? s_kmin[w] : kmin;
+            kmax = s_kmax[w] > kmax ? s_kmax[w] : kmax;
+            amax = s_amax[w] > amax ? s_amax[w] : amax;
+        }
+        if (e != INT_MIN) atomicMax(&st->emax, e);
         if (bad) atomicOr(&st->nonfinite, 1u);
         atomicMin((unsigned long long*)&st->minkey, (unsigned long long)kmin);
         atomicMax((unsigned long long*)&st->maxkey, (unsigned long long)kmax);
@@ -135,42 +188,59 @@ __global__ __launch_bounds__(kThreads) void k_stats(const void* xv, uint64_t n, 
 // plane); a workgroup covers a tile of 256 blocks and walks a contiguous range
 // of tiles.  Per block:
 //   y = |x| * 2^(B-e) (exact), mag = floor(y), sign bit;
-//   error keys: for every k, fract(y * 2^(k-B)) = (|x| mod 2^(e-k)) / 2^(e-k),
-//     a running maximum per k (values with mag = 0 lie below every cut: their
-//     error is |x| for every k and is tracked separately as `small`);
-//   32x32 in-register bit transpose (two of them for f64) -> plane words;
+//   error keys: key_k = fract(y * 2^(k-B)) = (|x| mod 2^(e-k)) / 2^(e-k); the
+//     workgroup keeps max_k key_k in LDS.  Values with mag = 0 lie below every
+//     cut: their error is |x| for every k (tracked as `small`);
+//   32x32 in-register bit transpose (two for f64) -> plane words;
 //   coalesced stores of each plane row, per-unit byte histograms (LDS), and
 //   counts of W-bit word transitions for the run-length estimate.
+//
+// Exact pruning of the f32 error keys.  Let K_k be the workgroup's running
+// maximum.  When K_k >= 1 - 2^-12 ("strong" cut), a value can exceed it only if
+// the 12 bits just below the cut, in y's binary expansion, are all ones.  With
+// Y = y * 2^32 (exact: y >= 1 has no bits below 2^-23), bit p of
+// r = AND_{i<12} (Y << i) says "bits p..p-11 of Y are ones", so the high word of
+// r flags every candidate cut c = B-k (bit c-1) at once.  Only flagged cuts are
+// evaluated and folded in with an LDS max; the others cannot change the result.
+// Cuts whose maximum is still below 1 - 2^-12 ("weak") take the direct per-block
+// maximum.  Stale thresholds only add candidates, so the result is exact.
 template <bool F64, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_encode(EncodeJob job)
+__device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t wg)
 {
     using T = std::conditional_t<F64, double, float>;
     constexpr int G = F64 ? 2 : 1;  // u32 words per W-bit word
-    constexpr int NK = F64 ? 65 : 33;
-    extern __shared__ uint32_t s_hist[];  // [nunits][256]
-    __shared__ uint32_t s_last[2][4][kMaxRows][G];
+    constexpr int NROW = F64 ? 65 : 33;
+    // dynamic LDS: [nunits][256] byte histograms, then the tile's plane words
+    // [rows][256] (f32: also this thread's y values, stride 33, in the same space)
+    extern __shared__ uint32_t s_dyn[];
+    __shared__ uint32_t s_prev[kMaxRows][G];  // last word(s) of the previous tile, per row
     __shared__ uint32_t s_trans[kMaxRows];
-    __shared__ unsigned long long s_ek[4][F64 ? kMaxRows : 1];
+    __shared__ uint32_t s_key32[F64 ? 1 : kKeyStride];
+    __shared__ unsigned long long s_key64[F64 ? kKeyStride : 1];
+    __shared__ uint32_t s_zero[kThreads];  // sink for zero bytes (one slot per thread)
 
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t B = job.B, nbd = job.nbd, m = job.m;
+    const uint32_t B = job.B, nbd = job.nbd, m = job.m, nunits = job.nunits;
     const uint64_t n = job.n;
     const int e = job.stats->emax == INT_MIN ? 0 : job.stats->emax;
     const T* x = static_cast<const T*>(job.x);
+    uint32_t* s_hist = s_dyn;
+    uint32_t* s_pl = s_dyn + nunits * 256;           // [B+1][256]
+    float* s_y = reinterpret_cast<float*>(s_pl);     // [256][36] (reuses the plane space)
 
-    for (uint32_t i = tid; i < job.nunits * 256; i += kThreads) s_hist[i] = 0;
+    for (uint32_t i = tid; i < nunits * 256; i += kThreads) s_hist[i] = 0;
     if (tid < kMaxRows) s_trans[tid] = 0;
-    if constexpr (F64) {
-        for (uint32_t i = tid; i < 4 * kMaxRows; i += kThreads) (&s_ek[0][0])[i] = 0;
+    if (tid < kKeyStride) {
+        if constexpr (F64)
+            s_key64[tid] = 0;
+        else
+            s_key32[tid] = 0;
     }
-    __syncthreads();
 
-    float kmax[F64 ? 1 : 33];
-#pragma unroll
-    for (int k = 0; k < (F64 ? 1 : 33); ++k) kmax[k] = 0.0f;
+    float frac_max = 0.0f;  // f32: max fract(y) = the k = B key
     T small = 0;
 
-    const uint32_t t0 = blockIdx.x * job.tiles_per_wg;
+    const uint32_t t0 = wg * job.tiles_per_wg;
     const uint32_t t1 = min(job.ntiles, t0 + job.tiles_per_wg);
     const uint32_t last_blk = min(nbd, t1 * kTileBlocks) - 1;
 
@@ -178,6 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncodeJob job)
         const uint32_t blk = t * kTileBlocks + tid;
         const bool valid = blk < nbd;
         const uint64_t base = (uint64_t)blk * 32;
+        __syncthreads();  // the previous tile's rows have been consumed
 
         // ---- load 32 consecutive values
         T v[32];
@@ -240,6 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncodeJob job)
 
         // ---- exact error keys, k = 0..B
         if constexpr (F64) {
+            // direct per-block maximum, folded per wave into LDS
             for (int k = 0; k <= (int)B; ++k) {
                 double km = 0.0;
 #pragma unroll
@@ -248,131 +320,183 @@ __global__ __launch_bounds__(kThreads) void k_encode(EncodeJob job)
                     km = key > km ? key : km;
                 }
                 km = wave_max(km);
-                if (lane == 0) {
-                    unsigned long long kb = (unsigned long long)__double_as_longlong(km);
-                    if (kb > s_ek[wave][k]) s_ek[wave][k] = kb;
-                }
+                if (lane == 0) atomicMax(&s_key64[k], (unsigned long long)__double_as_longlong(km));
             }
         } else {
+            float* ys = s_y + tid * 36;
 #pragma unroll
-            for (int k = 0; k < 33; ++k) {
-                if (k <= (int)B) {
-                    float km = kmax[k];
+            for (int q = 0; q < 8; ++q)
+                *reinterpret_cast<float4*>(ys + 4 * q) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            // cut c = B - k for k = 0..B-1 is bit c-1; k = B is the fraction itself
+            uint32_t strong = 0;
 #pragma unroll
-                    for (int j = 0; j < 32; j += 2) {
-                        float k0 = __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(v[j], k - (int)B));
-                        float k1 = __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(v[j + 1], k - (int)B));
-                        km = fmaxf(km, fmaxf(k0, k1));
-                    }
-                    kmax[k] = km;
+            for (int c = 1; c <= 32; ++c) {
+                const uint32_t kk = c <= (int)B ? B - c : 0u;
+                strong |= (c <= (int)B && s_key32[kk] >= 0x3F7FF000u) ? (1u << (c - 1)) : 0u;  // K >= 1 - 2^-12
+            }
+            strong = __builtin_amdgcn_readfirstlane(strong);
+            auto one = [&](float y) {
+                const float f = __builtin_amdgcn_fractf(y);
+                frac_max = fmaxf(frac_max, f);
+                const uint64_t Y = ((uint64_t)(uint32_t)y << 32) | (uint32_t)(f * 0x1p32f);
+                uint64_t r = Y & (Y << 1);
+                r &= r << 2;
+                r &= r << 4;
+                r &= r << 4;
+                uint32_t cand = (uint32_t)(r >> 32) & strong;
+                while (cand) {
+                    const int c = __ffs(cand);  // 1-based bit index == cut
+                    cand &= cand - 1;
+                    const float key = __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y, -c));
+                    atomicMax(&s_key32[B - c], __float_as_uint(key));
                 }
+            };
+            const float4* ys4 = reinterpret_cast<const float4*>(ys);
+            float4 nxt = ys4[0];
+            for (int q = 0; q < 8; ++q) {
+                const float4 cur = nxt;
+                if (q < 7) nxt = ys4[q + 1];
+                one(cur.x);
+                one(cur.y);
+                one(cur.z);
+                one(cur.w);
+            }
+            const uint32_t all = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+            uint32_t weak = all & ~strong;
+            while (weak) {
+                const int c = __ffs(weak);
+                weak &= weak - 1;
+                float km = 0.0f;
+#pragma unroll 2
+                for (int q = 0; q < 8; ++q) {
+                    const float4 y4 = ys4[q];
+                    km = fmaxf(km, fmaxf(fmaxf(__builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.x, -c)),
+                                               __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.y, -c))),
+                                         fmaxf(__builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.z, -c)),
+                                               __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.w, -c)))));
+                }
+                km = wave_max(km);
+                if (lane == 0) atomicMax(&s_key32[B - c], __float_as_uint(km));
             }
         }
 
-        // ---- bit transpose: lo[c] (and hi[c]) become the plane words of bit c (32 + c)
+        // ---- bit transpose: lo[c] (and hi[c]) become the plane words of bit c (32 + c);
+        // stage them row-major in LDS: row 0 = sign, row r >= 1 = plane r-1 = bit B-r
         transpose32(lo);
         if constexpr (F64) transpose32(hi);
-
-        // ---- store rows, histogram bytes, remember the last words of this wave
-        // row 0 = sign; row r >= 1 = plane r-1 = bit B-r.
-        const bool rec_last = valid && blk + G > last_blk;  // lanes holding the range's last word
-        const bool rec_first = valid && t == t0 && wave == 0 && lane < G;
-        auto emit = [&](uint32_t r, uint32_t w) {
-            if (valid) {
-                job.rows[(uint64_t)r * nbd + blk] = w;
-                uint32_t u = r == 0 ? 0 : 1 + (r - 1) / m;
-                uint32_t* h = s_hist + u * 256;
+        __syncthreads();  // every thread is done with its y values
+        s_pl[tid] = sgn;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    uint32_t byte = (w >> (8 * q)) & 0xFFu;
-                    if (byte) atomicAdd(&h[byte], 1u);
+        for (int c = 0; c < 32; ++c)
+            if (c < (int)B) s_pl[(B - c) * kTileBlocks + tid] = lo[c];
+        if constexpr (F64) {
+#pragma unroll
+            for (int c = 0; c < 32; ++c)
+                if (32 + c < (int)B) s_pl[(B - 32 - c) * kTileBlocks + tid] = hi[c];
+        }
+        __syncthreads();
+
+        // ---- per row: coalesced store, byte histogram, word transitions.
+        // Rows go four at a time so their LDS reads overlap; zero bytes are
+        // counted by difference later and go to this thread's sink slot here.
+        const bool have_prev = t > t0;
+        const bool lead = valid && (tid % G) == 0 && (tid >= G || have_prev);
+        for (uint32_t r0 = 0; r0 <= B; r0 += 4) {
+            uint32_t w[4], pv[4], pv1[4], nx[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t r = min(r0 + i, B);
+                const uint32_t* row = s_pl + r * kTileBlocks;
+                w[i] = row[tid];
+                pv[i] = tid >= G ? row[tid - G] : s_prev[r][tid];
+                if constexpr (G == 2) {
+                    nx[i] = row[tid + 1 < kTileBlocks ? tid + 1 : tid];
+                    pv1[i] = tid >= G ? row[tid - 1] : s_prev[r][1];
                 }
             }
-            if (lane >= 64 - G) s_last[t & 1][wave][r][lane - (64 - G)] = w;
-            uint32_t* rec = job.recs + ((uint64_t)blockIdx.x * kMaxRows + r) * 2 * G;
-            if (rec_first) rec[lane] = w;
-            if (rec_last) rec[G + (blk - (last_blk + 1 - G))] = w;
-        };
-        emit(0, sgn);
 #pragma unroll
-        for (int c = 31; c >= 0; --c)
-            if (c < (int)B) emit(B - c, lo[c]);
-        if constexpr (F64) {
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t r = r0 + i;
+                if (r > B) break;
+                if (valid) {
+                    job.rows[(uint64_t)r * nbd + blk] = w[i];
+                    uint32_t* h = s_hist + job.hist_off[r];
 #pragma unroll
-            for (int c = 31; c >= 0; --c)
-                if (32 + c < (int)B) emit(B - 32 - c, hi[c]);
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t byte = (w[i] >> (8 * q)) & 0xFFu;
+                        atomicAdd(byte ? &h[byte] : &s_zero[tid], 1u);
+                    }
+                }
+                bool flag = w[i] != pv[i];
+                if constexpr (G == 2) flag = flag || nx[i] != pv1[i];
+                unsigned long long bal = __ballot(lead && flag);
+                if (lane == 0 && bal) atomicAdd(&s_trans[r], (uint32_t)__popcll(bal));
+            }
         }
+        // first / last words of this workgroup's range, for the boundaries
+        if (t == t0 && tid < G)
+            for (uint32_t r = 0; r <= B; ++r)
+                job.recs[((uint64_t)wg * kMaxRows + r) * 2 * G + tid] = s_pl[r * kTileBlocks + tid];
+        if (valid && blk + G > last_blk)
+            for (uint32_t r = 0; r <= B; ++r)
+                job.recs[((uint64_t)wg * kMaxRows + r) * 2 * G + G + (blk - (last_blk + 1 - G))] =
+                    s_pl[r * kTileBlocks + tid];
         __syncthreads();
-
-        // ---- run-length statistics: transitions between consecutive W-bit words
-        const bool have_prev = !(t == t0 && wave == 0);
-        auto count = [&](uint32_t r, uint32_t w) {
-            uint32_t prev = __shfl_up(w, G, 64);
-            if (lane < G) {
-                if (wave > 0)
-                    prev = s_last[t & 1][wave - 1][r][lane];
-                else if (have_prev)
-                    prev = s_last[(t - 1) & 1][3][r][lane];
-            }
-            bool ne = w != prev;
-            bool flag;
-            if constexpr (G == 2) {
-                bool ne1 = __shfl_down(ne ? 1 : 0, 1, 64) != 0;
-                flag = ((lane & 1) == 0) && (ne || ne1);
-            } else {
-                flag = ne;
-            }
-            flag = flag && valid && (lane >= G || have_prev);
-            unsigned long long bal = __ballot(flag);
-            if (lane == 0 && bal) atomicAdd(&s_trans[r], (uint32_t)__popcll(bal));
-        };
-        count(0, sgn);
-#pragma unroll
-        for (int c = 31; c >= 0; --c)
-            if (c < (int)B) count(B - c, lo[c]);
-        if constexpr (F64) {
-#pragma unroll
-            for (int c = 31; c >= 0; --c)
-                if (32 + c < (int)B) count(B - 32 - c, hi[c]);
-        }
+        if (tid >= kTileBlocks - G)
+            for (uint32_t r = 0; r <= B; ++r) s_prev[r][tid - (kTileBlocks - G)] = s_pl[r * kTileBlocks + tid];
+        (void)NROW;
     }
 
-    // ---- flush
+    // ---- flush: per-workgroup partials (reduced by the selection kernel)
     small = wave_max(small);
-    if (lane == 0 && small > 0) {
-        unsigned long long sb = F64 ? (unsigned long long)__double_as_longlong((double)small)
-                                    : (unsigned long long)__float_as_uint((float)small);
-        atomicMax((unsigned long long*)&job.stats->small_bits, sb);
-    }
     if constexpr (F64) {
-        __syncthreads();
-        if (tid <= B) {
-            unsigned long long mx = 0;
-            for (int w = 0; w < 4; ++w) mx = s_ek[w][tid] > mx ? s_ek[w][tid] : mx;
-            if (mx) atomicMax(&job.ekeys[tid], mx);
-        }
+        if (lane == 0) atomicMax(&s_key64[kKeyStride - 1], (unsigned long long)__double_as_longlong(small));
     } else {
-#pragma unroll
-        for (int k = 0; k < 33; ++k) {
-            if (k <= (int)B) {
-                float km = wave_max(kmax[k]);
-                if (lane == 0 && km > 0.0f)
-                    atomicMax(&job.ekeys[k], (unsigned long long)__float_as_uint(km));
-            }
+        frac_max = wave_max(frac_max);
+        if (lane == 0) {
+            atomicMax(&s_key32[B], __float_as_uint(frac_max));
+            atomicMax(&s_key32[kKeyStride - 1], __float_as_uint(small));
         }
-        (void)NK;
     }
     __syncthreads();
-    uint32_t* gh = job.hist + (uint64_t)blockIdx.x * job.nunits * 256;
-    for (uint32_t i = tid; i < job.nunits * 256; i += kThreads) gh[i] = s_hist[i];
-    if (tid <= B && s_trans[tid]) atomicAdd(&job.trans[tid], s_trans[tid]);
+    unsigned long long* kp = job.key_part + (uint64_t)wg * kKeyStride;
+    if (tid < kKeyStride) {
+        if constexpr (F64)
+            kp[tid] = s_key64[tid];
+        else
+            kp[tid] = s_key32[tid];
+    }
+    uint32_t* gh = job.hist + (uint64_t)wg * nunits * 256;
+    for (uint32_t i = tid; i < nunits * 256; i += kThreads) gh[i] = s_hist[i];
+    if (tid < kMaxRows) job.trans_part[(uint64_t)wg * kMaxRows + tid] = s_trans[tid];
+}
+
+// f32 fits three waves per SIMD without spilling; f64 keeps the default budget
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_encode_f32(
+    const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
+{
+    const EncodeJob& job = jobs[wg_job[blockIdx.x]];
+    encode_body<false, VEC>(job, blockIdx.x - job.wg_base);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void k_encode_f64(const EncodeJob* __restrict__ jobs,
+                                                         const uint32_t* __restrict__ wg_job)
+{
+    const EncodeJob& job = jobs[wg_job[blockIdx.x]];
+    encode_body<true, VEC>(job, blockIdx.x - job.wg_base);
 }
 
 // ------------------------------------------------------------------ hybrid selection
-// One workgroup per unit (Alg. 2): gather the byte histogram and the run count,
-// build length-limited Huffman code lengths with the two-queue construction,
-// canonical codes, both size estimates, and the method decision.
-__global__ __launch_bounds__(kThreads) void k_select(SelectJob job)
+// One workgroup of 1024 threads per (unit, level) (Alg. 2): gather the byte
+// histogram and the run count, build length-limited Huffman code lengths with
+// the two-queue construction, canonical codes, both size estimates, and the
+// method decision.  Units that Alg. 2 can only copy (S <= T_s) skip the codebook.
+constexpr int kSelThreads = 1024;
+
+__global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
+                                                         const SelectLevel* __restrict__ levels)
 {
     __shared__ unsigned long long s_f[256];     // working counts (halved when limiting)
     __shared__ unsigned long long s_f0[256];    // original counts
@@ -380,76 +504,185 @@ __global__ __launch_bounds__(kThreads) void k_select(SelectJob job)
     __shared__ int s_parent[512];
     __shared__ int s_sorted[256];
     __shared__ uint8_t s_len[256];
-    __shared__ unsigned long long s_red[kThreads / 64];
+    __shared__ uint32_t s_part[16][256];
+    __shared__ unsigned long long s_red[kSelThreads / 64];
     __shared__ int s_nl, s_maxlen;
     __shared__ uint32_t s_count[33], s_first[33];
 
+    const SelectLevel& lv = levels[blockIdx.y];
     const uint32_t u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t B = job.B, m = job.m, G = job.G, grid = job.grid;
+    const uint32_t B = job.B, m = job.m, G = job.G, grid = lv.grid, nunits = job.nunits;
     const uint32_t r0 = u == 0 ? 0 : 1 + (u - 1) * m;
     const uint32_t r1 = u == 0 ? 1 : min(B + 1, r0 + m);
-    const uint64_t S = (uint64_t)(r1 - r0) * job.nbd * 4;
+    const uint64_t S = (uint64_t)(r1 - r0) * lv.nbd * 4;
+    if (lv.nbd == 0) {
+        // empty level: no planes; every unit is an empty stream of the forced
+        // method (direct copy under Alg. 2)
+        if (tid < 256) {
+            lv.lens[u * 256 + tid] = 0;
+            lv.codes[u * 256 + tid] = 0;
+        }
+        if (u == 0 && tid < kKeyStride) lv.keys[tid] = 0;
+        if (tid == 0) {
+            UnitInfo ui;
+            ui.S = 0;
+            ui.est_huf = 8 + 256 + 4;
+            ui.est_rle = 8;
+            ui.nruns = 0;
+            ui.method = job.force_method >= 0 ? (uint32_t)job.force_method : 0u;
+            ui.nchunks = 0;
+            ui.maxlen = 0;
+            ui.pad = 0;
+            lv.units[u] = ui;
+        }
+        return;
+    }
 
     auto block_sum = [&](unsigned long long v) -> unsigned long long {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
         if (lane == 0) s_red[wave] = v;
         __syncthreads();
-        unsigned long long t = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+        unsigned long long t = 0;
+        for (int w = 0; w < kSelThreads / 64; ++w) t += s_red[w];
         __syncthreads();
         return t;
     };
 
-    // ---- byte histogram (zeros are implied: S minus the nonzero bytes)
+    // ---- byte histogram: 16 slices of the per-workgroup partials; each thread
+    // sums four adjacent bins with 16-byte loads, two loads in flight
+    {
+        const uint32_t q4 = tid & 63, slice = tid >> 6;
+        const uint4* h = reinterpret_cast<const uint4*>(lv.hist + (uint64_t)u * 256) + q4;
+        const uint64_t rowstride = (uint64_t)nunits * 256 / 4;
+        uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+        uint32_t w = slice;
+        for (; w + 16 < grid; w += 32) {
+            uint4 p0 = h[(uint64_t)w * rowstride], p1 = h[(uint64_t)(w + 16) * rowstride];
+            a.x += p0.x, a.y += p0.y, a.z += p0.z, a.w += p0.w;
+            b.x += p1.x, b.y += p1.y, b.z += p1.z, b.w += p1.w;
+        }
+        for (; w < grid; w += 16) {
+            uint4 p0 = h[(uint64_t)w * rowstride];
+            a.x += p0.x, a.y += p0.y, a.z += p0.z, a.w += p0.w;
+        }
+        s_part[slice][4 * q4 + 0] = a.x + b.x;
+        s_part[slice][4 * q4 + 1] = a.y + b.y;
+        s_part[slice][4 * q4 + 2] = a.z + b.z;
+        s_part[slice][4 * q4 + 3] = a.w + b.w;
+    }
+    __syncthreads();
     unsigned long long f = 0;
-    for (uint32_t w = 0; w < grid; ++w) f += job.hist[((uint64_t)w * job.nunits + u) * 256 + tid];
-    unsigned long long nz = block_sum(tid ? f : 0);
-    if (tid == 0) f = S - nz;
-    s_f[tid] = f;
-    s_f0[tid] = f;
+    if (tid < 256)
+        for (int q = 0; q < 16; ++q) f += s_part[q][tid];
+    unsigned long long nz = block_sum((tid > 0 && tid < 256) ? f : 0);
+    if (tid == 0) f = S - nz;  // zero bytes are not counted by the encoder
+    if (tid < 256) {
+        s_f[tid] = f;
+        s_f0[tid] = f;
+    }
 
     // ---- runs of equal W-bit words: transitions inside workgroup ranges, at
     // range boundaries, and between consecutive planes of the group
-    unsigned long long tr = 0;
-    for (uint32_t r = r0 + tid; r < r1; r += kThreads) tr += job.trans[r];
     const uint32_t nrow = r1 - r0;
-    for (uint32_t i = tid; i < (grid - 1) * nrow; i += kThreads) {
+    unsigned long long tr = 0;
+    for (uint32_t i = tid; i < grid * nrow; i += kSelThreads)
+        tr += lv.trans_part[(uint64_t)(i / nrow) * kMaxRows + r0 + i % nrow];
+    if (u == 0 && tid < kKeyStride && (tid <= B || tid == kKeyStride - 1)) {
+        unsigned long long kmax = 0;
+        for (uint32_t w = 0; w < grid; ++w) {
+            unsigned long long kv = lv.key_part[(uint64_t)w * kKeyStride + tid];
+            kmax = kv > kmax ? kv : kmax;
+        }
+        lv.keys[tid] = kmax;
+    }
+    for (uint32_t i = tid; i < (grid - 1) * nrow; i += kSelThreads) {
         uint32_t w = 1 + i / nrow, r = r0 + i % nrow;
-        const uint32_t* cur = job.recs + ((uint64_t)w * kMaxRows + r) * 2 * G;
-        const uint32_t* prv = job.recs + ((uint64_t)(w - 1) * kMaxRows + r) * 2 * G;
+        const uint32_t* cur = lv.recs + ((uint64_t)w * kMaxRows + r) * 2 * G;
+        const uint32_t* prv = lv.recs + ((uint64_t)(w - 1) * kMaxRows + r) * 2 * G;
         bool ne = false;
         for (uint32_t g = 0; g < G; ++g) ne = ne || cur[g] != prv[G + g];
         tr += ne ? 1 : 0;
     }
-    for (uint32_t r = r0 + 1 + tid; r < r1; r += kThreads) {
-        const uint32_t* cur = job.recs + ((uint64_t)0 * kMaxRows + r) * 2 * G;
-        const uint32_t* prv = job.recs + ((uint64_t)(grid - 1) * kMaxRows + (r - 1)) * 2 * G;
+    for (uint32_t r = r0 + 1 + tid; r < r1; r += kSelThreads) {
+        const uint32_t* cur = lv.recs + ((uint64_t)0 * kMaxRows + r) * 2 * G;
+        const uint32_t* prv = lv.recs + ((uint64_t)(grid - 1) * kMaxRows + (r - 1)) * 2 * G;
         bool ne = false;
         for (uint32_t g = 0; g < G; ++g) ne = ne || cur[g] != prv[G + g];
         tr += ne ? 1 : 0;
     }
-    unsigned long long trans = block_sum(tr);
+    const unsigned long long trans = block_sum(tr);
     const unsigned long long nruns = S ? 1 + trans : 0;
+
+    const bool need_code = job.force_method == 2 || (job.force_method < 0 && S > job.t_s);
+    if (tid < 256) s_len[tid] = 0;
+    if (tid == 0) s_maxlen = 0;
     __syncthreads();
 
-    // ---- length-limited Huffman code lengths
-    for (;;) {
-        // rank of symbol tid among the nonzero counts, ordered by (count, symbol)
-        unsigned long long ft = s_f[tid];
+    // ---- Huffman code lengths: two-queue tree, depths by pointer jumping, and
+    // the per-length count adjustment when the tree is deeper than huf_lmax
+    if (need_code) {
+        const unsigned long long ft = tid < 256 ? s_f[tid] : 0;
         int rank = 0;
-        for (int s = 0; s < 256; ++s) {
-            unsigned long long fs = s_f[s];
-            rank += (fs && (fs < ft || (fs == ft && s < (int)tid))) ? 1 : 0;
+        if (tid < 256 && ft) {
+            for (int q = 0; q < 256; ++q) {
+                unsigned long long fs = s_f[q];
+                rank += (fs && (fs < ft || (fs == ft && q < (int)tid))) ? 1 : 0;
+            }
         }
         if (tid == 0) s_nl = 0;
         __syncthreads();
-        if (ft) {
+        if (tid < 256 && ft) {
             s_sorted[rank] = (int)tid;
             atomicAdd(&s_nl, 1);
         }
-        s_len[tid] = 0;
         __syncthreads();
         const int nl = s_nl;
+        if (tid < nl) s_w[tid] = s_f[s_sorted[tid]];
+        __syncthreads();
+        if (tid == 0 && nl > 1) {
+            int q1 = 0, q2 = nl, next = nl;
+            while ((nl - q1) + (next - q2) > 1) {
+                int a, b;
+                if (q1 < nl && (q2 == next || s_w[q1] <= s_w[q2]))
+                    a = q1++;
+                else
+                    a = q2++;
+                if (q1 < nl && (q2 == next || s_w[q1] <= s_w[q2]))
+                    b = q1++;
+                else
+                    b = q2++;
+                s_w[next] = s_w[a] + s_w[b];
+                s_parent[a] = next;
+                s_parent[b] = next;
+                ++next;
+            }
+            s_parent[next - 1] = next - 1;  // the root points to itself
+        }
+        __syncthreads();
+        // depth of every node: d <- d + d[parent], parent <- parent[parent] (9 rounds for 511 nodes)
+        const int nnodes = nl > 1 ? 2 * nl - 1 : 0;
+        int* s_d = reinterpret_cast<int*>(s_part);       // reuse: >= 512 ints
+        int* s_p = reinterpret_cast<int*>(s_part) + 512;
+        if (tid < nnodes) {
+            s_p[tid] = s_parent[tid];
+            s_d[tid] = (tid == (uint32_t)(nnodes - 1)) ? 0 : 1;
+        }
+        __syncthreads();
+        for (int round = 0; round < 9; ++round) {
+            int nd = 0, np = 0;
+            if (tid < nnodes) {
+                int p = s_p[tid];
+                nd = s_d[tid] + s_d[p];
+                np = s_p[p];
+            }
+            __syncthreads();
+            if (tid < nnodes) {
+                s_d[tid] = nd;
+                s_p[tid] = np;
+            }
+            __syncthreads();
+        }
         if (tid == 0) {
             int maxlen = 0;
             if (nl == 1) {
@@ -457,45 +690,52 @@ __global__ __launch_bounds__(kThreads) void k_select(SelectJob job)
                 s_len[s0] = 1;
                 s_len[s0 == 0 ? 1 : 0] = 1;
                 maxlen = 1;
-            } else if (nl > 1) {
-                for (int i = 0; i < nl; ++i) s_w[i] = s_f[s_sorted[i]];
-                int q1 = 0, q2 = nl, next = nl;
-                while ((nl - q1) + (next - q2) > 1) {
-                    int pk[2];
-                    for (int t = 0; t < 2; ++t) {
-                        if (q1 < nl && (q2 == next || s_w[q1] <= s_w[q2]))
-                            pk[t] = q1++;
-                        else
-                            pk[t] = q2++;
-                    }
-                    s_w[next] = s_w[pk[0]] + s_w[pk[1]];
-                    s_parent[pk[0]] = next;
-                    s_parent[pk[1]] = next;
-                    ++next;
-                }
-                // depths, reusing s_w as storage (root has the largest index)
-                int root = next - 1;
-                s_w[root] = 0;
-                for (int i = root - 1; i >= 0; --i) s_w[i] = s_w[s_parent[i]] + 1;
-                for (int i = 0; i < nl; ++i) {
-                    int d = (int)s_w[i];
-                    s_len[s_sorted[i]] = (uint8_t)d;
-                    maxlen = d > maxlen ? d : maxlen;
-                }
             }
+            for (int i = 0; i < nl && nl > 1; ++i) maxlen = s_d[i] > maxlen ? s_d[i] : maxlen;
             s_maxlen = maxlen;
         }
         __syncthreads();
-        if (s_maxlen <= (int)job.huf_lmax) break;
-        unsigned long long h = s_f[tid];
-        if (h) s_f[tid] = (h >> 1) ? (h >> 1) : 1;
+        if (nl > 1 && s_maxlen <= (int)job.huf_lmax) {
+            if (tid < nl) s_len[s_sorted[tid]] = (uint8_t)s_d[tid];
+        } else if (nl > 1) {
+            // ITU-T T.81 Annex K count adjustment on one lane, then hand the
+            // lengths out again: heaviest leaf (last in sorted order) shortest
+            uint32_t* s_bits = reinterpret_cast<uint32_t*>(s_parent);  // 256+1 entries
+            if (tid <= 256) s_bits[tid] = 0;
+            __syncthreads();
+            if (tid < nl) atomicAdd(&s_bits[s_d[tid]], 1u);
+            __syncthreads();
+            if (tid == 0) {
+                for (int i = s_maxlen; i > (int)job.huf_lmax; --i) {
+                    while (s_bits[i] > 0) {
+                        int j = i - 2;
+                        while (s_bits[j] == 0) --j;
+                        s_bits[i] -= 2;
+                        s_bits[i - 1] += 1;
+                        s_bits[j + 1] += 2;
+                        s_bits[j] -= 1;
+                    }
+                }
+                s_maxlen = (int)job.huf_lmax;
+            }
+            __syncthreads();
+            if (tid < nl) {
+                const uint32_t pos = (uint32_t)(nl - 1) - tid;  // 0 = heaviest
+                uint32_t cum = 0, Lh = 1;
+                for (; Lh <= job.huf_lmax; ++Lh) {
+                    cum += s_bits[Lh];
+                    if (pos < cum) break;
+                }
+                s_len[s_sorted[tid]] = (uint8_t)Lh;
+            }
+        }
         __syncthreads();
     }
 
     // ---- canonical codes: (length, symbol) order
     if (tid < 33) s_count[tid] = 0;
     __syncthreads();
-    const uint32_t L = s_len[tid];
+    const uint32_t L = tid < 256 ? s_len[tid] : 0;
     if (L) atomicAdd(&s_count[L], 1u);
     __syncthreads();
     if (tid == 0) {
@@ -506,20 +746,22 @@ __global__ __launch_bounds__(kThreads) void k_select(SelectJob job)
         }
     }
     __syncthreads();
-    uint32_t code = 0;
-    if (L) {
-        uint32_t before = 0;
-        for (uint32_t s = 0; s < tid; ++s) before += s_len[s] == L ? 1u : 0u;
-        code = s_first[L] + before;
+    if (tid < 256) {
+        uint32_t code = 0;
+        if (L) {
+            uint32_t before = 0;
+            for (uint32_t q = 0; q < tid; ++q) before += s_len[q] == L ? 1u : 0u;
+            code = s_first[L] + before;
+        }
+        lv.lens[u * 256 + tid] = (uint8_t)L;
+        lv.codes[u * 256 + tid] = code;
     }
-    job.lens[u * 256 + tid] = (uint8_t)L;
-    job.codes[u * 256 + tid] = code;
 
     // ---- estimates and the decision
-    unsigned long long bits = block_sum(s_f0[tid] * (unsigned long long)L);
+    unsigned long long bits = block_sum(tid < 256 ? s_f0[tid] * (unsigned long long)L : 0);
     if (tid == 0) {
         const uint64_t nchunks = (S + job.huf_chunk - 1) / job.huf_chunk;
-        const uint64_t est_huf = (bits + 7) / 8 + 8 + 256 + 4 * (nchunks + 1);
+        const uint64_t est_huf = need_code ? (bits + 7) / 8 + 8 + 256 + 4 * (nchunks + 1) : 0;
         const uint64_t est_rle = 8 + nruns * (4ull * G + 4);
         uint32_t method;
         if (job.force_method >= 0) {
@@ -543,7 +785,7 @@ __global__ __launch_bounds__(kThreads) void k_select(SelectJob job)
         ui.nchunks = (uint32_t)nchunks;
         ui.maxlen = (uint32_t)s_maxlen;
         ui.pad = 0;
-        job.units[u] = ui;
+        lv.units[u] = ui;
     }
 }
 
@@ -573,40 +815,69 @@ hipError_t launch_init_stats(LevelStats* st, int count, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_stats(const void* x, uint64_t n, bool f64, LevelStats* st, hipStream_t s)
+hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
+                              bool vec, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    unsigned g = grid_for(n, kThreads * 16, 2048);
-    if (f64)
-        hipLaunchKernelGGL(k_stats<true>, dim3(g), dim3(kThreads), 0, s, x, n, st);
-    else
-        hipLaunchKernelGGL(k_stats<false>, dim3(g), dim3(kThreads), 0, s, x, n, st);
-    return hipGetLastError();
-}
-
-hipError_t launch_encode(const EncodeJob& job, bool f64, hipStream_t s)
-{
-    if (job.nbd == 0) return hipSuccess;
-    size_t shmem = (size_t)job.nunits * 256 * sizeof(uint32_t);
-    bool vec = ((uintptr_t)job.x % 16) == 0;
-    dim3 g(job.grid), b(kThreads);
+    if (grid == 0) return hipSuccess;
     if (f64) {
         if (vec)
-            hipLaunchKernelGGL((k_encode<true, true>), g, b, shmem, s, job);
+            hipLaunchKernelGGL((k_stats<true, true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
         else
-            hipLaunchKernelGGL((k_encode<true, false>), g, b, shmem, s, job);
+            hipLaunchKernelGGL((k_stats<true, false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     } else {
         if (vec)
-            hipLaunchKernelGGL((k_encode<false, true>), g, b, shmem, s, job);
+            hipLaunchKernelGGL((k_stats<false, true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
         else
-            hipLaunchKernelGGL((k_encode<false, false>), g, b, shmem, s, job);
+            hipLaunchKernelGGL((k_stats<false, false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_select(const SelectJob& job, hipStream_t s)
+size_t encode_lds_bytes(uint32_t nunits, uint32_t B, bool f64)
 {
-    hipLaunchKernelGGL(k_select, dim3(job.nunits), dim3(kThreads), 0, s, job);
+    size_t planes = (size_t)(B + 1) * kTileBlocks * sizeof(uint32_t);
+    size_t ys = f64 ? 0 : (size_t)kTileBlocks * 36 * sizeof(float);
+    return (size_t)nunits * 256 * sizeof(uint32_t) + (planes > ys ? planes : ys);
+}
+
+hipError_t encode_set_lds(uint32_t nunits, uint32_t B, bool f64)
+{
+    const size_t shmem = encode_lds_bytes(nunits, B, f64);
+    if (shmem <= 64 * 1024) return hipSuccess;
+    const void* fns[2] = {f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true>,
+                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false>};
+    for (const void* fn : fns) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_encode_batch(const EncodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
+                               uint32_t nunits, uint32_t B, bool f64, bool vec, hipStream_t s)
+{
+    if (grid == 0) return hipSuccess;
+    const size_t shmem = encode_lds_bytes(nunits, B, f64);
+    dim3 g(grid), b(kThreads);
+    if (f64) {
+        if (vec)
+            hipLaunchKernelGGL((k_encode_f64<true>), g, b, shmem, s, jobs, wg_job);
+        else
+            hipLaunchKernelGGL((k_encode_f64<false>), g, b, shmem, s, jobs, wg_job);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_encode_f32<true>), g, b, shmem, s, jobs, wg_job);
+        else
+            hipLaunchKernelGGL((k_encode_f32<false>), g, b, shmem, s, jobs, wg_job);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_select_batch(const SelectParams& p, const SelectLevel* lv, uint32_t nlev,
+                               hipStream_t s)
+{
+    if (nlev == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3(p.nunits, nlev), dim3(kSelThreads), 0, s, p, lv);
     return hipGetLastError();
 }
 

@@ -74,7 +74,63 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(ReconJob j)
     }
 }
 
+// V_total error estimate (Sec. 5.2): with |v - vhat| <= eps_c per component,
+// |v^2 - vhat^2| <= eps_c (2|vhat| + eps_c); the estimate is the maximum over
+// points of the sum over x, y, z, evaluated in double in that order (no
+// contraction: the library is built with -ffp-contract=off).
+template <bool F64>
+__global__ __launch_bounds__(kThreads) void k_qoi_vtotal(const void* px, const void* py,
+                                                         const void* pz, uint64_t n, double ex,
+                                                         double ey, double ez,
+                                                         unsigned long long* out)
+{
+    using T = std::conditional_t<F64, double, float>;
+    const T* x = static_cast<const T*>(px);
+    const T* y = static_cast<const T*>(py);
+    const T* z = static_cast<const T*>(pz);
+    double worst = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double ax = fabs((double)x[i]), ay = fabs((double)y[i]), az = fabs((double)z[i]);
+        double tx = ex * ((2.0 * ax) + ex);
+        double ty = ey * ((2.0 * ay) + ey);
+        double tz = ez * ((2.0 * az) + ez);
+        double s = 0.0;
+        s = s + tx;
+        s = s + ty;
+        s = s + tz;
+        worst = s > worst ? s : worst;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double o = __shfl_xor(worst, off, 64);
+        worst = o > worst ? o : worst;
+    }
+    __shared__ double s_w[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = worst;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / 64; ++w) worst = s_w[w] > worst ? s_w[w] : worst;
+        atomicMax(out, (unsigned long long)__double_as_longlong(worst));
+    }
+}
+
 }  // namespace
+
+hipError_t launch_qoi_vtotal(const void* x, const void* y, const void* z, uint64_t n, bool f64,
+                             const double eps[3], unsigned long long* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    uint64_t g = (n + kThreads * 8 - 1) / (kThreads * 8);
+    if (g > 1024) g = 1024;
+    if (f64)
+        hipLaunchKernelGGL((k_qoi_vtotal<true>), dim3((unsigned)g), dim3(kThreads), 0, s, x, y, z, n,
+                           eps[0], eps[1], eps[2], out);
+    else
+        hipLaunchKernelGGL((k_qoi_vtotal<false>), dim3((unsigned)g), dim3(kThreads), 0, s, x, y, z, n,
+                           eps[0], eps[1], eps[2], out);
+    return hipGetLastError();
+}
 
 hipError_t launch_reconstruct(const ReconJob& job, bool f64, hipStream_t s)
 {

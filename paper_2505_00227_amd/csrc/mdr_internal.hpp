@@ -11,8 +11,9 @@ namespace mdr {
 constexpr int kThreads = 256;     // threads per workgroup: 4 wavefronts of 64
 constexpr int kTileBlocks = 256;  // 32-value blocks per tile: one per thread
 constexpr int kMaxRows = 65;      // sign row + up to 64 magnitude planes
-constexpr int kMaxWgEncode = 1024;
+constexpr int kMaxWgEncode = 768;  // three encoder workgroups per CU run at once
 constexpr int kLutBitsMax = 12;   // Huffman decode table: 2^lmax entries
+constexpr int kKeyStride = 66;    // error keys k = 0..64, then [65] = max |x| below 2^(e-B)
 
 // Per-level statistics gathered on the device (zeroed by k_fill before use).
 struct LevelStats {
@@ -21,8 +22,7 @@ struct LevelStats {
     uint64_t minkey;       // order-preserving integer key of the minimum
     uint64_t maxkey;       // order-preserving integer key of the maximum
     uint64_t maxabs_bits;  // bit pattern of max |x|
-    uint64_t small_bits;   // bit pattern of max |x| over values below 2^(e-B)
-    uint64_t pad[3];
+    uint64_t pad[4];
 };
 
 // Selection result of one lossless unit (sign plane, or a group of m planes).
@@ -37,6 +37,17 @@ struct UnitInfo {
     uint32_t pad;
 };
 
+// Work of one level in a flattened batch launch.  The tables below live in
+// device memory; a workgroup finds its job through a per-launch map
+// (workgroup -> job index) and its rank within the job as blockIdx - wg_base.
+struct StatsJob {
+    const void* x;
+    uint64_t n;
+    LevelStats* stats;
+    uint32_t wg_base;       // first workgroup of this job in its launch
+    uint32_t grid;          // workgroups of this job
+};
+
 struct EncodeJob {
     const void* x;          // level values (f32 or f64)
     uint64_t n;
@@ -46,54 +57,93 @@ struct EncodeJob {
     uint32_t nunits;        // 1 + ceil(B / m)
     uint32_t ntiles;        // ceil(nbd / kTileBlocks)
     uint32_t tiles_per_wg;
-    uint32_t grid;          // workgroups of the encode launch
-    uint32_t pad;
+    uint32_t grid;          // workgroups of this job
+    uint32_t wg_base;       // first workgroup of this job in its launch
     uint32_t* rows;         // [(B+1)][nbd]: row 0 sign, row 1+p plane p (bit B-1-p)
     LevelStats* stats;
     uint32_t* hist;         // [grid][nunits][256] nonzero-byte counts
-    uint32_t* trans;        // [B+1] word transitions inside each workgroup's range
-    uint32_t* recs;         // [grid][B+1][2G] first / last words of each workgroup's range
-    unsigned long long* ekeys;  // [B+1] max error keys (float / double bit patterns)
+    uint32_t* trans_part;   // [grid][kMaxRows] word transitions inside each workgroup's range
+    uint32_t* recs;         // [grid][kMaxRows][2G] first / last words of each workgroup's range
+    unsigned long long* key_part;  // [grid][kKeyStride] max error keys (float/double bits), small
+    uint16_t hist_off[kMaxRows];   // row r -> its unit's histogram offset (unit * 256)
 };
 
-struct SelectJob {
-    uint64_t nbd;
-    uint32_t B, m, nunits, grid, G;  // G: u32 words per W-bit word (1 f32, 2 f64)
-    uint32_t t_cr_milli, huf_chunk, huf_lmax;
-    int32_t force_method;
-    uint64_t t_s;
-    const uint32_t* hist;
-    const uint32_t* trans;
-    const uint32_t* recs;
+// Per-level inputs / outputs of the selection kernel.
+struct SelectLevel {
+    uint64_t nbd;           // 0 for an empty level
+    uint32_t grid;          // workgroups of that level's encode job
+    uint32_t pad;
+    const uint32_t* hist;   // [grid][nunits][256]
+    const uint32_t* trans_part;            // [grid][kMaxRows]
+    const uint32_t* recs;   // [grid][kMaxRows][2G]
+    const unsigned long long* key_part;    // [grid][kKeyStride]
+    unsigned long long* keys;              // [kKeyStride] reduced over workgroups
     UnitInfo* units;        // [nunits]
     uint8_t* lens;          // [nunits][256]
     uint32_t* codes;        // [nunits][256]
 };
 
+struct SelectParams {
+    uint32_t B, m, nunits, G;  // G: u32 words per W-bit word (1 f32, 2 f64)
+    uint32_t t_cr_milli, huf_chunk, huf_lmax;
+    int32_t force_method;
+    uint64_t t_s;
+};
+
+// Lossless stage of a batch.  Units are numbered level-major over the batch
+// (unit u = job * nunits + i); unit i of a level holds rows [r0, r1) with
+// r0 = i == 0 ? 0 : 1 + (i - 1) m.  Sizes are decided on the device, so the
+// stage needs no host round trip; payloads go to one arena of capacity `cap`.
+constexpr uint32_t kRleTileWords = 4096;  // W-bit words per run-length tile
+constexpr uint32_t kPersistWg = 1024;     // workgroups of the persistent lossless kernels
+
+struct LosslessArgs {
+    const EncodeJob* jobs;  // rows and nbd of each level
+    const UnitInfo* units;  // [U] selection results
+    const uint8_t* lens;    // [U][256]
+    const uint32_t* codes;  // [U][256]
+    uint32_t* chunk_base;   // [U+1] first Huffman chunk of each unit (0 if not HUF)
+    uint32_t* tile_base;    // [U+1] first run-length tile of each unit
+    uint32_t* chunk_words;  // [chunks+1] words per chunk, scanned in place to offsets
+    uint32_t* tile_runs;    // [tiles+1] runs starting in each tile, scanned in place
+    uint64_t* pay_off;      // [U] payload offset in the arena (DC: unused)
+    uint64_t* unit_bytes;   // [U] stream bytes
+    uint32_t* counts;       // [0] chunks, [1] tiles, [2] arena overflow, [3] pad, [4..5] arena bytes
+    uint8_t* arena;
+    uint64_t cap;
+    uint32_t U, nunits, B, m, G, huf_chunk;
+};
+
 // ---- launchers (k_refactor.hip) ----
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
 hipError_t launch_init_stats(LevelStats* st, int count, hipStream_t s);
-hipError_t launch_stats(const void* x, uint64_t n, bool f64, LevelStats* st, hipStream_t s);
-hipError_t launch_encode(const EncodeJob& job, bool f64, hipStream_t s);
-hipError_t launch_select(const SelectJob& job, hipStream_t s);
+// statistics of every job; wg_job maps each of `grid` workgroups to its job
+hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
+                              bool vec, hipStream_t s);
+size_t encode_lds_bytes(uint32_t nunits, uint32_t B, bool f64);
+// raise the encoder kernels' dynamic LDS limit (call outside graph capture)
+hipError_t encode_set_lds(uint32_t nunits, uint32_t B, bool f64);
+hipError_t launch_encode_batch(const EncodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
+                               uint32_t nunits, uint32_t B, bool f64, bool vec, hipStream_t s);
+hipError_t launch_select_batch(const SelectParams& p, const SelectLevel* lv, uint32_t nlev,
+                               hipStream_t s);
 
 // ---- launchers (k_lossless.hip) ----
 // exclusive scan of n u32 values (out may alias in); temp: scan_temp_words(n) u32
 uint64_t scan_temp_words(uint64_t n);
 hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* temp,
                                  hipStream_t s);
-// Huffman: payload layout u64 nsym | u8 len[256] | u32 off[nchunks+1] | u32 words[]
-hipError_t launch_huf_encode(const uint8_t* g, uint64_t S, uint32_t chunk, const uint8_t* lens,
-                             const uint32_t* codes, uint8_t* payload, uint32_t* temp,
-                             hipStream_t s);
+// Huffman and run-length encoding of every unit the selection chose, sizes
+// and arena offsets decided on the device (grid sizes fixed: graph-capturable).
+// scan_part: 2 * kPersistWg + 64 u32 of scratch.
+hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_dev, uint32_t* scan_part,
+                                 hipStream_t s);
+// Huffman decode: payload u64 nsym | u8 len[256] | u32 off[nchunks+1] | u32 words[]
 hipError_t launch_huf_decode(const uint8_t* payload, uint64_t S, uint32_t chunk, uint32_t lmax,
                              uint8_t* g, hipStream_t s);
-// RLE: payload u32 nruns | u32 wbytes | symbols[nruns] | u32 lengths[nruns]
-hipError_t launch_rle_encode(const uint8_t* g, uint64_t nwords, uint32_t G, uint64_t nruns,
-                             uint8_t* payload, uint32_t* temp, hipStream_t s);
+// RLE decode: payload u32 nruns | u32 wbytes | symbols[nruns] | u32 lengths[nruns]
 hipError_t launch_rle_decode(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
                              uint8_t* g, uint32_t* temp, hipStream_t s);
-uint64_t rle_temp_words(uint64_t nwords);
 
 // ---- launchers (k_retrieve.hip) ----
 struct ReconJob {
@@ -104,5 +154,8 @@ struct ReconJob {
     int32_t e;
 };
 hipError_t launch_reconstruct(const ReconJob& job, bool f64, hipStream_t s);
+// out must hold 0 before the first call; each call folds one level in (max of bit patterns)
+hipError_t launch_qoi_vtotal(const void* x, const void* y, const void* z, uint64_t n, bool f64,
+                             const double eps[3], unsigned long long* out, hipStream_t s);
 
 }  // namespace mdr

@@ -35,7 +35,7 @@ def run_case(mdr, ctx, levels_np, B, params, ks=None, check_streams=True):
     compare_refactor(r, orc, check_streams)
     rt = mdr.Retriever(ctx, r)
     outs = gpu_outputs(levels_np)
-    m = params.group_planes
+    m = min(params.group_planes, B)
     if ks is None:
         ks = sorted(set([0, m, min(B, 2 * m), B]))
     for k in ks:
