@@ -54,7 +54,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 4, 5])
+    ap.add_argument("--serve-requests", type=int, default=10000, help="serving workload: requests per load")
+    ap.add_argument("--serve-edge", type=int, default=512, help="serving workload: field edge")
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.9,2.0",
+                    help="serving workload: offered loads (x measured sequential capacity)")
+    ap.add_argument("--batch-vars", type=int, default=256, help="variables of the batched workload")
+    ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the launch-shape sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22,
                     help="values of the finest level the oracle baseline refactors")
@@ -93,12 +99,258 @@ def cpu_baseline(w, sample: int):
                       "incremental retrievals" % (x.size, x.nbytes / 2 ** 20, len(w["tols"]))}
 
 
+def progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def bench_batched(args):
+    """256 variables of uneven size (cube edge ~ U{16..256}, 5 Laplace levels,
+    f32): refactor every variable in one batched pass (a replayed HIP graph) and
+    retrieve all of them (every plane, then relative 1e-3) in one batched call,
+    against the same work done one variable at a time (mdr_refactor /
+    mdr_retrieve per variable) at identical bounds."""
+    import numpy as np
+    import torch
+
+    import paper_2505_00227_amd as mdr
+    import workloads
+
+    B = 32
+    edges, vs = workloads.batch_variables(seed=4, nvars=args.batch_vars, nlevels=5, lo=16, hi=256,
+                                          dtype=np.float32)
+    progress("generated", len(vs), "variables")
+    nvals = sum(a.size for v in vs for a in v)
+    nbytes = 4 * nvals
+    dev = [[torch.from_numpy(a).cuda() for a in v] for v in vs]
+    outs = [[torch.empty_like(t) for t in v] for v in dev]
+    del vs
+    ctx = mdr.Context(0)
+    params = mdr.default_params(group_planes=4)
+    tols = [0.0, 1e-3]  # 0 = every plane (relative bound 0 is met only by all planes)
+    torch.cuda.synchronize()
+
+    def batched_step(times):
+        t0 = time.perf_counter()
+        rs = mdr.refactor_batch(ctx, dev, B, params)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tr = []
+        for tol in tols:  # each bound from a fresh retriever
+            rts = [mdr.Retriever(ctx, r) for r in rs]
+            ta = time.perf_counter()
+            mdr.retrieve_batch(rts, [tol] * len(rts), outs)
+            torch.cuda.synchronize()
+            tr.append(time.perf_counter() - ta)
+            for rt in rts:
+                rt.close()
+        times.append((t1 - t0, tr))
+        for r in rs:
+            r.close()
+
+    def single_step(times):
+        t0 = time.perf_counter()
+        rs = [mdr.refactor(ctx, v, B, params) for v in dev]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tr = []
+        for tol in tols:
+            rts = [mdr.Retriever(ctx, r) for r in rs]
+            ta = time.perf_counter()
+            for rt, o in zip(rts, outs):
+                rt.retrieve(tol, o)
+            torch.cuda.synchronize()
+            tr.append(time.perf_counter() - ta)
+            for rt in rts:
+                rt.close()
+        times.append((t1 - t0, tr))
+        for r in rs:
+            r.close()
+
+    tune = []
+    if not args.no_tune:
+        # launch-shape sweep (results are identical for every shape; only time changes)
+        best = None
+        for tgt in (768, 1536, 2304, 4608, 9216):
+            for sv in (4096, 16384, 65536):
+                ctx.set_launch(enc_target_wg=tgt, stats_wg_values=sv, graphs=1)
+                t = []
+                for _ in range(2):
+                    batched_step(t)
+                ms = min(x[0] for x in t) * 1e3
+                tune.append({"enc_target_wg": tgt, "stats_wg_values": sv, "refactor_ms": ms})
+                progress("tune", tune[-1])
+                if best is None or ms < best[0]:
+                    best = (ms, tgt, sv)
+        ctx.set_launch(enc_target_wg=best[1], stats_wg_values=best[2], graphs=1)
+
+    for _ in range(args.warmup):
+        batched_step([])
+        single_step([])
+    bt, st = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched_step(bt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for _ in range(args.steps):
+        single_step(st)
+
+    def summary(times):
+        ref = statistics.median(x[0] for x in times)
+        ret = [statistics.median(x[1][i] for x in times) for i in range(len(tols))]
+        return {"refactor_ms": ref * 1e3, "refactor_gbps": nbytes / ref / 1e9,
+                "retrieve_ms": {("all" if t == 0 else "%.0e" % t): r * 1e3 for t, r in zip(tols, ret)},
+                "retrieve_gbps": {("all" if t == 0 else "%.0e" % t): nbytes / r / 1e9 for t, r in zip(tols, ret)},
+                "step_ms": (ref + sum(ret)) * 1e3}
+    sb, ss = summary(bt), summary(st)
+    moved = nbytes * (1 + len(tols))
+    res = {
+        "metric": "refactor & retrieve GB/s (frac of HBM peak); p50/p99 retrieval latency",
+        "value": moved / (elapsed / args.steps) / 1e9,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch-%d-vars-edge16..256-f32-5-levels" % len(dev), "values": nvals,
+                   "nplanes": B, "group_planes": 4, "bounds_rel": ["all planes", 1e-3],
+                   "parallelism": "single-gpu"},
+        "batched": sb,
+        "per_variable": ss,
+        "speedup_batched_vs_per_variable": ss["step_ms"] / sb["step_ms"],
+        "tune": tune,
+    }
+    print(json.dumps(res))
+
+
+def bench_serving(args):
+    """8 resident fields (edge^3 f32, 9 levels; fields 0..2 = vx, vy, vz), a
+    Poisson stream of retrieval requests (tolerance log-uniform in 1e-7..1e-1,
+    half raw fields, half V_total, 30% refining an earlier request), served with
+    continuous batching under a 16 GiB output budget at several offered loads,
+    against the same stream served one request at a time (one slot)."""
+    import numpy as np
+    import torch
+
+    import paper_2505_00227_amd as mdr
+    import workloads
+
+    ctx = mdr.Context(0)
+    params = mdr.default_params(group_planes=4)
+    fields = []
+    nbytes_field = 0
+    for f in range(8):
+        levels = workloads.field_levels(seed=50 + f, edge=args.serve_edge, nlevels=9, dtype=np.float32)
+        dev = [torch.from_numpy(a).cuda() for a in levels]
+        nbytes_field = sum(a.nbytes for a in levels)
+        fields.append(mdr.refactor(ctx, dev, 32, params))
+        torch.cuda.synchronize()
+        del dev, levels
+        progress("field", f, "refactored")
+
+    def make_requests(rate, n):
+        reqs = workloads.serving_requests(seed=58, n=n, nfields=8, rate=rate)
+        for q in reqs:  # a refinement continues its parent's kind and field
+            if q["parent"] is not None:
+                p = reqs[q["parent"]]
+                q["kind"], q["field"] = p["kind"], p["field"]
+        return reqs
+
+    def run(reqs, slots):
+        srv = mdr.Server(ctx, hbm_budget=16 << 30, max_slots=slots)
+        for r in fields:
+            srv.add_field(r)
+        tickets = [0] * len(reqs)
+        by_ticket = {}
+        lat, served = [], 0
+        t0 = time.perf_counter()
+        i = 0
+        while len(lat) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i]["t"] <= now:
+                q = reqs[i]
+                parent = tickets[q["parent"]] if q["parent"] is not None else 0
+                if q["kind"] == "raw":
+                    t = srv.submit(mdr.MDR_REQ_FIELD, [q["field"]], q["tol"], parent=parent)
+                else:
+                    t = srv.submit(mdr.MDR_REQ_QOI_VTOTAL, [0, 1, 2], q["tol"], parent=parent)
+                tickets[i] = t
+                by_ticket[t] = q
+                i += 1
+            for c in srv.poll(1024):
+                if c["status"] != 0:
+                    raise RuntimeError("request failed: %r" % (c,))
+                lat.append(c["t_done_ms"] - c["t_submit_ms"])
+                served += nbytes_field * (1 if by_ticket[c["ticket"]]["kind"] == "raw" else 3)
+                srv.release(c["ticket"])
+            if i < len(reqs):
+                time.sleep(max(0.0, min(0.0005, reqs[i]["t"] - (time.perf_counter() - t0))))
+            else:
+                time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat.sort()
+        pct = lambda p: lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
+        return {"requests": len(reqs), "wall_s": wall, "gbps": served / wall / 1e9,
+                "p50_ms": pct(50), "p99_ms": pct(99), "mean_ms": sum(lat) / len(lat),
+                "batch_depth": st["step_requests"] / max(1, st["steps"])}
+
+    # capacity: the request mix served back to back, one at a time
+    n = args.serve_requests
+    cap_reqs = make_requests(1e9, min(n, 300))
+    cap = run(cap_reqs, 1)
+    capacity = cap["requests"] / cap["wall_s"]
+    progress("capacity %.1f req/s" % capacity)
+    loads = {}
+    for rho in [float(x) for x in args.serve_loads.split(",")]:
+        reqs = make_requests(rho * capacity, n)
+        b = run(reqs, 64)
+        progress("load", rho, "batched", b)
+        q = run(reqs, 1)
+        progress("load", rho, "sequential", q)
+        loads["%.1f" % rho] = {"batched": b, "sequential": q}
+    main_load = loads.get("0.9") or next(iter(loads.values()))
+    res = {
+        "metric": "refactor & retrieve GB/s (frac of HBM peak); p50/p99 retrieval latency",
+        "value": main_load["batched"]["gbps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": n,
+        "warmup": 0,
+        "ms_per_step": main_load["batched"]["mean_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving-8-fields-%d^3-f32-9-levels" % args.serve_edge,
+                   "requests": n, "budget_gib": 16, "slots": 64, "parallelism": "single-gpu"},
+        "capacity_req_per_s": capacity,
+        "latency_ms": {"p50": main_load["batched"]["p50_ms"], "p99": main_load["batched"]["p99_ms"]},
+        "loads": loads,
+    }
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU component "
               "(variables and chunks shard independently); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.config == 4:
+        bench_batched(args)
+        return
+    if args.config == 5:
+        bench_serving(args)
+        return
     import numpy as np
     import torch
 

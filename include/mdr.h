@@ -209,6 +209,15 @@ mdr_status mdr_retrieve(mdr_retriever* rt, mdr_bound kind, double tol, void* con
  * whole group and may not go below what is already held). */
 mdr_status mdr_retrieve_planes(mdr_retriever* rt, const uint32_t* k, void* const* level_out,
                                void* stream, mdr_retrieve_info* info);
+/* Retrieval for n retrievers at once (each at most once): retriever i plans to
+ * tols[i] (kind as in mdr_retrieve) and writes level_out[i][l].  Results equal n
+ * separate mdr_retrieve calls, bit for bit; the work is one Huffman-decode
+ * launch for every group that enters a plan and one reconstruction launch per
+ * dtype for every level of every variable.  infos (n entries) may be NULL.
+ * On error no retriever changes. */
+mdr_status mdr_retrieve_batch(mdr_retriever* const* rts, uint32_t n, mdr_bound kind,
+                              const double* tols, void* const* const* level_out, void* stream,
+                              mdr_retrieve_info* infos);
 /* Planes currently held per level (nlevels entries). */
 mdr_status mdr_retriever_planes(const mdr_retriever* rt, uint32_t* k);
 
@@ -240,6 +249,75 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
                                    mdr_bound kind, double tau, double mape_c,
                                    void* const* out_x, void* const* out_y, void* const* out_z,
                                    void* stream, mdr_qoi_info* info);
+
+/* ---------------------------------------------------------------- serving */
+/*
+ * A retrieval server keeps refactored fields resident in HBM and serves
+ * requests from an engine thread with continuous batching: every engine step
+ * advances every admitted request by one round (a field request finishes in one
+ * round; a V_total request takes the rounds of mdr_retrieve_qoi_vtotal), with
+ * one batched decode, one batched reconstruction and one batched estimate for
+ * all of them on the server's own stream.  A request is admitted when one of
+ * max_slots slots and the HBM for its outputs (within hbm_budget) are free; the
+ * others wait in arrival order.  Decoded groups are cached per field and shared
+ * by every request on it, so planes fetched once are reused.  A request's
+ * result depends only on its own tolerance and starting planes: it is the same,
+ * bit for bit, alone or in any mix, and equal to mdr_retrieve /
+ * mdr_retrieve_qoi_vtotal from the same planes.  The server uses a context of
+ * its own on ctx's device; fields must outlive the server.
+ */
+typedef struct mdr_server mdr_server;
+
+typedef enum { MDR_REQ_FIELD = 0, MDR_REQ_QOI_VTOTAL = 1 } mdr_request_kind;
+
+typedef struct {
+    int32_t kind;        /* MDR_REQ_FIELD: field[0]; MDR_REQ_QOI_VTOTAL: vx, vy, vz = field[0..2] */
+    uint32_t field[3];
+    int32_t bound;       /* MDR_ABS, or MDR_REL (field: x value range; QoI: x Q_max)              */
+    double tol;          /* L-inf tolerance (field) or V_total tolerance (QoI)                    */
+    double mape_c;       /* QoI: MAPE threshold (<= 0 means 10)                                   */
+    uint64_t parent;     /* 0, or the ticket of an earlier request of the same kind and fields:   */
+                         /* start from the planes it ended with (an incremental refinement)       */
+    uint64_t tag;        /* echoed in the completion                                              */
+} mdr_request;
+
+typedef struct {
+    uint64_t ticket, tag;
+    int32_t status;          /* mdr_status of the request                                          */
+    int32_t met;             /* bound <= tol_abs                                                   */
+    double tol_abs;          /* absolute tolerance worked to                                       */
+    double bound;            /* field: L-inf bound of the planes used; QoI: the estimate tau'      */
+    uint64_t bytes_fetched;  /* stream bytes of groups beyond the starting planes                  */
+    uint32_t iterations;     /* engine rounds taken                                               */
+    uint32_t pad;
+    double t_submit_ms, t_start_ms, t_done_ms;  /* server clock (ms since creation)             */
+} mdr_completion;
+
+typedef struct {
+    uint32_t pending, active, completed_unreleased, pad;
+    uint64_t steps;          /* engine steps so far                                                */
+    uint64_t step_requests;  /* sum over steps of the requests advanced (batching depth)           */
+    uint64_t hbm_in_use, hbm_budget;
+} mdr_server_info;
+
+mdr_status mdr_server_create(mdr_context* ctx, uint64_t hbm_budget, uint32_t max_slots, mdr_server** out);
+/* Registers a refactored field (while no request is queued); ids count from 0. */
+mdr_status mdr_server_add_field(mdr_server* s, const mdr_refactored* r, uint32_t* field_id);
+/* Queues a request and returns at once.  Rejected at once (no ticket): bad
+ * fields, mismatched QoI fields, outputs larger than the budget, unknown parent. */
+mdr_status mdr_server_submit(mdr_server* s, const mdr_request* req, uint64_t* ticket);
+/* Copies up to cap completions (oldest first) and returns at once. */
+mdr_status mdr_server_poll(mdr_server* s, mdr_completion* out, uint32_t cap, uint32_t* n);
+/* Device output of a completed request: component comp (0 for a field request;
+ * 0..2 = x, y, z for QoI), level `level`, n values of the field's dtype.  Valid
+ * until mdr_server_release(ticket). */
+mdr_status mdr_server_output(mdr_server* s, uint64_t ticket, uint32_t comp, uint32_t level, void** dev_ptr,
+                             uint64_t* n);
+/* Returns a completed request's outputs to the budget. */
+mdr_status mdr_server_release(mdr_server* s, uint64_t ticket);
+mdr_status mdr_server_stats(mdr_server* s, mdr_server_info* info);
+/* Stops the engine (queued requests are dropped) and frees everything. */
+void mdr_server_destroy(mdr_server* s);
 
 #ifdef __cplusplus
 }

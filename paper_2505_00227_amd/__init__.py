@@ -70,6 +70,30 @@ class mdr_retrieve_info(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class mdr_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("field", C.c_uint32 * 3), ("bound", C.c_int32),
+                ("tol", C.c_double), ("mape_c", C.c_double), ("parent", C.c_uint64),
+                ("tag", C.c_uint64)]
+
+
+class mdr_completion(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("tag", C.c_uint64), ("status", C.c_int32), ("met", C.c_int32),
+                ("tol_abs", C.c_double), ("bound", C.c_double), ("bytes_fetched", C.c_uint64),
+                ("iterations", C.c_uint32), ("pad", C.c_uint32), ("t_submit_ms", C.c_double),
+                ("t_start_ms", C.c_double), ("t_done_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
+class mdr_server_info(C.Structure):
+    _fields_ = [("pending", C.c_uint32), ("active", C.c_uint32), ("completed_unreleased", C.c_uint32),
+                ("pad", C.c_uint32), ("steps", C.c_uint64), ("step_requests", C.c_uint64),
+                ("hbm_in_use", C.c_uint64), ("hbm_budget", C.c_uint64)]
+
+
+MDR_REQ_FIELD, MDR_REQ_QOI_VTOTAL = 0, 1
+
 _vp, _u32, _u64, _i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
 _P = C.POINTER
 _SIGS = {
@@ -97,8 +121,18 @@ _SIGS = {
     "mdr_retrieve": ([_vp, C.c_int, C.c_double, _P(_vp), _vp, _P(mdr_retrieve_info)], C.c_int),
     "mdr_retrieve_planes": ([_vp, _P(_u32), _P(_vp), _vp, _P(mdr_retrieve_info)], C.c_int),
     "mdr_retriever_planes": ([_vp, _P(_u32)], C.c_int),
+    "mdr_retrieve_batch": ([_P(_vp), _u32, C.c_int, _P(C.c_double), _P(_P(_vp)), _vp,
+                            _P(mdr_retrieve_info)], C.c_int),
     "mdr_retrieve_qoi_vtotal": ([_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _P(_vp), _P(_vp),
                                  _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
+    "mdr_server_create": ([_vp, _u64, _u32, _P(_vp)], C.c_int),
+    "mdr_server_add_field": ([_vp, _vp, _P(_u32)], C.c_int),
+    "mdr_server_submit": ([_vp, _P(mdr_request), _P(_u64)], C.c_int),
+    "mdr_server_poll": ([_vp, _P(mdr_completion), _u32, _P(_u32)], C.c_int),
+    "mdr_server_output": ([_vp, _u64, _u32, _u32, _P(_vp), _P(_u64)], C.c_int),
+    "mdr_server_release": ([_vp, _u64], C.c_int),
+    "mdr_server_stats": ([_vp, _P(mdr_server_info)], C.c_int),
+    "mdr_server_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -345,6 +379,19 @@ class Retriever:
         return list(k)
 
 
+def retrieve_batch(rts, tols, outs_per_var, relative: bool = True, stream=None) -> list:
+    """mdr_retrieve_batch: retriever i to tols[i], writing outs_per_var[i] (per level)."""
+    n = len(rts)
+    hs = (_vp * n)(*[r.handle.value for r in rts])
+    tl = (C.c_double * n)(*[float(t) for t in tols])
+    keep = [Retriever._outs(o) for o in outs_per_var]
+    op = (_P(_vp) * n)(*[C.cast(o, _P(_vp)) for o in keep])
+    infos = (mdr_retrieve_info * n)()
+    _check(_lib.mdr_retrieve_batch(hs, n, MDR_REL if relative else MDR_ABS, tl, op,
+                                   _stream_ptr(stream), infos))
+    return [i.as_dict() for i in infos]
+
+
 def retrieve_qoi_vtotal(rx: Retriever, ry: Retriever, rz: Retriever, tau: float, outs3,
                         relative: bool = False, mape_c: float = 10.0, stream=None) -> dict:
     """mdr_retrieve_qoi_vtotal: refine vx, vy, vz until the V_total bound meets tau."""
@@ -354,3 +401,64 @@ def retrieve_qoi_vtotal(rx: Retriever, ry: Retriever, rz: Retriever, tau: float,
                                         MDR_REL if relative else MDR_ABS, float(tau), float(mape_c),
                                         o[0], o[1], o[2], _stream_ptr(stream), C.byref(info)))
     return info.as_dict()
+
+
+class Server:
+    """Retrieval server (mdr_server): resident fields, continuous batching on an
+    engine thread, admission by HBM budget."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int = 64):
+        h = _vp()
+        _check(_lib.mdr_server_create(ctx.handle, int(hbm_budget), int(max_slots), C.byref(h)))
+        self.ctx, self.handle, self.fields = ctx, h, []
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mdr_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def add_field(self, r: Refactored) -> int:
+        fid = _u32()
+        _check(_lib.mdr_server_add_field(self.handle, r.handle, C.byref(fid)))
+        self.fields.append(r)  # keep the field alive as long as the server
+        return fid.value
+
+    def submit(self, kind: int, fields, tol: float, relative: bool = True, parent: int = 0,
+               tag: int = 0, mape_c: float = 10.0) -> int:
+        q = mdr_request()
+        q.kind = kind
+        fl = list(fields) + [0] * (3 - len(fields))
+        for i in range(3):
+            q.field[i] = int(fl[i])
+        q.bound = MDR_REL if relative else MDR_ABS
+        q.tol = float(tol)
+        q.mape_c = float(mape_c)
+        q.parent = int(parent)
+        q.tag = int(tag)
+        t = _u64()
+        _check(_lib.mdr_server_submit(self.handle, C.byref(q), C.byref(t)))
+        return t.value
+
+    def poll(self, cap: int = 256) -> list:
+        buf = (mdr_completion * cap)()
+        n = _u32()
+        _check(_lib.mdr_server_poll(self.handle, buf, cap, C.byref(n)))
+        return [buf[i].as_dict() for i in range(n.value)]
+
+    def output(self, ticket: int, comp: int, level: int):
+        """(device pointer, values) of one output level of a completed request."""
+        p, n = _vp(), _u64()
+        _check(_lib.mdr_server_output(self.handle, int(ticket), int(comp), int(level), C.byref(p),
+                                      C.byref(n)))
+        return (p.value or 0), n.value
+
+    def release(self, ticket: int) -> None:
+        _check(_lib.mdr_server_release(self.handle, int(ticket)))
+
+    def stats(self) -> dict:
+        i = mdr_server_info()
+        _check(_lib.mdr_server_stats(self.handle, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in i._fields_ if f != "pad"}

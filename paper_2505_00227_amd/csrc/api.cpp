@@ -227,111 +227,17 @@ double value_range(const mdr_refactored* r)
 }
 
 // ------------------------------------------------------------------ retrieve
-mdr_status retrieve_impl(mdr_retriever* rt, const std::vector<uint32_t>& knew,
-                         void* const* level_out, hipStream_t s, double tol_abs,
-                         mdr_retrieve_info* info, bool all_levels = true)
+static mdr_status retrieve_one(mdr_retriever* rt, const std::vector<uint32_t>& knew,
+                               void* const* level_out, hipStream_t s, double tol_abs,
+                               mdr_retrieve_info* info)
 {
-    const mdr_refactored* r = rt->r;
-    const bool f64 = r->dtype == MDR_F64;
-    const uint32_t B = r->B, m = r->m, G = r->G;
-    MDR_HIP(hipSetDevice(rt->ctx->device));
-    for (size_t l = 0; l < r->levels.size(); ++l)
-        if (r->levels[l].n && !level_out[l])
-            return fail(MDR_ERR_INVALID_ARG, "level_out[" + std::to_string(l) + "] is NULL");
-
-    // decode the units entering [k_old, k_new); state is committed at the end
-    std::vector<std::pair<size_t, uint32_t>> fresh;
-    std::vector<PoolBuf> fresh_bufs;
-    struct SyncOnFail {
-        hipStream_t s;
-        bool armed = true;
-        ~SyncOnFail() { if (armed) (void)hipStreamSynchronize(s); }
-    } sync_on_fail{s};
-    uint64_t fetched = 0;
-    uint32_t groups = 0;
-    for (size_t l = 0; l < r->levels.size(); ++l) {
-        const LevelRec& LR = r->levels[l];
-        const uint32_t k0 = rt->k[l], k1 = knew[l];
-        for (uint32_t slot = 0; slot <= B; slot = slot == 0 ? 1 : slot + m) {
-            bool needed_before = slot == 0 ? k0 > 0 : (slot - 1) < k0;
-            bool needed_now = slot == 0 ? k1 > 0 : (slot - 1) < k1;
-            if (!needed_now || needed_before) continue;
-            const UnitRec& ur = LR.units[slot];
-            fetched += ur.bytes;
-            ++groups;
-            if (ur.method == MDR_DC || LR.n == 0) continue;
-            PoolBuf buf;
-            hipError_t e = buf.alloc(rt->ctx->pool, std::max<uint64_t>(ur.S, 4));
-            if (e != hipSuccess) return hip_fail(e, "hipMalloc(decoded group)");
-            if (ur.method == MDR_HUF) {
-                StageTimer tm(rt->ctx, MDR_STAGE_HUF_DECODE, s);
-                MDR_HIP(launch_huf_decode(ur.dev, ur.S, r->prm.huf_chunk, r->prm.huf_lmax,
-                                          static_cast<uint8_t*>(buf.p), s));
-            } else if (ur.method == MDR_RLE) {
-                uint64_t need = 4 * (ur.nruns + 64 + scan_temp_words(ur.nruns));
-                if (rt->temp.bytes < need) {
-                    MDR_HIP(hipStreamSynchronize(s));
-                    hipError_t e2 = rt->temp.alloc(rt->ctx->pool, need);
-                    if (e2 != hipSuccess) return hip_fail(e2, "hipMalloc(decode scratch)");
-                }
-                StageTimer tm(rt->ctx, MDR_STAGE_RLE_DECODE, s);
-                MDR_HIP(launch_rle_decode(ur.dev, ur.S / 4 / G, G, ur.nruns,
-                                          static_cast<uint8_t*>(buf.p),
-                                          static_cast<uint32_t*>(rt->temp.p), s));
-            } else {
-                return fail(MDR_ERR_CORRUPT_STREAM, "unknown lossless method");
-            }
-            fresh.push_back({l, slot});
-            fresh_bufs.push_back(std::move(buf));
-        }
-    }
-    auto source = [&](size_t l, uint32_t slot) -> const uint8_t* {
-        for (size_t i = 0; i < fresh.size(); ++i)
-            if (fresh[i].first == l && fresh[i].second == slot)
-                return static_cast<const uint8_t*>(fresh_bufs[i].p);
-        const PoolBuf& d = rt->dec[l][slot];
-        if (d.p) return static_cast<const uint8_t*>(d.p);
-        return r->levels[l].units[slot].dev;  // direct copy: the payload is the plane rows
-    };
-    for (size_t l = 0; l < r->levels.size(); ++l) {
-        const LevelRec& LR = r->levels[l];
-        if (LR.n == 0) continue;
-        if (!all_levels && knew[l] == rt->k[l]) continue;  // output already holds these planes
-        ReconJob job{};
-        job.out = level_out[l];
-        job.n = LR.n;
-        job.nbd = LR.nbd;
-        job.B = B;
-        job.k = knew[l];
-        job.e = LR.e;
-        if (knew[l] > 0) {
-            for (uint32_t row = 0; row <= B; ++row) {
-                uint32_t slot = row == 0 ? 0 : 1 + ((row - 1) / m) * m;
-                if (row > 0 && row - 1 >= knew[l]) break;
-                uint32_t r0, r1;
-                slot_rows(slot, B, m, r0, r1);
-                job.rows[row] = reinterpret_cast<const uint32_t*>(source(l, slot)) +
-                                (uint64_t)(row - r0) * LR.nbd;
-            }
-        }
-        StageTimer tm(rt->ctx, MDR_STAGE_RECONSTRUCT, s);
-        MDR_HIP(launch_reconstruct(job, f64, s));
-    }
-    // commit
-    sync_on_fail.armed = false;
-    for (size_t i = 0; i < fresh.size(); ++i)
-        rt->dec[fresh[i].first][fresh[i].second] = std::move(fresh_bufs[i]);
-    rt->k = knew;
-    rt->bytes_held += fetched;
-    if (info) {
-        info->tol_abs = tol_abs;
-        info->bound = plan_bound(r, knew);
-        info->bytes_fetched = fetched;
-        info->bytes_held = rt->bytes_held;
-        info->groups_fetched = groups;
-        info->met = info->bound <= tol_abs ? 1 : 0;
-    }
-    return MDR_OK;
+    RetrieveTask t;
+    t.rt = rt;
+    t.knew = knew;
+    t.out = level_out;
+    t.tol_abs = tol_abs;
+    t.info = info;
+    return retrieve_many(rt->ctx, &t, 1, s);
 }
 
 }  // namespace mdr
@@ -581,7 +487,7 @@ mdr_status mdr_retrieve(mdr_retriever* rt, mdr_bound kind, double tol, void* con
     double tol_abs = kind == MDR_REL ? tol * value_range(rt->r) : tol;
     std::vector<uint32_t> k = rt->k;
     plan_to(rt->r, tol_abs, k);
-    return retrieve_impl(rt, k, level_out, static_cast<hipStream_t>(stream), tol_abs, info);
+    return retrieve_one(rt, k, level_out, static_cast<hipStream_t>(stream), tol_abs, info);
 }
 
 mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_retriever* vz,
@@ -645,17 +551,37 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
     double tprime = 0.0, eps[3] = {0, 0, 0};
     for (;;) {
         ++it;
-        for (int c = 0; c < 3; ++c) {
-            mdr_retrieve_info ri{};
-            st = retrieve_impl(rts[c], ks[c], outs[c], s, 0.0, &ri, it == 1);
+        {
+            RetrieveTask tk[3];
+            mdr_retrieve_info ri[3];
+            for (int c = 0; c < 3; ++c) {
+                tk[c].rt = rts[c];
+                tk[c].knew = ks[c];
+                tk[c].out = outs[c];
+                tk[c].info = &ri[c];
+                tk[c].all_levels = it == 1;
+            }
+            st = retrieve_many(ctx, tk, 3, s);
             if (st) return st;
-            fetched += ri.bytes_fetched;
-            eps[c] = plan_bound(rts[c]->r, ks[c]);
+            for (int c = 0; c < 3; ++c) {
+                fetched += ri[c].bytes_fetched;
+                eps[c] = plan_bound(rts[c]->r, ks[c]);
+            }
         }
-        MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(acc), 2, 0u, s));
-        for (size_t l = 0; l < r0->levels.size(); ++l) {
-            if (r0->levels[l].n == 0) continue;
-            MDR_HIP(launch_qoi_vtotal(out_x[l], out_y[l], out_z[l], r0->levels[l].n, f64, eps, acc, s));
+        {
+            std::vector<QoiJob> jobs;
+            for (size_t l = 0; l < r0->levels.size(); ++l) {
+                QoiJob j{};
+                j.x = out_x[l];
+                j.y = out_y[l];
+                j.z = out_z[l];
+                j.n = r0->levels[l].n;
+                for (int c = 0; c < 3; ++c) j.eps[c] = eps[c];
+                j.acc = acc;
+                jobs.push_back(j);
+            }
+            st = enqueue_qoi(ctx, jobs, std::vector<bool>(jobs.size(), f64), acc, 1, s);
+            if (st) return st;
         }
         unsigned long long* hb = static_cast<unsigned long long*>(ctx->stage);
         MDR_HIP(hipMemcpyAsync(hb, acc, 8, hipMemcpyDeviceToHost, s));
@@ -691,6 +617,29 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
     return MDR_OK;
 }
 
+mdr_status mdr_retrieve_batch(mdr_retriever* const* rts, uint32_t n, mdr_bound kind,
+                              const double* tols, void* const* const* level_out, void* stream,
+                              mdr_retrieve_info* infos)
+{
+    g_err.clear();
+    if (n == 0) return MDR_OK;
+    if (!rts || !tols || !level_out) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
+    if (kind != MDR_ABS && kind != MDR_REL) return fail(MDR_ERR_INVALID_ARG, "bad bound kind");
+    std::vector<RetrieveTask> tk(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!rts[i] || !level_out[i]) return fail(MDR_ERR_INVALID_ARG, "NULL retriever or outputs");
+        if (!(tols[i] >= 0.0) || std::isinf(tols[i]))
+            return fail(MDR_ERR_INVALID_ARG, "tolerance must be finite and >= 0");
+        tk[i].rt = rts[i];
+        tk[i].tol_abs = kind == MDR_REL ? tols[i] * value_range(rts[i]->r) : tols[i];
+        tk[i].knew = rts[i]->k;
+        plan_to(rts[i]->r, tk[i].tol_abs, tk[i].knew);
+        tk[i].out = level_out[i];
+        tk[i].info = infos ? infos + i : nullptr;
+    }
+    return retrieve_many(rts[0]->ctx, tk.data(), n, static_cast<hipStream_t>(stream));
+}
+
 mdr_status mdr_retrieve_planes(mdr_retriever* rt, const uint32_t* kreq, void* const* level_out,
                                void* stream, mdr_retrieve_info* info)
 {
@@ -703,7 +652,7 @@ mdr_status mdr_retrieve_planes(mdr_retriever* rt, const uint32_t* kreq, void* co
         uint32_t want = std::min(B, (kreq[l] + m - 1) / m * m);
         k[l] = std::max(k[l], want);
     }
-    return retrieve_impl(rt, k, level_out, static_cast<hipStream_t>(stream), 0.0, info);
+    return retrieve_one(rt, k, level_out, static_cast<hipStream_t>(stream), 0.0, info);
 }
 
 }  // extern "C"

@@ -173,6 +173,54 @@ mdr_status refactor_batch(mdr_context* ctx, const VarLevels* vars, uint32_t nvar
                           mdr_refactored** outs);
 void release_graphs(mdr_context* ctx);
 
+// One retriever's share of a batched retrieval.
+struct RetrieveTask {
+    mdr_retriever* rt = nullptr;
+    std::vector<uint32_t> knew;         // planes per level after the call
+    void* const* out = nullptr;         // per-level outputs
+    double tol_abs = 0.0;
+    mdr_retrieve_info* info = nullptr;  // may be NULL
+    bool all_levels = true;             // false: skip levels whose planes did not change
+    bool reconstruct = true;            // false: decode only (a shared decode cache)
+};
+// A reconstruction from a retriever's decoded groups at k (each k_l no more
+// than the planes it holds after the call's decodes), written to out.
+struct ReconOnly {
+    const mdr_retriever* rt = nullptr;
+    std::vector<uint32_t> k;
+    const std::vector<uint32_t>* kprev = nullptr;  // skip levels where k equals this (may be NULL)
+    void* const* out = nullptr;
+};
+// Decode and reconstruct for every task at once (each retriever at most once),
+// plus the extra reconstructions.
+mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, hipStream_t s,
+                         const ReconOnly* extra = nullptr, size_t nextra = 0);
+// V_total estimates: jobs (acc pointers included) in one launch per dtype,
+// after clearing `nacc` accumulators at acc0.
+mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const std::vector<bool>& f64,
+                       unsigned long long* acc0, uint32_t nacc, hipStream_t s);
+
+// tolerance planner (greedy over levels, exact error tables)
+double plan_bound(const mdr_refactored* r, const std::vector<uint32_t>& k);
+bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k);
+double plan_to(const mdr_refactored* r, double tol, std::vector<uint32_t>& k);
+double value_range(const mdr_refactored* r);
+
+// Staging for the job tables of asynchronous launches: pinned host memory and
+// its device copy, reused once the event recorded behind their readers fires.
+constexpr int kDescSlots = 4;
+struct DescSlot {
+    DevBuf dev;
+    void* host = nullptr;
+    uint64_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+    DescSlot() = default;
+    DescSlot(const DescSlot&) = delete;
+    DescSlot& operator=(const DescSlot&) = delete;
+    ~DescSlot();
+};
+
 }  // namespace mdr
 
 namespace mdr {
@@ -213,6 +261,9 @@ struct mdr_context {
     hipStream_t capture_stream = nullptr;
     std::vector<std::unique_ptr<mdr::BatchGraph>> graph_cache;
     uint64_t graph_clock = 0;
+    // job tables of retrieval launches
+    mdr::DescSlot ring[mdr::kDescSlots];
+    uint32_t ring_next = 0;
     void* stage = nullptr;  // pinned host staging
     uint64_t stage_bytes = 0;
 };

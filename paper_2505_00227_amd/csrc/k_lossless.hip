@@ -497,10 +497,14 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
 // ------------------------------------------------------------------ Huffman decode
 // One thread per chunk; a 2^lmax-entry table in LDS maps the next lmax bits to
 // (symbol, length).
-__global__ __launch_bounds__(kThreads) void k_huf_decode(const uint8_t* payload, uint64_t S,
-                                                         uint32_t chunk, uint32_t lmax,
-                                                         uint8_t* g, uint32_t nchunks)
+__global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
+                                                         const uint32_t* __restrict__ wg_job)
 {
+    const DecodeJob& job = jobs[wg_job[blockIdx.x]];
+    const uint8_t* payload = job.payload;
+    const uint64_t S = job.S;
+    const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
+    uint8_t* g = job.out;
     __shared__ uint16_t s_lut[1 << kLutBitsMax];
     __shared__ uint8_t s_len[256];
     __shared__ uint32_t s_count[33], s_first[33], s_offset[33];
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const uint8_t* payload,
         s_lut[i] = ent;
     }
     __syncthreads();
-    const uint32_t c = blockIdx.x * kThreads + tid;
+    const uint32_t c = (blockIdx.x - job.wg_base) * kThreads + tid;
     if (c >= nchunks) return;
     const uint32_t* off = reinterpret_cast<const uint32_t*>(payload + kHufHeader);
     const uint32_t* words = reinterpret_cast<const uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1));
@@ -658,13 +662,11 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
     return hipGetLastError();
 }
 
-hipError_t launch_huf_decode(const uint8_t* payload, uint64_t S, uint32_t chunk, uint32_t lmax,
-                             uint8_t* g, hipStream_t s)
+hipError_t launch_huf_decode_batch(const DecodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
+                                   hipStream_t s)
 {
-    const uint32_t nchunks = (uint32_t)((S + chunk - 1) / chunk);
-    if (nchunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_huf_decode, dim3(blocks_for(nchunks, kThreads, 1u << 30)), dim3(kThreads),
-                       0, s, payload, S, chunk, lmax, g, nchunks);
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_huf_decode, dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     return hipGetLastError();
 }
 

@@ -14,11 +14,14 @@ namespace {
 // write x = (-1)^s * mag * 2^(e-B).  The magnitude keeps at most the input
 // type's significand bits, so the integer-to-float conversion and the ldexp
 // are exact (subnormal results included).
-template <bool F64, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_reconstruct(ReconJob j)
+// One launch covers many levels (of many variables): workgroup -> job via wg_job.
+template <bool F64>
+__global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __restrict__ jobs,
+                                                          const uint32_t* __restrict__ wg_job)
 {
     using T = std::conditional_t<F64, double, float>;
-    const uint32_t blk = blockIdx.x * kThreads + threadIdx.x;
+    const ReconJob& j = jobs[wg_job[blockIdx.x]];
+    const uint32_t blk = (blockIdx.x - j.wg_base) * kThreads + threadIdx.x;
     if (blk >= j.nbd) return;
     const uint64_t base = (uint64_t)blk * 32;
     if (base >= j.n) return;
@@ -57,7 +60,7 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(ReconJob j)
             v[t] = ((sgn >> t) & 1u) ? -a : a;
         }
     }
-    if (VEC && cnt == 32) {
+    if (j.vec && cnt == 32) {
         if constexpr (F64) {
             double2* p = reinterpret_cast<double2*>(out);
 #pragma unroll
@@ -78,19 +81,21 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(ReconJob j)
 // |v^2 - vhat^2| <= eps_c (2|vhat| + eps_c); the estimate is the maximum over
 // points of the sum over x, y, z, evaluated in double in that order (no
 // contraction: the library is built with -ffp-contract=off).
+// Many (request, level) jobs in one launch; each job folds its maximum into
+// its own accumulator.
 template <bool F64>
-__global__ __launch_bounds__(kThreads) void k_qoi_vtotal(const void* px, const void* py,
-                                                         const void* pz, uint64_t n, double ex,
-                                                         double ey, double ez,
-                                                         unsigned long long* out)
+__global__ __launch_bounds__(kThreads) void k_qoi_vtotal_batch(const QoiJob* __restrict__ jobs,
+                                                               const uint32_t* __restrict__ wg_job)
 {
     using T = std::conditional_t<F64, double, float>;
-    const T* x = static_cast<const T*>(px);
-    const T* y = static_cast<const T*>(py);
-    const T* z = static_cast<const T*>(pz);
+    const QoiJob& j = jobs[wg_job[blockIdx.x]];
+    const T* x = static_cast<const T*>(j.x);
+    const T* y = static_cast<const T*>(j.y);
+    const T* z = static_cast<const T*>(j.z);
+    const double ex = j.eps[0], ey = j.eps[1], ez = j.eps[2];
     double worst = 0.0;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint64_t stride = (uint64_t)j.grid * blockDim.x;
+    for (uint64_t i = (uint64_t)(blockIdx.x - j.wg_base) * blockDim.x + threadIdx.x; i < j.n; i += stride) {
         double ax = fabs((double)x[i]), ay = fabs((double)y[i]), az = fabs((double)z[i]);
         double tx = ex * ((2.0 * ax) + ex);
         double ty = ey * ((2.0 * ay) + ey);
@@ -111,43 +116,31 @@ __global__ __launch_bounds__(kThreads) void k_qoi_vtotal(const void* px, const v
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kThreads / 64; ++w) worst = s_w[w] > worst ? s_w[w] : worst;
-        atomicMax(out, (unsigned long long)__double_as_longlong(worst));
+        atomicMax(j.acc, (unsigned long long)__double_as_longlong(worst));
     }
 }
 
 }  // namespace
 
-hipError_t launch_qoi_vtotal(const void* x, const void* y, const void* z, uint64_t n, bool f64,
-                             const double eps[3], unsigned long long* out, hipStream_t s)
+hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
+                                   hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    uint64_t g = (n + kThreads * 8 - 1) / (kThreads * 8);
-    if (g > 1024) g = 1024;
+    if (grid == 0) return hipSuccess;
     if (f64)
-        hipLaunchKernelGGL((k_qoi_vtotal<true>), dim3((unsigned)g), dim3(kThreads), 0, s, x, y, z, n,
-                           eps[0], eps[1], eps[2], out);
+        hipLaunchKernelGGL((k_qoi_vtotal_batch<true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     else
-        hipLaunchKernelGGL((k_qoi_vtotal<false>), dim3((unsigned)g), dim3(kThreads), 0, s, x, y, z, n,
-                           eps[0], eps[1], eps[2], out);
+        hipLaunchKernelGGL((k_qoi_vtotal_batch<false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     return hipGetLastError();
 }
 
-hipError_t launch_reconstruct(const ReconJob& job, bool f64, hipStream_t s)
+hipError_t launch_reconstruct_batch(const ReconJob* jobs, const uint32_t* wg_job, uint32_t grid,
+                                   bool f64, hipStream_t s)
 {
-    if (job.n == 0) return hipSuccess;
-    dim3 g((job.nbd + kThreads - 1) / kThreads), b(kThreads);
-    bool vec = ((uintptr_t)job.out % 16) == 0;
-    if (f64) {
-        if (vec)
-            hipLaunchKernelGGL((k_reconstruct<true, true>), g, b, 0, s, job);
-        else
-            hipLaunchKernelGGL((k_reconstruct<true, false>), g, b, 0, s, job);
-    } else {
-        if (vec)
-            hipLaunchKernelGGL((k_reconstruct<false, true>), g, b, 0, s, job);
-        else
-            hipLaunchKernelGGL((k_reconstruct<false, false>), g, b, 0, s, job);
-    }
+    if (grid == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL((k_reconstruct<true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+    else
+        hipLaunchKernelGGL((k_reconstruct<false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     return hipGetLastError();
 }
 

@@ -138,24 +138,45 @@ hipError_t launch_scan_exclusive(const uint32_t* in, uint32_t* out, uint64_t n, 
 // scan_part: 2 * kPersistWg + 64 u32 of scratch.
 hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_dev, uint32_t* scan_part,
                                  hipStream_t s);
-// Huffman decode: payload u64 nsym | u8 len[256] | u32 off[nchunks+1] | u32 words[]
-hipError_t launch_huf_decode(const uint8_t* payload, uint64_t S, uint32_t chunk, uint32_t lmax,
-                             uint8_t* g, hipStream_t s);
+// Huffman decode of many streams in one launch (payload u64 nsym | u8 len[256] |
+// u32 off[nchunks+1] | u32 words[]); kThreads chunks per workgroup
+struct DecodeJob {
+    const uint8_t* payload;
+    uint8_t* out;           // S decoded bytes
+    uint64_t S;
+    uint32_t nchunks, chunk, lmax;
+    uint32_t wg_base;       // first workgroup of this job in the launch
+};
+hipError_t launch_huf_decode_batch(const DecodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
+                                   hipStream_t s);
 // RLE decode: payload u32 nruns | u32 wbytes | symbols[nruns] | u32 lengths[nruns]
 hipError_t launch_rle_decode(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
                              uint8_t* g, uint32_t* temp, hipStream_t s);
 
 // ---- launchers (k_retrieve.hip) ----
 struct ReconJob {
-    const uint32_t* rows[kMaxRows];  // row pointers (row 0 = sign, 1+p = plane p), by value
+    const uint32_t* rows[kMaxRows];  // row pointers (row 0 = sign, 1+p = plane p)
     void* out;
     uint64_t n;
     uint32_t nbd, B, k;
     int32_t e;
+    uint32_t wg_base;  // first workgroup of this job in the launch
+    uint32_t vec;      // out is 16-byte aligned
 };
-hipError_t launch_reconstruct(const ReconJob& job, bool f64, hipStream_t s);
-// out must hold 0 before the first call; each call folds one level in (max of bit patterns)
-hipError_t launch_qoi_vtotal(const void* x, const void* y, const void* z, uint64_t n, bool f64,
-                             const double eps[3], unsigned long long* out, hipStream_t s);
+// reconstruction of many levels (one dtype) in one launch; kThreads blocks per workgroup
+hipError_t launch_reconstruct_batch(const ReconJob* jobs, const uint32_t* wg_job, uint32_t grid,
+                                   bool f64, hipStream_t s);
+// V_total estimate of many (request, level) jobs of one dtype; acc must hold 0 first
+struct QoiJob {
+    const void* x;
+    const void* y;
+    const void* z;
+    uint64_t n;
+    double eps[3];
+    unsigned long long* acc;  // max of the estimate's bit patterns (non-negative doubles)
+    uint32_t wg_base, grid;   // this job's workgroups in the launch
+};
+hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
+                                   hipStream_t s);
 
 }  // namespace mdr

@@ -106,3 +106,29 @@ def test_batch_rejects_nonfinite(mdr, ctx):
         mdr.refactor_batch(ctx, [upload(good), upload(bad)], 32)
     assert ei.value.status == mdr.MDR_ERR_INVALID_ARG
     assert "variable 1" in str(ei.value)
+
+
+def test_retrieve_batch_matches_oracle(mdr, ctx):
+    """Batched retrieval (each variable its own tolerance, two rounds to check
+    incremental state) equals the oracle's retrieval of each variable."""
+    vs = _mixed_vars(49, np.float32, nvars=5)
+    vs.append([a.astype(np.float64) for a in _mixed_vars(50, np.float32, nvars=1)[0]])  # one f64 variable
+    p = mdr.default_params()
+    op = to_oracle_params(p)
+    rs = [mdr.refactor(ctx, upload(v), 32 if v[0].dtype == np.float32 else 52, p) for v in vs]
+    orc = [oracle.refactor(v, 32 if v[0].dtype == np.float32 else 52, op) for v in vs]
+    rts = [mdr.Retriever(ctx, r) for r in rs]
+    outs = [gpu_outputs(v) for v in vs]
+    k_prev = [None] * len(vs)
+    rounds = [[10 ** -(1 + i) for i in range(len(vs))], [10 ** -(4 + i % 3) for i in range(len(vs))]]
+    for rnd, tols in enumerate(rounds):
+        say("retrieve batch round", rnd, "tols", tols)
+        infos = mdr.retrieve_batch(rts, tols, outs)
+        for i, v in enumerate(vs):
+            vals, k, bound, met = oracle.retrieve_to(orc[i], tols[i], k_in=k_prev[i])
+            assert rts[i].planes() == list(k), (i, rts[i].planes(), k)
+            assert infos[i]["bound"] == bound and infos[i]["met"] == int(met)
+            got = np.concatenate([host(o).astype(np.float64) for o in outs[i]])
+            ref = np.concatenate([np.asarray(a, np.float64) for a in vals])
+            assert_same_bits(got, ref, ("var", i, "round", rnd))
+            k_prev[i] = k
