@@ -250,6 +250,41 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
                                    void* const* out_x, void* const* out_y, void* const* out_z,
                                    void* stream, mdr_qoi_info* info);
 
+/* ---------------------------------------------------------------- chunked pipeline */
+/*
+ * A field held in host memory as nchunks chunks, each an independent
+ * sub-domain of nlevels levels (sizes level_sizes[], coarsest first; chunk c's
+ * values at host + c * chunk_values, levels concatenated).  Refactor: the H2D
+ * copy of chunk c+1, the refactor of chunk c and the D2H copy of chunk c-1's
+ * streams overlap on three streams (overlap = 0: one stage at a time, the
+ * unpipelined reference); the streams stay in the pipeline's pinned host
+ * memory.  Retrieve: the H2D copy of chunk c+1's streams, the decode and
+ * reconstruction of chunk c and the D2H copy of chunk c-1's values overlap
+ * likewise; every chunk is planned to the same absolute tolerance (MDR_REL:
+ * tol x the whole field's value range).  Each chunk's result equals
+ * mdr_refactor / mdr_retrieve of that chunk alone, bit for bit.  host_values /
+ * host_out should be pinned (hipHostMalloc) for the copies to overlap.
+ */
+typedef struct mdr_pipeline mdr_pipeline;
+typedef struct {
+    double wall_ms;                     /* whole call, host clock                               */
+    double h2d_ms, compute_ms, d2h_ms;  /* summed device time of each stream's work (events)   */
+    uint64_t h2d_bytes, d2h_bytes;      /* bytes copied each way                                 */
+    uint64_t stream_bytes;              /* refactor: stream bytes made; retrieve: bytes decoded */
+} mdr_pipeline_info;
+
+mdr_status mdr_pipeline_create(mdr_context* ctx, uint32_t nchunks, const uint64_t* level_sizes,
+                               uint32_t nlevels, mdr_dtype dtype, uint32_t nplanes,
+                               const mdr_codec_params* params, mdr_pipeline** out);
+mdr_status mdr_pipeline_refactor(mdr_pipeline* p, const void* host_values, int overlap,
+                                 mdr_pipeline_info* info);
+mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, void* host_out,
+                                 int overlap, mdr_pipeline_info* info);
+/* A device copy of one refactored chunk (for inspection or serialization). */
+mdr_status mdr_pipeline_chunk(const mdr_pipeline* p, uint32_t chunk, mdr_context* ctx,
+                              mdr_refactored** out);
+void mdr_pipeline_destroy(mdr_pipeline* p);
+
 /* ---------------------------------------------------------------- serving */
 /*
  * A retrieval server keeps refactored fields resident in HBM and serves

@@ -92,6 +92,15 @@ class mdr_server_info(C.Structure):
                 ("hbm_in_use", C.c_uint64), ("hbm_budget", C.c_uint64)]
 
 
+class mdr_pipeline_info(C.Structure):
+    _fields_ = [("wall_ms", C.c_double), ("h2d_ms", C.c_double), ("compute_ms", C.c_double),
+                ("d2h_ms", C.c_double), ("h2d_bytes", C.c_uint64), ("d2h_bytes", C.c_uint64),
+                ("stream_bytes", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 MDR_REQ_FIELD, MDR_REQ_QOI_VTOTAL = 0, 1
 
 _vp, _u32, _u64, _i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
@@ -125,6 +134,12 @@ _SIGS = {
                             _P(mdr_retrieve_info)], C.c_int),
     "mdr_retrieve_qoi_vtotal": ([_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _P(_vp), _P(_vp),
                                  _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
+    "mdr_pipeline_create": ([_vp, _u32, _P(_u64), _u32, C.c_int, _u32, _P(mdr_codec_params), _P(_vp)],
+                            C.c_int),
+    "mdr_pipeline_refactor": ([_vp, _vp, C.c_int, _P(mdr_pipeline_info)], C.c_int),
+    "mdr_pipeline_retrieve": ([_vp, C.c_int, C.c_double, _vp, C.c_int, _P(mdr_pipeline_info)], C.c_int),
+    "mdr_pipeline_chunk": ([_vp, _u32, _vp, _P(_vp)], C.c_int),
+    "mdr_pipeline_destroy": ([_vp], None),
     "mdr_server_create": ([_vp, _u64, _u32, _P(_vp)], C.c_int),
     "mdr_server_add_field": ([_vp, _vp, _P(_u32)], C.c_int),
     "mdr_server_submit": ([_vp, _P(mdr_request), _P(_u64)], C.c_int),
@@ -462,3 +477,44 @@ class Server:
         i = mdr_server_info()
         _check(_lib.mdr_server_stats(self.handle, C.byref(i)))
         return {f: getattr(i, f) for f, _ in i._fields_ if f != "pad"}
+
+
+class Pipeline:
+    """Chunked H2D / refactor / D2H pipeline over a field in host memory (mdr_pipeline)."""
+
+    def __init__(self, ctx: Context, nchunks: int, level_sizes, dtype, nplanes: int,
+                 params: mdr_codec_params | None = None):
+        import torch
+        dt = MDR_F64 if dtype in (torch.float64, "f64") else MDR_F32
+        sz = (_u64 * len(level_sizes))(*[int(n) for n in level_sizes])
+        h = _vp()
+        _check(_lib.mdr_pipeline_create(ctx.handle, int(nchunks), sz, len(level_sizes), dt, int(nplanes),
+                                        C.byref(params) if params is not None else None, C.byref(h)))
+        self.ctx, self.handle = ctx, h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.mdr_pipeline_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    def refactor(self, host_values, overlap: bool = True) -> dict:
+        """host_values: a (pinned) CPU tensor holding every chunk, levels concatenated."""
+        info = mdr_pipeline_info()
+        _check(_lib.mdr_pipeline_refactor(self.handle, C.c_void_p(host_values.data_ptr()),
+                                          1 if overlap else 0, C.byref(info)))
+        return info.as_dict()
+
+    def retrieve(self, tol: float, host_out, relative: bool = True, overlap: bool = True) -> dict:
+        info = mdr_pipeline_info()
+        _check(_lib.mdr_pipeline_retrieve(self.handle, MDR_REL if relative else MDR_ABS, float(tol),
+                                          C.c_void_p(host_out.data_ptr()), 1 if overlap else 0,
+                                          C.byref(info)))
+        return info.as_dict()
+
+    def chunk(self, c: int) -> Refactored:
+        h = _vp()
+        _check(_lib.mdr_pipeline_chunk(self.handle, int(c), self.ctx.handle, C.byref(h)))
+        return Refactored(self.ctx, h)
