@@ -94,10 +94,25 @@ def cpu_baseline(w, sample: int):
         vals, k, bound, met = oracle.retrieve_to(lv, tol, k_in=k)
     t = time.perf_counter() - t0
     nbytes = x.nbytes * (1 + len(w["tols"]))
-    return {"value": nbytes / t / 1e9, "unit": "GB/s", "cores": oracle.get_threads(),
+    cores = oracle.get_threads()
+    # the same work on one thread, over a quarter of the sample
+    x1 = x[: max(1, x.size // 4)]
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        lv = oracle.refactor([x1], w["B"], p)
+        k = None
+        for tol in w["tols"]:
+            vals, k, bound, met = oracle.retrieve_to(lv, tol, k_in=k)
+        t1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
+    return {"value": nbytes / t / 1e9, "unit": "GB/s", "cores": cores,
             "kind": "oracle", "seconds": t,
+            "single_thread_value": x1.nbytes * (1 + len(w["tols"])) / t1 / 1e9,
             "sample": "first %d values of the finest level (%.1f MiB): refactor + %d "
-                      "incremental retrievals" % (x.size, x.nbytes / 2 ** 20, len(w["tols"]))}
+                      "incremental retrievals (single thread: first %d values)"
+                      % (x.size, x.nbytes / 2 ** 20, len(w["tols"]), x1.size)}
 
 
 def progress(*a):
@@ -465,6 +480,14 @@ def main():
     ref = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
     ref_copy = ref.clone()
     torch.cuda.synchronize()
+    # measured device-to-device copy bandwidth (read + write): the practical ceiling
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        ref_copy.copy_(ref)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * ref.numel() * 10 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
     del ref, ref_copy
 
     ms_step = elapsed / args.steps * 1e3
@@ -522,6 +545,7 @@ def main():
                      "encoder_sha": encoder_hash(),
                      "kernel": "k_encode", "launches_per_step": enc_launches_per_step,
                      "algorithmic_bytes_per_step": enc_bytes_per_step},
+        "copy_gbps": copy_gbps,
         "reconstruct_kernel_gbps": ((nbytes * len(w["tols"]) * args.steps) / (rec_ms / 1e3) / 1e9
                                     if rec_ms else None),
     }

@@ -7,6 +7,21 @@
 
 namespace mdr {
 
+// Pointers taken from job tables are generic; casting them to the global
+// address space lets the compiler use global (not flat) loads and stores, which
+// do not share a wait counter with LDS traffic.
+// 16-byte vectors for global loads / stores through such pointers (the HIP
+// vector classes cannot be copied out of another address space)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // In-register transpose of a 32x32 bit matrix: afterwards bit r of a[c] is the
 // former bit c of a[r].  Five butterfly stages swap the off-diagonal blocks of
 // size 16, 8, 4, 2, 1 (each output word is one bit-field insert).

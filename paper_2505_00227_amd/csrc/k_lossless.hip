@@ -1,6 +1,7 @@
 // Lossless kernels for gfx950 (Sec. 4.1): device-wide exclusive scan, chunked
 // canonical Huffman coding of byte symbols, and run-length coding of W-bit
 // plane words.  Direct copy needs no kernel: its payload is the plane rows.
+#include "device_bits.hpp"
 #include "mdr_internal.hpp"
 
 namespace mdr {
@@ -181,13 +182,13 @@ __global__ __launch_bounds__(kThreads) void k_huf_count(const LosslessArgs* __re
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             cached = u;
         }
-        const uint8_t* g = reinterpret_cast<const uint8_t*>(unit_rows(A, u));
+        const auto g = gmem(unit_rows(A, u));
         const uint64_t S = A.units[u].S;
         const uint64_t lo = (uint64_t)(c - A.chunk_base[u]) * chunk + (uint64_t)lane * per;
         uint32_t bits = 0;
         for (uint32_t q = 0; q < per; q += 4) {
             if (lo + q >= S) break;
-            uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
+            uint32_t w = g[(lo + q) / 4];
             bits += L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
         }
 #pragma unroll
@@ -390,22 +391,22 @@ __global__ __launch_bounds__(kThreads) void k_huf_write(const LosslessArgs* __re
         const uint64_t S = ui.S;
         const uint32_t nch = ui.nchunks, first = A.chunk_base[u], lc = c - first;
         uint8_t* pay = A.arena + A.pay_off[u];
-        uint32_t* off = reinterpret_cast<uint32_t*>(pay + kHufHeader);
-        uint32_t* words = off + nch + 1;
+        const auto off = gmem(reinterpret_cast<uint32_t*>(pay + kHufHeader));
+        const auto words = off + nch + 1;
         const uint32_t base = A.chunk_words[first];
         const uint32_t w0 = A.chunk_words[c] - base, nw = A.chunk_words[c + 1] - A.chunk_words[c];
-        const uint8_t* g = reinterpret_cast<const uint8_t*>(unit_rows(A, u));
+        const auto g = gmem(unit_rows(A, u));
         const uint64_t lo = (uint64_t)lc * chunk + (uint64_t)lane * per;
         uint32_t bits = 0;
         for (uint32_t q = 0; q < per; q += 4) {
             if (lo + q >= S) break;
-            uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
+            uint32_t w = g[(lo + q) / 4];
             bits += L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
         }
         uint32_t pos = wave_incl_scan(bits, lane) - bits;
         for (uint32_t q = 0; q < per; q += 4) {
             if (lo + q >= S) break;
-            uint32_t w = *reinterpret_cast<const uint32_t*>(g + lo + q);
+            uint32_t w = g[(lo + q) / 4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const uint32_t sym = (w >> (8 * b)) & 0xFF;
@@ -546,8 +547,8 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     __syncthreads();
     const uint32_t c = (blockIdx.x - job.wg_base) * kThreads + tid;
     if (c >= nchunks) return;
-    const uint32_t* off = reinterpret_cast<const uint32_t*>(payload + kHufHeader);
-    const uint32_t* words = reinterpret_cast<const uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1));
+    const auto off = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader));
+    const auto words = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1)));
     uint32_t wp = off[c];
     const uint32_t wend = off[c + 1];
     // four compressed words in flight: a refill consumes the oldest and issues
@@ -559,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     int nb = 0;
     const uint64_t lo = (uint64_t)c * chunk;
     const uint64_t cnt = (lo + chunk <= S) ? chunk : S - lo;
-    uint32_t* dst = reinterpret_cast<uint32_t*>(g + lo);
+    const auto dst = gmem(reinterpret_cast<uint32_t*>(g + lo));
     for (uint64_t i = 0; i < cnt; i += 4) {
         uint32_t out = 0;
 #pragma unroll

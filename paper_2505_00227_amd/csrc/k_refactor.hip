@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
     using U = typename StatAcc<F64>::U;
     constexpr int PER = 16 / sizeof(U);  // values per 16-byte vector
     const StatsJob& job = jobs[wg_job[blockIdx.x]];
-    const U* x = static_cast<const U*>(job.x);
+    const auto x = gmem(static_cast<const U*>(job.x));
     const uint64_t n = job.n;
     LevelStats* st = job.stats;
     StatAcc<F64> acc;
@@ -134,9 +134,9 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
     uint64_t done = 0;
     if (VEC) {
         const uint64_t nvec = n / PER;
-        const uint4* xv4 = reinterpret_cast<const uint4*>(x);
+        const auto xv4 = gmem(reinterpret_cast<const u32x4*>(job.x));
         for (uint64_t i = tid0; i < nvec; i += stride) {
-            uint4 q = xv4[i];
+            const u32x4 q = xv4[i];
             if constexpr (F64) {
                 acc.add(((uint64_t)q.y << 32) | q.x);
                 acc.add(((uint64_t)q.w << 32) | q.z);
@@ -219,11 +219,24 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     __shared__ unsigned long long s_key64[F64 ? kKeyStride : 1];
     __shared__ uint32_t s_zero[kThreads];  // sink for zero bytes (one slot per thread)
 
-    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ uint32_t s_hoff[kMaxRows];  // row -> its unit's histogram offset
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
+    // every field the tile loop needs, in registers: stores through the row
+    // pointer could otherwise alias the job table and force reloads
     const uint32_t B = job.B, nbd = job.nbd, m = job.m, nunits = job.nunits;
+    const uint32_t ntiles = job.ntiles, tpw = job.tiles_per_wg;
     const uint64_t n = job.n;
-    const int e = job.stats->emax == INT_MIN ? 0 : job.stats->emax;
-    const T* x = static_cast<const T*>(job.x);
+    const int emax = job.stats->emax;
+    const int e = emax == INT_MIN ? 0 : emax;
+    const T* xg = static_cast<const T*>(job.x);
+    const auto x = gmem(xg);
+    const auto rows = gmem(job.rows);
+    const auto recs = gmem(job.recs);
+    const auto key_part = gmem(job.key_part);
+    const auto hist = gmem(job.hist);
+    const auto trans_part = gmem(job.trans_part);
+    if (tid < kMaxRows) s_hoff[tid] = job.hist_off[tid];
+    (void)m;
     uint32_t* s_hist = s_dyn;
     uint32_t* s_pl = s_dyn + nunits * 256;           // [B+1][256]
     float* s_y = reinterpret_cast<float*>(s_pl);     // [256][36] (reuses the plane space)
@@ -240,8 +253,8 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     float frac_max = 0.0f;  // f32: max fract(y) = the k = B key
     T small = 0;
 
-    const uint32_t t0 = wg * job.tiles_per_wg;
-    const uint32_t t1 = min(job.ntiles, t0 + job.tiles_per_wg);
+    const uint32_t t0 = wg * tpw;
+    const uint32_t t1 = min(ntiles, t0 + tpw);
     const uint32_t last_blk = min(nbd, t1 * kTileBlocks) - 1;
 
     for (uint32_t t = t0; t < t1; ++t) {
@@ -254,18 +267,18 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         T v[32];
         if (VEC && valid && base + 32 <= n) {
             if constexpr (F64) {
-                const double2* p = reinterpret_cast<const double2*>(x + base);
+                const auto p = gmem(reinterpret_cast<const f64x2*>(xg + base));
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    double2 q = p[j];
+                    const f64x2 q = p[j];
                     v[2 * j] = q.x;
                     v[2 * j + 1] = q.y;
                 }
             } else {
-                const float4* p = reinterpret_cast<const float4*>(x + base);
+                const auto p = gmem(reinterpret_cast<const f32x4*>(xg + base));
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    float4 q = p[j];
+                    const f32x4 q = p[j];
                     v[4 * j] = q.x;
                     v[4 * j + 1] = q.y;
                     v[4 * j + 2] = q.z;
@@ -419,8 +432,8 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 const uint32_t r = r0 + i;
                 if (r > B) break;
                 if (valid) {
-                    job.rows[(uint64_t)r * nbd + blk] = w[i];
-                    uint32_t* h = s_hist + job.hist_off[r];
+                    rows[(uint64_t)r * nbd + blk] = w[i];
+                    uint32_t* h = s_hist + s_hoff[r];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const uint32_t byte = (w[i] >> (8 * q)) & 0xFFu;
@@ -436,10 +449,10 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         // first / last words of this workgroup's range, for the boundaries
         if (t == t0 && tid < G)
             for (uint32_t r = 0; r <= B; ++r)
-                job.recs[((uint64_t)wg * kMaxRows + r) * 2 * G + tid] = s_pl[r * kTileBlocks + tid];
+                recs[((uint64_t)wg * kMaxRows + r) * 2 * G + tid] = s_pl[r * kTileBlocks + tid];
         if (valid && blk + G > last_blk)
             for (uint32_t r = 0; r <= B; ++r)
-                job.recs[((uint64_t)wg * kMaxRows + r) * 2 * G + G + (blk - (last_blk + 1 - G))] =
+                recs[((uint64_t)wg * kMaxRows + r) * 2 * G + G + (blk - (last_blk + 1 - G))] =
                     s_pl[r * kTileBlocks + tid];
         __syncthreads();
         if (tid >= kTileBlocks - G)
@@ -459,16 +472,16 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         }
     }
     __syncthreads();
-    unsigned long long* kp = job.key_part + (uint64_t)wg * kKeyStride;
+    const auto kp = key_part + (uint64_t)wg * kKeyStride;
     if (tid < kKeyStride) {
         if constexpr (F64)
             kp[tid] = s_key64[tid];
         else
             kp[tid] = s_key32[tid];
     }
-    uint32_t* gh = job.hist + (uint64_t)wg * nunits * 256;
+    const auto gh = hist + (uint64_t)wg * nunits * 256;
     for (uint32_t i = tid; i < nunits * 256; i += kThreads) gh[i] = s_hist[i];
-    if (tid < kMaxRows) job.trans_part[(uint64_t)wg * kMaxRows + tid] = s_trans[tid];
+    if (tid < kMaxRows) trans_part[(uint64_t)wg * kMaxRows + tid] = s_trans[tid];
 }
 
 // f32 fits three waves per SIMD without spilling; f64 keeps the default budget
@@ -553,17 +566,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
     // sums four adjacent bins with 16-byte loads, two loads in flight
     {
         const uint32_t q4 = tid & 63, slice = tid >> 6;
-        const uint4* h = reinterpret_cast<const uint4*>(lv.hist + (uint64_t)u * 256) + q4;
+        const auto h = gmem(reinterpret_cast<const u32x4*>(lv.hist + (uint64_t)u * 256) + q4);
         const uint64_t rowstride = (uint64_t)nunits * 256 / 4;
-        uint4 a = make_uint4(0, 0, 0, 0), b = make_uint4(0, 0, 0, 0);
+        u32x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
         uint32_t w = slice;
         for (; w + 16 < grid; w += 32) {
-            uint4 p0 = h[(uint64_t)w * rowstride], p1 = h[(uint64_t)(w + 16) * rowstride];
+            const u32x4 p0 = h[(uint64_t)w * rowstride], p1 = h[(uint64_t)(w + 16) * rowstride];
             a.x += p0.x, a.y += p0.y, a.z += p0.z, a.w += p0.w;
             b.x += p1.x, b.y += p1.y, b.z += p1.z, b.w += p1.w;
         }
         for (; w < grid; w += 16) {
-            uint4 p0 = h[(uint64_t)w * rowstride];
+            const u32x4 p0 = h[(uint64_t)w * rowstride];
             a.x += p0.x, a.y += p0.y, a.z += p0.z, a.w += p0.w;
         }
         s_part[slice][4 * q4 + 0] = a.x + b.x;

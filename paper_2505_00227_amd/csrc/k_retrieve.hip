@@ -20,34 +20,50 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
                                                           const uint32_t* __restrict__ wg_job)
 {
     using T = std::conditional_t<F64, double, float>;
+    // the job's row pointers, staged once per workgroup (uniform LDS reads
+    // afterwards instead of one dependent scalar load per row)
+    __shared__ const uint32_t* s_rows[kMaxRows];
     const ReconJob& j = jobs[wg_job[blockIdx.x]];
+    if (threadIdx.x < kMaxRows) s_rows[threadIdx.x] = j.rows[threadIdx.x];
+    const uint32_t nbd = j.nbd, B = j.B, k = j.k, vec = j.vec;
+    const uint64_t n = j.n;
+    const int e = j.e;
+    __syncthreads();
     const uint32_t blk = (blockIdx.x - j.wg_base) * kThreads + threadIdx.x;
-    if (blk >= j.nbd) return;
+    if (blk >= nbd) return;
     const uint64_t base = (uint64_t)blk * 32;
-    if (base >= j.n) return;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(32, j.n - base);
-    T* out = static_cast<T*>(j.out) + base;
+    if (base >= n) return;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(32, n - base);
+    T* outg = static_cast<T*>(j.out) + base;
+    const auto out = gmem(outg);
     T v[32];
-    if (j.k == 0) {
+    if (k == 0) {
 #pragma unroll
         for (int t = 0; t < 32; ++t) v[t] = T(0);
     } else {
-        const uint32_t B = j.B, k = j.k;
-        const uint32_t sgn = j.rows[0][blk];
+        const uint32_t sgn = gmem(s_rows[0])[blk];
         uint32_t lo[32];
         uint32_t hi[F64 ? 32 : 1];
         // bit c lives in plane p = B-1-c, present when p < k, i.e. c >= B-k
+        // branch-free: rows that are not held read the sign row again (a cache
+        // hit) and are masked, so every load can be in flight at once
 #pragma unroll
-        for (int c = 0; c < 32; ++c)
-            lo[c] = (c < (int)B && c >= (int)(B - k)) ? j.rows[B - c][blk] : 0u;
+        for (int c = 0; c < 32; ++c) {
+            const bool held = c < (int)B && c >= (int)(B - k);
+            const uint32_t w = gmem(s_rows[held ? B - c : 0])[blk];
+            lo[c] = held ? w : 0u;
+        }
         transpose32(lo);
         if constexpr (F64) {
 #pragma unroll
-            for (int c = 0; c < 32; ++c)
-                hi[c] = (32 + c < (int)B && 32 + c >= (int)(B - k)) ? j.rows[B - 32 - c][blk] : 0u;
+            for (int c = 0; c < 32; ++c) {
+                const bool held = 32 + c < (int)B && 32 + c >= (int)(B - k);
+                const uint32_t w = gmem(s_rows[held ? B - 32 - c : 0])[blk];
+                hi[c] = held ? w : 0u;
+            }
             transpose32(hi);
         }
-        const int sh = j.e - (int)B;
+        const int sh = e - (int)B;
 #pragma unroll
         for (int t = 0; t < 32; ++t) {
             T mag;
@@ -60,15 +76,15 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
             v[t] = ((sgn >> t) & 1u) ? -a : a;
         }
     }
-    if (j.vec && cnt == 32) {
+    if (vec && cnt == 32) {
         if constexpr (F64) {
-            double2* p = reinterpret_cast<double2*>(out);
+            const auto p = gmem(reinterpret_cast<f64x2*>(outg));
 #pragma unroll
-            for (int q = 0; q < 16; ++q) p[q] = make_double2(v[2 * q], v[2 * q + 1]);
+            for (int q = 0; q < 16; ++q) p[q] = f64x2{v[2 * q], v[2 * q + 1]};
         } else {
-            float4* p = reinterpret_cast<float4*>(out);
+            const auto p = gmem(reinterpret_cast<f32x4*>(outg));
 #pragma unroll
-            for (int q = 0; q < 8; ++q) p[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            for (int q = 0; q < 8; ++q) p[q] = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
         }
     } else {
 #pragma unroll
@@ -89,9 +105,9 @@ __global__ __launch_bounds__(kThreads) void k_qoi_vtotal_batch(const QoiJob* __r
 {
     using T = std::conditional_t<F64, double, float>;
     const QoiJob& j = jobs[wg_job[blockIdx.x]];
-    const T* x = static_cast<const T*>(j.x);
-    const T* y = static_cast<const T*>(j.y);
-    const T* z = static_cast<const T*>(j.z);
+    const auto x = gmem(static_cast<const T*>(j.x));
+    const auto y = gmem(static_cast<const T*>(j.y));
+    const auto z = gmem(static_cast<const T*>(j.z));
     const double ex = j.eps[0], ey = j.eps[1], ez = j.eps[2];
     double worst = 0.0;
     const uint64_t stride = (uint64_t)j.grid * blockDim.x;
