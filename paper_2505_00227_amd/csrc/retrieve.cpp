@@ -78,8 +78,18 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
             if (tasks[u].rt == tasks[t].rt) return fail(MDR_ERR_INVALID_ARG, "a retriever appears twice in one batch");
         if (tasks[t].rt->ctx->device != ctx->device)
             return fail(MDR_ERR_INVALID_ARG, "retrievers on different devices");
-        for (size_t l = 0; l < r->levels.size(); ++l)
-            if (r->levels[l].n && !tasks[t].out[l])
+        if (tasks[t].reconstruct) {  // decode-only tasks have no outputs
+            if (!tasks[t].out) return fail(MDR_ERR_INVALID_ARG, "level_out is NULL");
+            for (size_t l = 0; l < r->levels.size(); ++l)
+                if (r->levels[l].n && !tasks[t].out[l])
+                    return fail(MDR_ERR_INVALID_ARG, "level_out[" + std::to_string(l) + "] is NULL");
+        }
+    }
+    for (size_t i = 0; i < nextra; ++i) {
+        if (!extra[i].rt || !extra[i].out || extra[i].k.size() != extra[i].rt->r->levels.size())
+            return fail(MDR_ERR_INVALID_ARG, "bad reconstruction request");
+        for (size_t l = 0; l < extra[i].k.size(); ++l)
+            if (extra[i].rt->r->levels[l].n && !extra[i].out[l])
                 return fail(MDR_ERR_INVALID_ARG, "level_out[" + std::to_string(l) + "] is NULL");
     }
 
