@@ -496,8 +496,11 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
 }
 
 // ------------------------------------------------------------------ Huffman decode
-// One thread per chunk; a 2^lmax-entry table in LDS maps the next lmax bits to
-// (symbol, length).
+// One thread per chunk.  A 2^lmax-entry table in LDS maps the next lmax bits
+// to up to four symbols: every code that lies wholly inside the window is
+// decoded by one lookup (codes are prefix-free, so the bits after a whole code
+// do not change it).  Skewed groups, whose frequent symbols have 1-3 bit codes,
+// take a quarter of the dependent lookups of a one-symbol table.
 __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
                                                          const uint32_t* __restrict__ wg_job)
 {
@@ -506,7 +509,8 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     const uint64_t S = job.S;
     const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
     uint8_t* g = job.out;
-    __shared__ uint16_t s_lut[1 << kLutBitsMax];
+    __shared__ uint16_t s_lut[1 << kLutBitsMax];             // (length << 8) | symbol
+    __shared__ unsigned long long s_multi[1 << kLutBitsMax];  // symbols | count << 32 | bits << 35
     __shared__ uint8_t s_len[256];
     __shared__ uint32_t s_count[33], s_first[33], s_offset[33];
     __shared__ uint8_t s_sorted[256];
@@ -533,7 +537,8 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
         s_sorted[s_offset[L] + before] = (uint8_t)tid;
     }
     __syncthreads();
-    for (uint32_t i = tid; i < (1u << lmax); i += kThreads) {
+    const uint32_t nent = 1u << lmax, mask = nent - 1;
+    for (uint32_t i = tid; i < nent; i += kThreads) {
         uint16_t ent = (uint16_t)(lmax << 8);  // invalid prefix: consume lmax bits
         for (uint32_t l = 1; l <= lmax; ++l) {
             uint32_t p = i >> (lmax - l);
@@ -543,6 +548,19 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
             }
         }
         s_lut[i] = ent;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nent; i += kThreads) {
+        uint32_t syms = 0, k = 0, used = 0;
+        while (k < 4) {
+            const uint32_t e = s_lut[(i << used) & mask];
+            const uint32_t l = e >> 8;
+            if (used + l > lmax) break;  // the next code does not fit in the window
+            syms |= (e & 0xFFu) << (8 * k);
+            ++k;
+            used += l;
+        }
+        s_multi[i] = (unsigned long long)syms | ((unsigned long long)k << 32) | ((unsigned long long)used << 35);
     }
     __syncthreads();
     const uint32_t c = (blockIdx.x - job.wg_base) * kThreads + tid;
@@ -559,28 +577,34 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     uint64_t buf = 0;
     int nb = 0;
     const uint64_t lo = (uint64_t)c * chunk;
-    const uint64_t cnt = (lo + chunk <= S) ? chunk : S - lo;
+    const uint32_t cnt = (uint32_t)((lo + chunk <= S) ? chunk : S - lo);  // a multiple of 4
     const auto dst = gmem(reinterpret_cast<uint32_t*>(g + lo));
-    for (uint64_t i = 0; i < cnt; i += 4) {
-        uint32_t out = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            if (nb <= 32) {
-                buf |= (uint64_t)q0 << (32 - nb);
-                nb += 32;
-                q0 = q1;
-                q1 = q2;
-                q2 = q3;
-                q3 = fetch(wp);
-                ++wp;
-            }
-            uint32_t ent = s_lut[buf >> (64 - lmax)];
-            uint32_t l = ent >> 8;
-            out |= (ent & 0xFFu) << (8 * b);
-            buf <<= l;
-            nb -= (int)l;
+    uint64_t pend = 0;  // decoded bytes not yet stored (fewer than 4 between iterations)
+    uint32_t npend = 0, done = 0, wo = 0;
+    while (done < cnt) {
+        if (nb <= 32) {
+            buf |= (uint64_t)q0 << (32 - nb);
+            nb += 32;
+            q0 = q1;
+            q1 = q2;
+            q2 = q3;
+            q3 = fetch(wp);
+            ++wp;
         }
-        dst[i / 4] = out;
+        const unsigned long long e = s_multi[buf >> (64 - lmax)];
+        const uint32_t k = min((uint32_t)(e >> 32) & 7u, cnt - done);
+        const uint32_t used = (uint32_t)(e >> 35);
+        const uint64_t syms = (uint64_t)(uint32_t)e & (k == 4 ? 0xFFFFFFFFull : ((1ull << (8 * k)) - 1));
+        pend |= syms << (8 * npend);
+        npend += k;
+        done += k;
+        buf <<= used;
+        nb -= (int)used;
+        if (npend >= 4) {
+            dst[wo++] = (uint32_t)pend;
+            pend >>= 32;
+            npend -= 4;
+        }
     }
 }
 
