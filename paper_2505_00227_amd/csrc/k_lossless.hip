@@ -172,11 +172,14 @@ __global__ __launch_bounds__(kThreads) void k_huf_count(const LosslessArgs* __re
     const uint32_t total = A.counts[0];
     if (blockIdx.x == 0 && tid == 0) A.chunk_words[total] = 0;
     uint32_t* L = s_len[wave];
-    uint32_t cached = 0xFFFFFFFFu;
+    uint32_t cached = 0xFFFFFFFFu, cb_lo = 1, cb_hi = 0;  // chunks [cb_lo, cb_hi) belong to `cached`
     const uint32_t chunk = A.huf_chunk, per = chunk / 64;
     for (uint32_t c = blockIdx.x * (kThreads / 64) + wave; c < total; c += gridDim.x * (kThreads / 64)) {
-        const uint32_t u = find_unit(A.chunk_base, A.U, c);
-        if (u != cached) {
+        uint32_t u = cached;
+        if (c < cb_lo || c >= cb_hi) {
+            u = find_unit(A.chunk_base, A.U, c);
+            cb_lo = A.chunk_base[u];
+            cb_hi = A.chunk_base[u + 1];
             for (uint32_t k = lane; k < 256; k += 64) L[k] = A.lens[(uint64_t)u * 256 + k];
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_count(const LosslessArgs* __re
         }
         const auto g = gmem(unit_rows(A, u));
         const uint64_t S = A.units[u].S;
-        const uint64_t lo = (uint64_t)(c - A.chunk_base[u]) * chunk + (uint64_t)lane * per;
+        const uint64_t lo = (uint64_t)(c - cb_lo) * chunk + (uint64_t)lane * per;
         uint32_t bits = 0;
         for (uint32_t q = 0; q < per; q += 4) {
             if (lo + q >= S) break;
@@ -213,11 +216,16 @@ __global__ __launch_bounds__(kThreads) void k_rle_count(const LosslessArgs* __re
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = A.counts[1];
     if (blockIdx.x == 0 && tid == 0) A.tile_runs[total] = 0;
+    uint32_t u = 0, tb_lo = 1, tb_hi = 0;  // tiles [tb_lo, tb_hi) belong to unit u
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t u = find_unit(A.tile_base, A.U, t);
+        if (t < tb_lo || t >= tb_hi) {
+            u = find_unit(A.tile_base, A.U, t);
+            tb_lo = A.tile_base[u];
+            tb_hi = A.tile_base[u + 1];
+        }
         const uint32_t* g = unit_rows(A, u);
         const uint64_t nw = A.units[u].S / (4ull * A.G);
-        const uint64_t i0 = (uint64_t)(t - A.tile_base[u]) * kRleTileWords;
+        const uint64_t i0 = (uint64_t)(t - tb_lo) * kRleTileWords;
         const uint64_t i1 = min(nw, i0 + kRleTileWords);
         uint32_t cnt = 0;
         for (uint64_t i = i0 + tid; i < i1; i += kThreads) cnt += (i == 0 || word_ne(g, i, i - 1, A.G)) ? 1u : 0u;
@@ -372,11 +380,14 @@ __global__ __launch_bounds__(kThreads) void k_huf_write(const LosslessArgs* __re
     uint32_t* buf = s_buf + wave * buf_words;
     uint32_t* L = s_len[wave];
     uint32_t* C = s_code[wave];
-    uint32_t cached = 0xFFFFFFFFu;
+    uint32_t cached = 0xFFFFFFFFu, cb_lo = 1, cb_hi = 0;
     const uint32_t chunk = A.huf_chunk, per = chunk / 64;
     for (uint32_t c = blockIdx.x * (kThreads / 64) + wave; c < total; c += gridDim.x * (kThreads / 64)) {
-        const uint32_t u = find_unit(A.chunk_base, A.U, c);
-        if (u != cached) {
+        uint32_t u = cached;
+        if (c < cb_lo || c >= cb_hi) {
+            u = find_unit(A.chunk_base, A.U, c);
+            cb_lo = A.chunk_base[u];
+            cb_hi = A.chunk_base[u + 1];
             for (uint32_t k = lane; k < 256; k += 64) {
                 L[k] = A.lens[(uint64_t)u * 256 + k];
                 C[k] = A.codes[(uint64_t)u * 256 + k];
@@ -389,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_write(const LosslessArgs* __re
 
         const UnitInfo& ui = A.units[u];
         const uint64_t S = ui.S;
-        const uint32_t nch = ui.nchunks, first = A.chunk_base[u], lc = c - first;
+        const uint32_t nch = ui.nchunks, first = cb_lo, lc = c - first;
         uint8_t* pay = A.arena + A.pay_off[u];
         const auto off = gmem(reinterpret_cast<uint32_t*>(pay + kHufHeader));
         const auto words = off + nch + 1;
@@ -451,15 +462,20 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
     if (A.counts[2]) return;
     const uint32_t tid = threadIdx.x;
     const uint32_t total = A.counts[1], G = A.G;
+    uint32_t u = 0, tb_lo = 1, tb_hi = 0;  // tiles [tb_lo, tb_hi) belong to unit u
     for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const uint32_t u = find_unit(A.tile_base, A.U, t);
+        if (t < tb_lo || t >= tb_hi) {
+            u = find_unit(A.tile_base, A.U, t);
+            tb_lo = A.tile_base[u];
+            tb_hi = A.tile_base[u + 1];
+        }
         const UnitInfo& ui = A.units[u];
         const uint32_t* g = unit_rows(A, u);
         const uint64_t nw = ui.S / (4ull * G), nruns = ui.nruns;
         uint8_t* pay = A.arena + A.pay_off[u];
         uint32_t* sym = reinterpret_cast<uint32_t*>(pay + 8);
         uint32_t* lslot = reinterpret_cast<uint32_t*>(pay + 8 + 4ull * G * nruns);
-        const uint32_t lt = t - A.tile_base[u];
+        const uint32_t lt = t - tb_lo;
         const uint64_t i0 = (uint64_t)lt * kRleTileWords + (uint64_t)tid * kRlePer;
         uint32_t flags = 0, cnt = 0;
         for (int k = 0; k < kRlePer; ++k) {
@@ -470,7 +486,7 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
         }
         uint32_t excl;
         block_excl_scan(cnt, s_wave, excl);
-        uint64_t r = (uint64_t)(A.tile_runs[t] - A.tile_runs[A.tile_base[u]]) + excl;
+        uint64_t r = (uint64_t)(A.tile_runs[t] - A.tile_runs[tb_lo]) + excl;
         if (!LEN && lt == 0 && tid == 0) {
             reinterpret_cast<uint32_t*>(pay)[0] = (uint32_t)nruns;
             reinterpret_cast<uint32_t*>(pay)[1] = 4 * G;

@@ -135,6 +135,7 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
     if (VEC) {
         const uint64_t nvec = n / PER;
         const auto xv4 = gmem(reinterpret_cast<const u32x4*>(job.x));
+#pragma unroll 4
         for (uint64_t i = tid0; i < nvec; i += stride) {
             const u32x4 q = xv4[i];
             if constexpr (F64) {
@@ -521,6 +522,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
     __shared__ unsigned long long s_red[kSelThreads / 64];
     __shared__ int s_nl, s_maxlen;
     __shared__ uint32_t s_count[33], s_first[33];
+    __shared__ unsigned long long s_kmax[kKeyStride];
 
     const SelectLevel& lv = levels[blockIdx.y];
     const uint32_t u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -601,13 +603,17 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
     unsigned long long tr = 0;
     for (uint32_t i = tid; i < grid * nrow; i += kSelThreads)
         tr += lv.trans_part[(uint64_t)(i / nrow) * kMaxRows + r0 + i % nrow];
-    if (u == 0 && tid < kKeyStride && (tid <= B || tid == kKeyStride - 1)) {
-        unsigned long long kmax = 0;
-        for (uint32_t w = 0; w < grid; ++w) {
-            unsigned long long kv = lv.key_part[(uint64_t)w * kKeyStride + tid];
-            kmax = kv > kmax ? kv : kmax;
-        }
-        lv.keys[tid] = kmax;
+    if (u == 0) {
+        // error keys: maximum over the encoder's workgroups, every thread
+        // reading consecutive partials (the partials are [grid][kKeyStride])
+        if (tid < kKeyStride) s_kmax[tid] = 0;
+        __syncthreads();
+        const auto kp = gmem(lv.key_part);
+        const uint64_t total = (uint64_t)grid * kKeyStride;
+#pragma unroll 4
+        for (uint64_t i = tid; i < total; i += kSelThreads) atomicMax(&s_kmax[i % kKeyStride], kp[i]);
+        __syncthreads();
+        if (tid < kKeyStride && (tid <= B || tid == kKeyStride - 1)) lv.keys[tid] = s_kmax[tid];
     }
     for (uint32_t i = tid; i < (grid - 1) * nrow; i += kSelThreads) {
         uint32_t w = 1 + i / nrow, r = r0 + i % nrow;

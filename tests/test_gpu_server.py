@@ -73,12 +73,18 @@ def _collect(mdr, srv, q, c):
     return out
 
 
-def _wait(srv, want, timeout=60.0):
+def _wait(mdr, srv, reqs_by_ticket, want, timeout=60.0):
+    """Collect completions; each one's outputs are copied out and released at
+    once, as a client would, so the budget frees up for waiting requests."""
     got = {}
     t0 = time.time()
     while len(got) < want:
         for c in srv.poll():
-            got[c["ticket"]] = c
+            q = reqs_by_ticket[c["ticket"]]
+            outs = _collect(mdr, srv, q, c) if c["status"] == 0 else None
+            if c["status"] == 0:
+                srv.release(c["ticket"])
+            got[c["ticket"]] = (c, outs)
         st = srv.stats()
         assert st["hbm_in_use"] <= st["hbm_budget"]
         assert time.time() - t0 < timeout, ("server did not finish", len(got), want, st)
@@ -98,13 +104,12 @@ def test_alone_equals_mix_equals_oracle(mdr, setup):
     tickets = []
     for q in reqs:
         tickets.append(_submit(mdr, srv, q, tickets))
-    got = _wait(srv, len(reqs))
+    got = _wait(mdr, srv, dict(zip(tickets, reqs)), len(reqs))
     mix = []
     for q, t in zip(reqs, tickets):
-        c = got[t]
+        c, outs = got[t]
         assert c["status"] == 0, (q, c)
-        mix.append((c, _collect(mdr, srv, q, c)))
-        srv.release(t)
+        mix.append((c, outs))
     st = srv.stats()
     say("mix stats", st)
     assert st["step_requests"] > st["steps"], "requests were never batched together"
@@ -118,9 +123,8 @@ def test_alone_equals_mix_equals_oracle(mdr, setup):
     for i, q in enumerate(reqs):
         t = _submit(mdr, srv, q, tickets)
         tickets.append(t)
-        c = _wait(srv, 1)[t]
-        alone = _collect(mdr, srv, q, c)
-        srv.release(t)
+        c, alone = _wait(mdr, srv, {t: q}, 1)[t]
+        assert c["status"] == 0, (q, c)
         assert alone == mix[i][1], ("alone vs mix", i, q)
         for key in ("bound", "met", "iterations", "bytes_fetched"):
             assert c[key] == mix[i][0][key], ("alone vs mix", i, key, c[key], mix[i][0][key])
