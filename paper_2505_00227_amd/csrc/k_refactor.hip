@@ -205,7 +205,10 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
 // evaluated and folded in with an LDS max; the others cannot change the result.
 // Cuts whose maximum is still below 1 - 2^-12 ("weak") take the direct per-block
 // maximum.  Stale thresholds only add candidates, so the result is exact.
-template <bool F64, bool VEC>
+// FAST: f32 with 32 planes in groups of 4 (every row, its unit and its
+// histogram offset known at compile time): rows go from registers straight to
+// memory, neighbours come by lane shuffle, runs are counted per thread and unit.
+template <bool F64, bool VEC, bool FAST>
 __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t wg)
 {
     using T = std::conditional_t<F64, double, float>;
@@ -221,6 +224,10 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     __shared__ uint32_t s_zero[kThreads];  // sink for zero bytes (one slot per thread)
 
     __shared__ uint32_t s_hoff[kMaxRows];  // row -> its unit's histogram offset
+    __shared__ uint32_t s_edge[FAST ? 2 : 1][kThreads / 64][FAST ? 33 : 1];  // last lane's words per wave
+    uint32_t trc[FAST ? 9 : 1];  // FAST: this thread's word transitions per unit
+#pragma unroll
+    for (int i = 0; i < (FAST ? 9 : 1); ++i) trc[i] = 0;
     const uint32_t tid = threadIdx.x, lane = tid & 63;
     // every field the tile loop needs, in registers: stores through the row
     // pointer could otherwise alias the job table and force reloads
@@ -395,9 +402,52 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         }
 
         // ---- bit transpose: lo[c] (and hi[c]) become the plane words of bit c (32 + c);
-        // stage them row-major in LDS: row 0 = sign, row r >= 1 = plane r-1 = bit B-r
+        // row 0 = sign, row r >= 1 = plane r-1 = bit B-r
         transpose32(lo);
         if constexpr (F64) transpose32(hi);
+        if constexpr (FAST) {
+            // row r (0..32) is sgn or lo[32 - r]; unit of row r is (r + 3) / 4
+            const uint32_t wave = tid >> 6;
+            const bool have_prev = t > t0;
+            const bool lead = valid && (tid >= 1 || have_prev);
+            const uint32_t par = (t - t0) & 1;
+            if (lane == 63) {
+                s_edge[par][wave][0] = sgn;
+#pragma unroll
+                for (int r = 1; r <= 32; ++r) s_edge[par][wave][r] = lo[32 - r];
+            }
+            __syncthreads();  // edges written; every thread is done with its y values
+            const uint32_t* edge = wave ? &s_edge[par][wave - 1][0] : &s_edge[par ^ 1][3][0];
+            if (t == t0 && tid == 0) {
+                recs[((uint64_t)wg * kMaxRows) * 2] = sgn;
+#pragma unroll
+                for (int r = 1; r <= 32; ++r) recs[((uint64_t)wg * kMaxRows + r) * 2] = lo[32 - r];
+            }
+            if (valid && blk == last_blk) {
+                recs[((uint64_t)wg * kMaxRows) * 2 + 1] = sgn;
+#pragma unroll
+                for (int r = 1; r <= 32; ++r) recs[((uint64_t)wg * kMaxRows + r) * 2 + 1] = lo[32 - r];
+            }
+            const auto row0 = rows + blk;
+#pragma unroll
+            for (int r = 0; r <= 32; ++r) {
+                const uint32_t w = r == 0 ? sgn : lo[32 - r];
+                const int unit = (r + 3) / 4;
+                if (valid) {
+                    row0[(uint64_t)r * nbd] = w;
+                    uint32_t* h = s_hist + unit * 256;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t byte = (w >> (8 * q)) & 0xFFu;
+                        atomicAdd(byte ? &h[byte] : &s_zero[tid], 1u);
+                    }
+                }
+                const uint32_t up = __shfl_up(w, 1, 64);
+                const uint32_t nb = lane == 0 ? edge[r] : up;
+                trc[unit] += (lead && w != nb) ? 1u : 0u;
+            }
+            continue;
+        }
         __syncthreads();  // every thread is done with its y values
         s_pl[tid] = sgn;
 #pragma unroll
@@ -462,6 +512,16 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     }
 
     // ---- flush: per-workgroup partials (reduced by the selection kernel)
+    if constexpr (FAST) {
+        // a unit's transitions go to its first row's slot (the selection sums a unit's rows)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            uint32_t v = trc[i];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0 && v) atomicAdd(&s_trans[i == 0 ? 0 : 1 + (i - 1) * 4], v);
+        }
+    }
     small = wave_max(small);
     if constexpr (F64) {
         if (lane == 0) atomicMax(&s_key64[kKeyStride - 1], (unsigned long long)__double_as_longlong(small));
@@ -486,12 +546,12 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
 }
 
 // f32 fits three waves per SIMD without spilling; f64 keeps the default budget
-template <bool VEC>
+template <bool VEC, bool FAST>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_encode_f32(
     const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
 {
     const EncodeJob& job = jobs[wg_job[blockIdx.x]];
-    encode_body<false, VEC>(job, blockIdx.x - job.wg_base);
+    encode_body<false, VEC, FAST>(job, blockIdx.x - job.wg_base);
 }
 
 template <bool VEC>
@@ -499,7 +559,7 @@ __global__ __launch_bounds__(kThreads) void k_encode_f64(const EncodeJob* __rest
                                                          const uint32_t* __restrict__ wg_job)
 {
     const EncodeJob& job = jobs[wg_job[blockIdx.x]];
-    encode_body<true, VEC>(job, blockIdx.x - job.wg_base);
+    encode_body<true, VEC, false>(job, blockIdx.x - job.wg_base);
 }
 
 // ------------------------------------------------------------------ hybrid selection
@@ -863,8 +923,10 @@ hipError_t encode_set_lds(uint32_t nunits, uint32_t B, bool f64)
 {
     const size_t shmem = encode_lds_bytes(nunits, B, f64);
     if (shmem <= 64 * 1024) return hipSuccess;
-    const void* fns[2] = {f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true>,
-                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false>};
+    const void* fns[4] = {f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true, false>,
+                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false, false>,
+                          f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true, true>,
+                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false, true>};
     for (const void* fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
@@ -873,8 +935,9 @@ hipError_t encode_set_lds(uint32_t nunits, uint32_t B, bool f64)
 }
 
 hipError_t launch_encode_batch(const EncodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
-                               uint32_t nunits, uint32_t B, bool f64, bool vec, hipStream_t s)
+                               uint32_t nunits, uint32_t B, uint32_t m, bool f64, bool vec, hipStream_t s)
 {
+    const bool fast = !f64 && B == 32 && m == 4;
     if (grid == 0) return hipSuccess;
     const size_t shmem = encode_lds_bytes(nunits, B, f64);
     dim3 g(grid), b(kThreads);
@@ -884,10 +947,17 @@ hipError_t launch_encode_batch(const EncodeJob* jobs, const uint32_t* wg_job, ui
         else
             hipLaunchKernelGGL((k_encode_f64<false>), g, b, shmem, s, jobs, wg_job);
     } else {
-        if (vec)
-            hipLaunchKernelGGL((k_encode_f32<true>), g, b, shmem, s, jobs, wg_job);
-        else
-            hipLaunchKernelGGL((k_encode_f32<false>), g, b, shmem, s, jobs, wg_job);
+        if (fast) {
+            if (vec)
+                hipLaunchKernelGGL((k_encode_f32<true, true>), g, b, shmem, s, jobs, wg_job);
+            else
+                hipLaunchKernelGGL((k_encode_f32<false, true>), g, b, shmem, s, jobs, wg_job);
+        } else {
+            if (vec)
+                hipLaunchKernelGGL((k_encode_f32<true, false>), g, b, shmem, s, jobs, wg_job);
+            else
+                hipLaunchKernelGGL((k_encode_f32<false, false>), g, b, shmem, s, jobs, wg_job);
+        }
     }
     return hipGetLastError();
 }

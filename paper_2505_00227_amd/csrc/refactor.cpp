@@ -362,8 +362,8 @@ mdr_status enqueue_pass(mdr_context* ctx, const Layout& L, const mdr_codec_param
     }
     {
         StageTimer tm(tctx, MDR_STAGE_ENCODE, s);
-        MDR_HIP(launch_encode_batch(ej, map[2], (uint32_t)L.map[2].size(), L.nunits, L.B, L.f64, false, s));
-        MDR_HIP(launch_encode_batch(ej, map[3], (uint32_t)L.map[3].size(), L.nunits, L.B, L.f64, true, s));
+        MDR_HIP(launch_encode_batch(ej, map[2], (uint32_t)L.map[2].size(), L.nunits, L.B, L.m, L.f64, false, s));
+        MDR_HIP(launch_encode_batch(ej, map[3], (uint32_t)L.map[3].size(), L.nunits, L.B, L.m, L.f64, true, s));
     }
     {
         StageTimer tm(tctx, MDR_STAGE_SELECT, s);
