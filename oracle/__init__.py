@@ -117,7 +117,7 @@ class Params:
     group_planes: int = 4
     t_cr_milli: int = 2000
     t_s: int = 4096
-    huf_chunk: int = 1024
+    huf_chunk: int = 256
     huf_lmax: int = 12
     force_method: int = -1
 

@@ -257,7 +257,7 @@ mdr_status mdr_codec_params_default(mdr_codec_params* out)
     out->group_planes = 4;
     out->t_cr_milli = 2000;
     out->t_s_bytes = 4096;
-    out->huf_chunk = 1024;
+    out->huf_chunk = 256;
     out->huf_lmax = 12;
     out->force_method = -1;
     return MDR_OK;

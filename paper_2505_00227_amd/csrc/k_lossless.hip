@@ -512,21 +512,18 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
 }
 
 // ------------------------------------------------------------------ Huffman decode
-// One thread per chunk.  A 2^lmax-entry table in LDS maps the next lmax bits
-// to up to four symbols: every code that lies wholly inside the window is
-// decoded by one lookup (codes are prefix-free, so the bits after a whole code
-// do not change it).  Skewed groups, whose frequent symbols have 1-3 bit codes,
-// take a quarter of the dependent lookups of a one-symbol table.
-__global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
-                                                         const uint32_t* __restrict__ wg_job)
+// A 2^lmax-entry table maps the next lmax bits to up to four symbols: every
+// code that lies wholly inside the window is decoded by one lookup (codes are
+// prefix-free, so the bits after a whole code do not change it).  Skewed
+// groups, whose frequent symbols have 1-3 bit codes, take a quarter of the
+// dependent lookups of a one-symbol table.  The table is built once per
+// stream (k_huf_table) and copied into LDS by every decoding workgroup.
+__global__ __launch_bounds__(kThreads) void k_huf_table(const DecodeJob* __restrict__ jobs)
 {
-    const DecodeJob& job = jobs[wg_job[blockIdx.x]];
+    const DecodeJob& job = jobs[blockIdx.x];
     const uint8_t* payload = job.payload;
-    const uint64_t S = job.S;
-    const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
-    uint8_t* g = job.out;
-    __shared__ uint16_t s_lut[1 << kLutBitsMax];             // (length << 8) | symbol
-    __shared__ unsigned long long s_multi[1 << kLutBitsMax];  // symbols | count << 32 | bits << 35
+    const uint32_t lmax = job.lmax;
+    __shared__ uint16_t s_lut[1 << kLutBitsMax];  // (length << 8) | symbol
     __shared__ uint8_t s_len[256];
     __shared__ uint32_t s_count[33], s_first[33], s_offset[33];
     __shared__ uint8_t s_sorted[256];
@@ -566,6 +563,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
         s_lut[i] = ent;
     }
     __syncthreads();
+    const auto table = gmem(job.table);
     for (uint32_t i = tid; i < nent; i += kThreads) {
         uint32_t syms = 0, k = 0, used = 0;
         while (k < 4) {
@@ -576,7 +574,25 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
             ++k;
             used += l;
         }
-        s_multi[i] = (unsigned long long)syms | ((unsigned long long)k << 32) | ((unsigned long long)used << 35);
+        table[i] = (unsigned long long)syms | ((unsigned long long)k << 32) | ((unsigned long long)used << 35);
+    }
+}
+
+// One thread per chunk: symbols | count << 32 | bits << 35 per table entry.
+__global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
+                                                         const uint32_t* __restrict__ wg_job)
+{
+    const DecodeJob& job = jobs[wg_job[blockIdx.x]];
+    const uint8_t* payload = job.payload;
+    const uint64_t S = job.S;
+    const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
+    uint8_t* g = job.out;
+    __shared__ unsigned long long s_multi[1 << kLutBitsMax];
+    const uint32_t tid = threadIdx.x;
+    {
+        const auto src = gmem(reinterpret_cast<const u32x4*>(job.table));
+        u32x4* dst = reinterpret_cast<u32x4*>(s_multi);
+        for (uint32_t i = tid; i < (1u << lmax) / 2; i += kThreads) dst[i] = src[i];
     }
     __syncthreads();
     const uint32_t c = (blockIdx.x - job.wg_base) * kThreads + tid;
@@ -703,10 +719,11 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
     return hipGetLastError();
 }
 
-hipError_t launch_huf_decode_batch(const DecodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
-                                   hipStream_t s)
+hipError_t launch_huf_decode_batch(const DecodeJob* jobs, uint32_t njobs, const uint32_t* wg_job,
+                                   uint32_t grid, hipStream_t s)
 {
-    if (grid == 0) return hipSuccess;
+    if (grid == 0 || njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_huf_table, dim3(njobs), dim3(kThreads), 0, s, jobs);
     hipLaunchKernelGGL(k_huf_decode, dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     return hipGetLastError();
 }

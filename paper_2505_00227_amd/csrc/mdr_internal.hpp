@@ -143,12 +143,15 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
 struct DecodeJob {
     const uint8_t* payload;
     uint8_t* out;           // S decoded bytes
+    unsigned long long* table;  // kDecodeTableBytes of scratch: the job's decode table
     uint64_t S;
     uint32_t nchunks, chunk, lmax;
     uint32_t wg_base;       // first workgroup of this job in the launch
 };
-hipError_t launch_huf_decode_batch(const DecodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
-                                   hipStream_t s);
+constexpr uint64_t kDecodeTableBytes = 8ull << kLutBitsMax;
+// builds every job's table (one workgroup per job), then decodes (kThreads chunks per workgroup)
+hipError_t launch_huf_decode_batch(const DecodeJob* jobs, uint32_t njobs, const uint32_t* wg_job,
+                                   uint32_t grid, hipStream_t s);
 // RLE decode: payload u32 nruns | u32 wbytes | symbols[nruns] | u32 lengths[nruns]
 hipError_t launch_rle_decode(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
                              uint8_t* g, uint32_t* temp, hipStream_t s);

@@ -15,7 +15,7 @@ namespace {
 
 // A descriptor slot: pinned host staging plus its device copy.  A slot is
 // reused only after the event recorded behind the kernels that read it.
-DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st)
+DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st, uint64_t scratch_bytes = 0)
 {
     DescSlot& d = ctx->ring[ctx->ring_next++ % kDescSlots];
     st = MDR_OK;
@@ -50,6 +50,13 @@ DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st)
             return nullptr;
         }
         d.bytes = want;
+    }
+    if (d.scratch.bytes < scratch_bytes) {
+        hipError_t e = d.scratch.alloc(scratch_bytes + scratch_bytes / 2);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "hipMalloc(decode tables)");
+            return nullptr;
+        }
     }
     return &d;
 }
@@ -227,8 +234,12 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
     const uint64_t o_m1 = take(4 * map_r[1].size());
     if (o) {
         mdr_status st;
-        DescSlot* slot = acquire_slot(ctx, o, st);
+        // decode tables: one per Huffman job, built once and copied by its workgroups
+        DescSlot* slot = acquire_slot(ctx, o, st, (uint64_t)dec.size() * kDecodeTableBytes);
         if (!slot) return st;
+        for (size_t i = 0; i < dec.size(); ++i)
+            dec[i].table = reinterpret_cast<unsigned long long*>(static_cast<uint8_t*>(slot->scratch.p) +
+                                                                 i * kDecodeTableBytes);
         uint8_t* h = static_cast<uint8_t*>(slot->host);
         uint8_t* dv = static_cast<uint8_t*>(slot->dev.p);
         auto put = [&](uint64_t at, const void* src, uint64_t bytes) {
@@ -243,7 +254,7 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
         MDR_HIP(hipMemcpyAsync(dv, h, o, hipMemcpyHostToDevice, s));
         if (!map_dec.empty()) {
             StageTimer tm(ctx, MDR_STAGE_HUF_DECODE, s);
-            MDR_HIP(launch_huf_decode_batch(reinterpret_cast<const DecodeJob*>(dv + o_dec),
+            MDR_HIP(launch_huf_decode_batch(reinterpret_cast<const DecodeJob*>(dv + o_dec), (uint32_t)dec.size(),
                                             reinterpret_cast<const uint32_t*>(dv + o_md),
                                             (uint32_t)map_dec.size(), s));
         }
