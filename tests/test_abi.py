@@ -36,7 +36,7 @@ def test_host_side_validation_without_gpu():
     import paper_2505_00227_amd as mdr
     p = mdr.default_params()
     assert (p.group_planes, p.t_cr_milli, p.t_s_bytes, p.huf_chunk, p.huf_lmax, p.force_method) == \
-        (4, 2000, 4096, 1024, 12, -1)
+        (4, 2000, 4096, 256, 12, -1)
     out = C.c_void_p()
     views = (mdr.mdr_level_view * 1)()
     st = mdr.mdr_refactor(None, views, 1, mdr.MDR_F32, 32, None, None, C.byref(out))
