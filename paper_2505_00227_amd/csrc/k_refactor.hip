@@ -197,14 +197,16 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
 //   counts of W-bit word transitions for the run-length estimate.
 //
 // Exact pruning of the f32 error keys.  Let K_k be the workgroup's running
-// maximum.  When K_k >= 1 - 2^-12 ("strong" cut), a value can exceed it only if
-// the 12 bits just below the cut, in y's binary expansion, are all ones.  With
-// Y = y * 2^32 (exact: y >= 1 has no bits below 2^-23), bit p of
-// r = AND_{i<12} (Y << i) says "bits p..p-11 of Y are ones", so the high word of
-// r flags every candidate cut c = B-k (bit c-1) at once.  Only flagged cuts are
-// evaluated and folded in with an LDS max; the others cannot change the result.
-// Cuts whose maximum is still below 1 - 2^-12 ("weak") take the direct per-block
-// maximum.  Stale thresholds only add candidates, so the result is exact.
+// maximum.  When K_k >= 1 - 2^-t (its binary fraction starts with t ones), a
+// value can exceed it only if the t bits just below the cut, in y's binary
+// expansion, are all ones.  With Y = (mag << 32) | top 32 fraction bits, bit p
+// of r_t = AND_{i<t} (Y << i) says "bits p..p-t+1 of Y are ones"; r_1, r_2,
+// r_4, r_8, r_12 come from four shift-ANDs, and each cut c = B-k (bit c-1 of
+// the high word) is tested with the longest of them its K_k allows, so one
+// pass flags every candidate cut of a value.  Only flagged cuts are evaluated
+// and folded in with an LDS max; the others cannot change the result.  Cuts
+// with K_k < 1/2 take the direct per-block maximum; k = 0 is max |x|, known from
+// the statistics.  Stale maxima only add candidates, so the result is exact.
 // FAST: f32 with 32 planes in groups of 4 (every row, its unit and its
 // histogram offset known at compile time): rows go from registers straight to
 // memory, neighbours come by lane shuffle, runs are counted per thread and unit.
@@ -224,7 +226,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     __shared__ uint32_t s_zero[kThreads];  // sink for zero bytes (one slot per thread)
 
     __shared__ uint32_t s_hoff[kMaxRows];  // row -> its unit's histogram offset
-    __shared__ uint32_t s_edge[FAST ? 2 : 1][kThreads / 64][FAST ? 33 : 1];  // last lane's words per wave
+    __shared__ uint32_t s_edge[FAST ? 4 : 1][kThreads / 64][FAST ? 33 : 1];  // last lane's words per wave
     uint32_t trc[FAST ? 9 : 1];  // FAST: this thread's word transitions per unit
 #pragma unroll
     for (int i = 0; i < (FAST ? 9 : 1); ++i) trc[i] = 0;
@@ -265,38 +267,43 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     const uint32_t t1 = min(ntiles, t0 + tpw);
     const uint32_t last_blk = min(nbd, t1 * kTileBlocks) - 1;
 
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t blk = t * kTileBlocks + tid;
-        const bool valid = blk < nbd;
-        const uint64_t base = (uint64_t)blk * 32;
-        __syncthreads();  // the previous tile's rows have been consumed
-
-        // ---- load 32 consecutive values
-        T v[32];
-        if (VEC && valid && base + 32 <= n) {
+    // ---- 32 consecutive values of tile tt (zeros past the level's end)
+    auto load_tile = [&](uint32_t tt, T (&vv)[32]) {
+        const uint32_t b = tt * kTileBlocks + tid;
+        const uint64_t bs = (uint64_t)b * 32;
+        if (VEC && b < nbd && bs + 32 <= n) {
             if constexpr (F64) {
-                const auto p = gmem(reinterpret_cast<const f64x2*>(xg + base));
+                const auto p = gmem(reinterpret_cast<const f64x2*>(xg + bs));
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const f64x2 q = p[j];
-                    v[2 * j] = q.x;
-                    v[2 * j + 1] = q.y;
+                    vv[2 * j] = q.x;
+                    vv[2 * j + 1] = q.y;
                 }
             } else {
-                const auto p = gmem(reinterpret_cast<const f32x4*>(xg + base));
+                const auto p = gmem(reinterpret_cast<const f32x4*>(xg + bs));
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const f32x4 q = p[j];
-                    v[4 * j] = q.x;
-                    v[4 * j + 1] = q.y;
-                    v[4 * j + 2] = q.z;
-                    v[4 * j + 3] = q.w;
+                    vv[4 * j] = q.x;
+                    vv[4 * j + 1] = q.y;
+                    vv[4 * j + 2] = q.z;
+                    vv[4 * j + 3] = q.w;
                 }
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < 32; ++j) v[j] = (valid && base + j < n) ? x[base + j] : T(0);
+            for (int j = 0; j < 32; ++j) vv[j] = (b < nbd && bs + j < n) ? x[bs + j] : T(0);
         }
+    };
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t blk = t * kTileBlocks + tid;
+        const bool valid = blk < nbd;
+        // the fast path shares nothing between tiles but the edge buffers (four
+        // of them), so its waves need no barrier here
+        if constexpr (!FAST) __syncthreads();  // the previous tile's rows have been consumed
+        T v[32];
+        load_tile(t, v);
 
         // ---- align to the level exponent: y = |x| 2^(B-e), mag = floor(y)
         uint32_t sgn = 0;
@@ -333,7 +340,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         // ---- exact error keys, k = 0..B
         if constexpr (F64) {
             // direct per-block maximum, folded per wave into LDS
-            for (int k = 0; k <= (int)B; ++k) {
+            for (int k = 1; k <= (int)B; ++k) {  // k = 0 is max |x|, known from the statistics
                 double km = 0.0;
 #pragma unroll
                 for (int j = 0; j < 32; ++j) {
@@ -348,23 +355,39 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 *reinterpret_cast<float4*>(ys + 4 * q) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-            // cut c = B - k for k = 0..B-1 is bit c-1; k = B is the fraction itself
-            uint32_t strong = 0;
-#pragma unroll
-            for (int c = 1; c <= 32; ++c) {
-                const uint32_t kk = c <= (int)B ? B - c : 0u;
-                strong |= (c <= (int)B && s_key32[kk] >= 0x3F7FF000u) ? (1u << (c - 1)) : 0u;  // K >= 1 - 2^-12
+            // Cut c = B - k (k = 1..B-1) is bit c-1 of y; k = B is the fraction
+            // itself (frac_max).  A value can raise the running maximum M_c only
+            // if its key exceeds M_c; when M_c has t leading ones (M_c >= 1 - 2^-t)
+            // that needs bits c-1 .. c-t of y to be ones.  Each cut is tested with
+            // the longest run in {12, 8, 4, 2, 1} that its M_c allows; cuts with
+            // M_c < 1/2 take the direct maximum.  Lane l decides cut l+1.
+            uint32_t S1, S2, S4, S8, S12;
+            {
+                const uint32_t c = lane + 1;
+                uint32_t tl = 0;
+                if (c < B) {
+                    const float M = __uint_as_float(s_key32[B - c]);
+                    if (M >= 0.5f) tl = __clz(~(uint32_t)(M * 0x1p32f));
+                }
+                const bool live = c < B;
+                S12 = (uint32_t)__ballot(live && tl >= 12);
+                S8 = (uint32_t)__ballot(live && tl >= 8 && tl < 12);
+                S4 = (uint32_t)__ballot(live && tl >= 4 && tl < 8);
+                S2 = (uint32_t)__ballot(live && tl >= 2 && tl < 4);
+                S1 = (uint32_t)__ballot(live && tl == 1);
             }
-            strong = __builtin_amdgcn_readfirstlane(strong);
+            const uint32_t strong = S1 | S2 | S4 | S8 | S12;
             auto one = [&](float y) {
                 const float f = __builtin_amdgcn_fractf(y);
                 frac_max = fmaxf(frac_max, f);
                 const uint64_t Y = ((uint64_t)(uint32_t)y << 32) | (uint32_t)(f * 0x1p32f);
-                uint64_t r = Y & (Y << 1);
-                r &= r << 2;
-                r &= r << 4;
-                r &= r << 4;
-                uint32_t cand = (uint32_t)(r >> 32) & strong;
+                const uint64_t r2 = Y & (Y << 1);    // bit p: bits p, p-1 are ones
+                const uint64_t r4 = r2 & (r2 << 2);  // p .. p-3
+                const uint64_t r8 = r4 & (r4 << 4);  // p .. p-7
+                const uint64_t r12 = r8 & (r8 << 4); // p .. p-11
+                uint32_t cand = ((uint32_t)(Y >> 32) & S1) | ((uint32_t)(r2 >> 32) & S2) |
+                                ((uint32_t)(r4 >> 32) & S4) | ((uint32_t)(r8 >> 32) & S8) |
+                                ((uint32_t)(r12 >> 32) & S12);
                 while (cand) {
                     const int c = __ffs(cand);  // 1-based bit index == cut
                     cand &= cand - 1;
@@ -382,7 +405,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 one(cur.z);
                 one(cur.w);
             }
-            const uint32_t all = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+            const uint32_t all = (1u << (B - 1)) - 1u;  // cuts 1 .. B-1
             uint32_t weak = all & ~strong;
             while (weak) {
                 const int c = __ffs(weak);
@@ -410,14 +433,16 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
             const uint32_t wave = tid >> 6;
             const bool have_prev = t > t0;
             const bool lead = valid && (tid >= 1 || have_prev);
-            const uint32_t par = (t - t0) & 1;
+            // four buffers: without a barrier at the top of the tile, a wave can
+            // be one tile ahead of another, never two (the edge barrier below)
+            const uint32_t par = (t - t0) & 3;
             if (lane == 63) {
                 s_edge[par][wave][0] = sgn;
 #pragma unroll
                 for (int r = 1; r <= 32; ++r) s_edge[par][wave][r] = lo[32 - r];
             }
             __syncthreads();  // edges written; every thread is done with its y values
-            const uint32_t* edge = wave ? &s_edge[par][wave - 1][0] : &s_edge[par ^ 1][3][0];
+            const uint32_t* edge = wave ? &s_edge[par][wave - 1][0] : &s_edge[(par + 3) & 3][3][0];
             if (t == t0 && tid == 0) {
                 recs[((uint64_t)wg * kMaxRows) * 2] = sgn;
 #pragma unroll

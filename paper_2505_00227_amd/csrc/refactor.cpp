@@ -445,7 +445,8 @@ mdr_status assemble(mdr_context* ctx, const Layout& L, mdr_dtype dtype, const md
                 LR.vmaxabs = bits_value(ls.maxabs_bits, L.f64);
                 const unsigned long long* keys = hek + (uint64_t)j * kKeyStride;
                 const double small = bits_value(keys[kKeyStride - 1], L.f64);
-                for (uint32_t k = 0; k <= L.B; ++k) {
+                LR.E[0] = LR.vmaxabs;  // nothing fetched: the error is max |x|
+                for (uint32_t k = 1; k <= L.B; ++k) {
                     const double ek = std::ldexp(bits_value(keys[k], L.f64), LR.e - (int)k);
                     LR.E[k] = ek > small ? ek : small;
                 }
