@@ -81,38 +81,24 @@ __global__ void k_init_stats(LevelStats* st, int count)
 // alignment exponent), min / max / max|x|, and a non-finite flag.  Each thread
 // folds 16-byte vectors, the workgroup reduces in LDS, and one lane per
 // workgroup publishes with device atomics (few workgroups -> little contention).
+// Per thread: the largest |x| bit pattern (which also gives the largest frexp
+// exponent and reveals NaN / Inf, whose patterns are the largest) and the float
+// minimum / maximum (zeros of either sign are reported as +0.0, so their order
+// does not matter).
 template <bool F64>
 struct StatAcc {
     using U = std::conditional_t<F64, uint64_t, uint32_t>;
-    int emax = INT_MIN;
-    uint32_t bad = 0;
-    uint64_t kmin = ~0ull, kmax = 0;
+    using T = std::conditional_t<F64, double, float>;
     U amax = 0;
+    T vmin = __builtin_huge_val(), vmax = -__builtin_huge_val();
     __device__ __forceinline__ void add(U b)
     {
-        U ab;
-        int ex;
-        uint64_t key;
-        bool finite;
-        if constexpr (F64) {
-            ab = b & 0x7FFFFFFFFFFFFFFFull;
-            finite = ab < 0x7FF0000000000000ull;
-            ex = ab ? frexp_exp_f64(ab) : INT_MIN;
-            key = order_key_f64(b);
-        } else {
-            ab = b & 0x7FFFFFFFu;
-            finite = ab < 0x7F800000u;
-            ex = ab ? frexp_exp_f32(ab) : INT_MIN;
-            key = order_key_f32(b);
-        }
-        if (!finite) {
-            bad = 1;
-            return;
-        }
-        emax = ex > emax ? ex : emax;
-        kmin = key < kmin ? key : kmin;
-        kmax = key > kmax ? key : kmax;
+        const U ab = b & (F64 ? 0x7FFFFFFFFFFFFFFFull : 0x7FFFFFFFu);
         amax = ab > amax ? ab : amax;
+        T v;
+        __builtin_memcpy(&v, &b, sizeof(T));
+        vmin = __builtin_fmin(vmin, v);
+        vmax = __builtin_fmax(vmax, v);
     }
 };
 
@@ -123,6 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
                                                     const uint32_t* __restrict__ wg_job)
 {
     using U = typename StatAcc<F64>::U;
+    using T = typename StatAcc<F64>::T;
     constexpr int PER = 16 / sizeof(U);  // values per 16-byte vector
     const StatsJob& job = jobs[wg_job[blockIdx.x]];
     const auto x = gmem(static_cast<const U*>(job.x));
@@ -152,35 +139,38 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
     }
     for (uint64_t i = done + tid0; i < n; i += stride) acc.add(x[i]);
 
-    __shared__ int s_e[kThreads / 64];
-    __shared__ uint32_t s_bad[kThreads / 64];
-    __shared__ unsigned long long s_kmin[kThreads / 64], s_kmax[kThreads / 64], s_amax[kThreads / 64];
+    __shared__ unsigned long long s_amax[kThreads / 64];
+    __shared__ T s_min[kThreads / 64], s_max[kThreads / 64];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int e = wave_max(acc.emax);
-    uint64_t kmin = wave_min(acc.kmin), kmax = wave_max(acc.kmax);
     uint64_t amax = wave_max((uint64_t)acc.amax);
-    uint32_t bad = __any(acc.bad) ? 1u : 0u;
+    T vmin = wave_min(acc.vmin), vmax = wave_max(acc.vmax);
     if (lane == 0) {
-        s_e[wave] = e;
-        s_bad[wave] = bad;
-        s_kmin[wave] = kmin;
-        s_kmax[wave] = kmax;
         s_amax[wave] = amax;
+        s_min[wave] = vmin;
+        s_max[wave] = vmax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kThreads / 64; ++w) {
-            e = s_e[w] > e ? s_e[w] : e;
-            bad |= s_bad[w];
-            kmin = s_kmin[w] < kmin ? s_kmin[w] : kmin;
-            kmax = s_kmax[w] > kmax ? s_kmax[w] : kmax;
             amax = s_amax[w] > amax ? s_amax[w] : amax;
+            vmin = s_min[w] < vmin ? s_min[w] : vmin;
+            vmax = s_max[w] > vmax ? s_max[w] : vmax;
         }
-        if (e != INT_MIN) atomicMax(&st->emax, e);
-        if (bad) atomicOr(&st->nonfinite, 1u);
-        atomicMin((unsigned long long*)&st->minkey, (unsigned long long)kmin);
-        atomicMax((unsigned long long*)&st->maxkey, (unsigned long long)kmax);
-        atomicMax((unsigned long long*)&st->maxabs_bits, (unsigned long long)amax);
+        const bool bad = F64 ? amax >= 0x7FF0000000000000ull : amax >= 0x7F800000u;
+        if (bad) {
+            atomicOr(&st->nonfinite, 1u);
+        } else {
+            U bmin, bmax;
+            __builtin_memcpy(&bmin, &vmin, sizeof(T));
+            __builtin_memcpy(&bmax, &vmax, sizeof(T));
+            const uint64_t kmin = F64 ? order_key_f64(bmin) : order_key_f32((uint32_t)bmin);
+            const uint64_t kmax = F64 ? order_key_f64(bmax) : order_key_f32((uint32_t)bmax);
+            const int e = amax == 0 ? INT_MIN : (F64 ? frexp_exp_f64(amax) : frexp_exp_f32((uint32_t)amax));
+            if (e != INT_MIN) atomicMax(&st->emax, e);
+            atomicMin((unsigned long long*)&st->minkey, (unsigned long long)kmin);
+            atomicMax((unsigned long long*)&st->maxkey, (unsigned long long)kmax);
+            atomicMax((unsigned long long*)&st->maxabs_bits, (unsigned long long)amax);
+        }
     }
 }
 
