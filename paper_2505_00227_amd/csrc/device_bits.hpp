@@ -24,40 +24,43 @@ __device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
 
 // In-register transpose of a 32x32 bit matrix: afterwards bit r of a[c] is the
 // former bit c of a[r].  Five butterfly stages swap the off-diagonal blocks of
-// size 16, 8, 4, 2, 1 (each output word is one bit-field insert).
+// size 16, 8, 4, 2, 1.  The two byte-granular stages are one byte permute per
+// output word; the bit-granular ones a shift and a bit-field insert.
 __device__ __forceinline__ void transpose32(uint32_t (&a)[32])
 {
+    // __builtin_amdgcn_perm(hi, lo, sel): byte i of the result is byte sel.i of
+    // the 8-byte value hi:lo (lo = bytes 0..3)
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-        uint32_t x = a[k], y = a[k + 16];
-        a[k] = (x & 0x0000FFFFu) | (y << 16);
-        a[k + 16] = (x >> 16) | (y & 0xFFFF0000u);
+        const uint32_t x = a[k], y = a[k + 16];
+        a[k] = __builtin_amdgcn_perm(y, x, 0x05040100u);       // x.lo16 | y.lo16 << 16
+        a[k + 16] = __builtin_amdgcn_perm(y, x, 0x07060302u);  // x.hi16 | y.hi16 << 16
     }
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
         if (k & 8) continue;
-        uint32_t x = a[k], y = a[k + 8];
-        a[k] = (x & 0x00FF00FFu) | ((y << 8) & 0xFF00FF00u);
-        a[k + 8] = ((x >> 8) & 0x00FF00FFu) | (y & 0xFF00FF00u);
+        const uint32_t x = a[k], y = a[k + 8];
+        a[k] = __builtin_amdgcn_perm(y, x, 0x06020400u);      // x0 y0 x2 y2
+        a[k + 8] = __builtin_amdgcn_perm(y, x, 0x07030501u);  // x1 y1 x3 y3
     }
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
         if (k & 4) continue;
-        uint32_t x = a[k], y = a[k + 4];
+        const uint32_t x = a[k], y = a[k + 4];
         a[k] = (x & 0x0F0F0F0Fu) | ((y << 4) & 0xF0F0F0F0u);
         a[k + 4] = ((x >> 4) & 0x0F0F0F0Fu) | (y & 0xF0F0F0F0u);
     }
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
         if (k & 2) continue;
-        uint32_t x = a[k], y = a[k + 2];
+        const uint32_t x = a[k], y = a[k + 2];
         a[k] = (x & 0x33333333u) | ((y << 2) & 0xCCCCCCCCu);
         a[k + 2] = ((x >> 2) & 0x33333333u) | (y & 0xCCCCCCCCu);
     }
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
         if (k & 1) continue;
-        uint32_t x = a[k], y = a[k + 1];
+        const uint32_t x = a[k], y = a[k + 1];
         a[k] = (x & 0x55555555u) | ((y << 1) & 0xAAAAAAAAu);
         a[k + 1] = ((x >> 1) & 0x55555555u) | (y & 0xAAAAAAAAu);
     }

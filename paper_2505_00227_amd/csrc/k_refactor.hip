@@ -206,14 +206,17 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     using T = std::conditional_t<F64, double, float>;
     constexpr int G = F64 ? 2 : 1;  // u32 words per W-bit word
     constexpr int NROW = F64 ? 65 : 33;
-    // dynamic LDS: [nunits][256] byte histograms, then the tile's plane words
-    // [rows][256] (f32: also this thread's y values, stride 33, in the same space)
+    // dynamic LDS (general path only): [nunits][256] byte histograms, then the
+    // tile's plane words [rows][256]
     extern __shared__ uint32_t s_dyn[];
     __shared__ uint32_t s_prev[kMaxRows][G];  // last word(s) of the previous tile, per row
     __shared__ uint32_t s_trans[kMaxRows];
     __shared__ uint32_t s_key32[F64 ? 1 : kKeyStride];
     __shared__ unsigned long long s_key64[F64 ? kKeyStride : 1];
-    __shared__ uint32_t s_zero[kThreads];  // sink for zero bytes (one slot per thread)
+    __shared__ uint32_t s_zero[FAST ? 1 : kThreads];  // sink for zero bytes (one slot per thread)
+    // FAST: the byte histograms at fixed LDS addresses, so each unit's offset is
+    // an instruction immediate
+    __shared__ uint32_t s_hist_fast[FAST ? 9 * 256 : 1];
 
     __shared__ uint32_t s_hoff[kMaxRows];  // row -> its unit's histogram offset
     __shared__ uint32_t s_edge[FAST ? 4 : 1][kThreads / 64][FAST ? 33 : 1];  // last lane's words per wave
@@ -237,9 +240,8 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     const auto trans_part = gmem(job.trans_part);
     if (tid < kMaxRows) s_hoff[tid] = job.hist_off[tid];
     (void)m;
-    uint32_t* s_hist = s_dyn;
-    uint32_t* s_pl = s_dyn + nunits * 256;           // [B+1][256]
-    float* s_y = reinterpret_cast<float*>(s_pl);     // [256][36] (reuses the plane space)
+    uint32_t* s_hist = FAST ? s_hist_fast : s_dyn;
+    uint32_t* s_pl = FAST ? s_dyn : s_dyn + nunits * 256;  // [B+1][256]
 
     for (uint32_t i = tid; i < nunits * 256; i += kThreads) s_hist[i] = 0;
     if (tid < kMaxRows) s_trans[tid] = 0;
@@ -319,14 +321,19 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 sgn |= (bits >> 31) << j;
                 float a = __uint_as_float(bits & 0x7FFFFFFFu);
                 float y = __builtin_amdgcn_ldexpf(a, (int)B - e);
-                uint32_t mg = (uint32_t)y;
-                bool tiny = mg == 0;
+                bool tiny = y < 1.0f;  // mag = floor(y) = 0
                 small = (tiny && a > small) ? a : small;
                 v[j] = tiny ? 0.0f : y;
-                lo[j] = mg;
             }
         }
 
+        if constexpr (!F64) {
+            // materialise y and the running `small` here, so the raw values die
+            // before the key loop instead of being carried through it
+#pragma unroll
+            for (int j = 0; j < 32; ++j) asm volatile("" : "+v"(v[j]));
+            asm volatile("" : "+v"(small));
+        }
         // ---- exact error keys, k = 0..B
         if constexpr (F64) {
             // direct per-block maximum, folded per wave into LDS
@@ -341,10 +348,6 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 if (lane == 0) atomicMax(&s_key64[k], (unsigned long long)__double_as_longlong(km));
             }
         } else {
-            float* ys = s_y + tid * 36;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                *reinterpret_cast<float4*>(ys + 4 * q) = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
             // Cut c = B - k (k = 1..B-1) is bit c-1 of y; k = B is the fraction
             // itself (frac_max).  A value can raise the running maximum M_c only
             // if its key exceeds M_c; when M_c has t leading ones (M_c >= 1 - 2^-t)
@@ -370,6 +373,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
             auto one = [&](float y) {
                 const float f = __builtin_amdgcn_fractf(y);
                 frac_max = fmaxf(frac_max, f);
+                asm volatile("" : "+v"(frac_max));  // fold in now, not at the end
                 const uint64_t Y = ((uint64_t)(uint32_t)y << 32) | (uint32_t)(f * 0x1p32f);
                 const uint64_t r2 = Y & (Y << 1);    // bit p: bits p, p-1 are ones
                 const uint64_t r4 = r2 & (r2 << 2);  // p .. p-3
@@ -385,35 +389,31 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                     atomicMax(&s_key32[B - c], __float_as_uint(key));
                 }
             };
-            const float4* ys4 = reinterpret_cast<const float4*>(ys);
-            float4 nxt = ys4[0];
-            for (int q = 0; q < 8; ++q) {
-                const float4 cur = nxt;
-                if (q < 7) nxt = ys4[q + 1];
-                one(cur.x);
-                one(cur.y);
-                one(cur.z);
-                one(cur.w);
-            }
+#pragma unroll
+            for (int j = 0; j < 32; ++j) one(v[j]);
             const uint32_t all = (1u << (B - 1)) - 1u;  // cuts 1 .. B-1
             uint32_t weak = all & ~strong;
             while (weak) {
                 const int c = __ffs(weak);
                 weak &= weak - 1;
                 float km = 0.0f;
-#pragma unroll 2
-                for (int q = 0; q < 8; ++q) {
-                    const float4 y4 = ys4[q];
-                    km = fmaxf(km, fmaxf(fmaxf(__builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.x, -c)),
-                                               __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.y, -c))),
-                                         fmaxf(__builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.z, -c)),
-                                               __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(y4.w, -c)))));
-                }
+#pragma unroll
+                for (int j = 0; j < 32; ++j)
+                    km = fmaxf(km, __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(v[j], -c)));
                 km = wave_max(km);
                 if (lane == 0) atomicMax(&s_key32[B - c], __float_as_uint(km));
             }
         }
 
+        if constexpr (!F64) {
+            // mag = floor(y) (0 when tiny), converted afresh: reusing the key
+            // loop's conversions would keep 32 more registers alive through it
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                asm volatile("" : "+v"(v[j]));
+                lo[j] = (uint32_t)v[j];
+            }
+        }
         // ---- bit transpose: lo[c] (and hi[c]) become the plane words of bit c (32 + c);
         // row 0 = sign, row r >= 1 = plane r-1 = bit B-r
         transpose32(lo);
@@ -421,8 +421,6 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         if constexpr (FAST) {
             // row r (0..32) is sgn or lo[32 - r]; unit of row r is (r + 3) / 4
             const uint32_t wave = tid >> 6;
-            const bool have_prev = t > t0;
-            const bool lead = valid && (tid >= 1 || have_prev);
             // four buffers: without a barrier at the top of the tile, a wave can
             // be one tile ahead of another, never two (the edge barrier below)
             const uint32_t par = (t - t0) & 3;
@@ -431,36 +429,58 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
 #pragma unroll
                 for (int r = 1; r <= 32; ++r) s_edge[par][wave][r] = lo[32 - r];
             }
-            __syncthreads();  // edges written; every thread is done with its y values
-            const uint32_t* edge = wave ? &s_edge[par][wave - 1][0] : &s_edge[(par + 3) & 3][3][0];
             if (t == t0 && tid == 0) {
+                // the first block of the range has no left neighbour: it sees its
+                // own words there (no transition).  Slot 3 of wave 3 is next
+                // written three tiles later, after this tile's barrier.
+                s_edge[3][3][0] = sgn;
+#pragma unroll
+                for (int r = 1; r <= 32; ++r) s_edge[3][3][r] = lo[32 - r];
                 recs[((uint64_t)wg * kMaxRows) * 2] = sgn;
 #pragma unroll
                 for (int r = 1; r <= 32; ++r) recs[((uint64_t)wg * kMaxRows + r) * 2] = lo[32 - r];
             }
+            __syncthreads();  // edges written; every thread is done with its y values
+            const uint32_t* edge = wave ? &s_edge[par][wave - 1][0] : &s_edge[(par + 3) & 3][3][0];
             if (valid && blk == last_blk) {
                 recs[((uint64_t)wg * kMaxRows) * 2 + 1] = sgn;
 #pragma unroll
                 for (int r = 1; r <= 32; ++r) recs[((uint64_t)wg * kMaxRows + r) * 2 + 1] = lo[32 - r];
             }
-            const auto row0 = rows + blk;
+            // per row: coalesced store, nonzero bytes into the unit's histogram
+            // (zero bytes are counted by difference later), and a transition
+            // against the left neighbour's word, which the wave shift brings
+            // from lane l-1 (lane 0: the previous wave's last word)
+            auto rows_out = [&](auto full_tile) {
+                constexpr bool FULL = decltype(full_tile)::value;
+                // row base in scalar registers, advanced per row (kept out of the
+                // tile loop's invariants, which would not fit), plus a 32-bit
+                // byte offset: a level holds < 2^32 values, so blk * 4 < 2^29
+                uint64_t rb = reinterpret_cast<uint64_t>(job.rows);
+                asm volatile("" : "+s"(rb));
+                const uint32_t boff = blk * 4u;
 #pragma unroll
-            for (int r = 0; r <= 32; ++r) {
-                const uint32_t w = r == 0 ? sgn : lo[32 - r];
-                const int unit = (r + 3) / 4;
-                if (valid) {
-                    row0[(uint64_t)r * nbd] = w;
-                    uint32_t* h = s_hist + unit * 256;
+                for (int r = 0; r <= 32; ++r) {
+                    const uint32_t w = r == 0 ? sgn : lo[32 - r];
+                    const int unit = (r + 3) / 4;
+                    if (FULL || valid) {
+                        *gmem(reinterpret_cast<uint32_t*>(rb + boff)) = w;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t byte = (w >> (8 * q)) & 0xFFu;
-                        atomicAdd(byte ? &h[byte] : &s_zero[tid], 1u);
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t byte = (w >> (8 * q)) & 0xFFu;
+                            if (byte) atomicAdd(&s_hist_fast[unit * 256 + byte], 1u);
+                        }
                     }
+                    // wave_shr:1 (lane l <- lane l-1); lane 0 keeps `old`
+                    const uint32_t nb = (uint32_t)__builtin_amdgcn_update_dpp((int)edge[r], (int)w, 0x138, 0xF, 0xF, false);
+                    trc[unit] += ((FULL || valid) && w != nb) ? 1u : 0u;
+                    rb += 4ull * nbd;
                 }
-                const uint32_t up = __shfl_up(w, 1, 64);
-                const uint32_t nb = lane == 0 ? edge[r] : up;
-                trc[unit] += (lead && w != nb) ? 1u : 0u;
-            }
+            };
+            if ((t + 1) * kTileBlocks <= nbd)
+                rows_out(std::true_type{});
+            else
+                rows_out(std::false_type{});
             continue;
         }
         __syncthreads();  // every thread is done with its y values
@@ -560,9 +580,10 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     if (tid < kMaxRows) trans_part[(uint64_t)wg * kMaxRows + tid] = s_trans[tid];
 }
 
-// f32 fits three waves per SIMD without spilling; f64 keeps the default budget
+// f32 fits five waves per SIMD (96 registers) with LDS to spare; f64 keeps
+// the default budget
 template <bool VEC, bool FAST>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_encode_f32(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_encode_f32(
     const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
 {
     const EncodeJob& job = jobs[wg_job[blockIdx.x]];
@@ -927,21 +948,20 @@ hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint
     return hipGetLastError();
 }
 
-size_t encode_lds_bytes(uint32_t nunits, uint32_t B, bool f64)
+size_t encode_lds_bytes(uint32_t nunits, uint32_t B, uint32_t m, bool f64)
 {
-    size_t planes = (size_t)(B + 1) * kTileBlocks * sizeof(uint32_t);
-    size_t ys = f64 ? 0 : (size_t)kTileBlocks * 36 * sizeof(float);
-    return (size_t)nunits * 256 * sizeof(uint32_t) + (planes > ys ? planes : ys);
+    (void)f64;
+    if (!f64 && B == 32 && m == 4) return 0;  // the fast path: static LDS only
+    const size_t planes = (size_t)(B + 1) * kTileBlocks * sizeof(uint32_t);
+    return (size_t)nunits * 256 * sizeof(uint32_t) + planes;
 }
 
-hipError_t encode_set_lds(uint32_t nunits, uint32_t B, bool f64)
+hipError_t encode_set_lds(uint32_t nunits, uint32_t B, uint32_t m, bool f64)
 {
-    const size_t shmem = encode_lds_bytes(nunits, B, f64);
-    if (shmem <= 64 * 1024) return hipSuccess;
-    const void* fns[4] = {f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true, false>,
-                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false, false>,
-                          f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true, true>,
-                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false, true>};
+    const size_t shmem = encode_lds_bytes(nunits, B, m, f64);
+    if (shmem <= 64 * 1024) return hipSuccess;  // the fast path always fits
+    const void* fns[2] = {f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true, false>,
+                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false, false>};
     for (const void* fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
@@ -954,7 +974,7 @@ hipError_t launch_encode_batch(const EncodeJob* jobs, const uint32_t* wg_job, ui
 {
     const bool fast = !f64 && B == 32 && m == 4;
     if (grid == 0) return hipSuccess;
-    const size_t shmem = encode_lds_bytes(nunits, B, f64);
+    const size_t shmem = encode_lds_bytes(nunits, B, m, f64);
     dim3 g(grid), b(kThreads);
     if (f64) {
         if (vec)

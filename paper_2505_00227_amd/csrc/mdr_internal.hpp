@@ -120,9 +120,9 @@ hipError_t launch_init_stats(LevelStats* st, int count, hipStream_t s);
 // statistics of every job; wg_job maps each of `grid` workgroups to its job
 hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                               bool vec, hipStream_t s);
-size_t encode_lds_bytes(uint32_t nunits, uint32_t B, bool f64);
+size_t encode_lds_bytes(uint32_t nunits, uint32_t B, uint32_t m, bool f64);
 // raise the encoder kernels' dynamic LDS limit (call outside graph capture)
-hipError_t encode_set_lds(uint32_t nunits, uint32_t B, bool f64);
+hipError_t encode_set_lds(uint32_t nunits, uint32_t B, uint32_t m, bool f64);
 hipError_t launch_encode_batch(const EncodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
                                uint32_t nunits, uint32_t B, uint32_t m, bool f64, bool vec, hipStream_t s);
 hipError_t launch_select_batch(const SelectParams& p, const SelectLevel* lv, uint32_t nlev,

@@ -494,7 +494,7 @@ mdr_status refactor_batch(mdr_context* ctx, const VarLevels* vars, uint32_t nvar
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(payloads)");
     }
     if (L.J == 0) return assemble(ctx, L, dtype, prm, nullptr, rows, pay, nvars, outs);
-    MDR_HIP(encode_set_lds(L.nunits, L.B, L.f64));
+    MDR_HIP(encode_set_lds(L.nunits, L.B, L.m, L.f64));
 
     // on failure after the first launch, let queued work end before the pool reuses the memory
     struct SyncOnFail {
