@@ -235,9 +235,6 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     const auto x = gmem(xg);
     const auto rows = gmem(job.rows);
     const auto recs = gmem(job.recs);
-    const auto key_part = gmem(job.key_part);
-    const auto hist = gmem(job.hist);
-    const auto trans_part = gmem(job.trans_part);
     if (tid < kMaxRows) s_hoff[tid] = job.hist_off[tid];
     (void)m;
     uint32_t* s_hist = FAST ? s_hist_fast : s_dyn;
@@ -568,16 +565,18 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         }
     }
     __syncthreads();
-    const auto kp = key_part + (uint64_t)wg * kKeyStride;
+    // fold this workgroup's results into the level totals (zeroed before the
+    // pass): key maxima (nonnegative float bits order as integers), nonzero
+    // byte counts and transitions
     if (tid < kKeyStride) {
-        if constexpr (F64)
-            kp[tid] = s_key64[tid];
-        else
-            kp[tid] = s_key32[tid];
+        const unsigned long long kv = F64 ? s_key64[tid] : (unsigned long long)s_key32[tid];
+        if (kv) atomicMax(&job.keys[tid], kv);
     }
-    const auto gh = hist + (uint64_t)wg * nunits * 256;
-    for (uint32_t i = tid; i < nunits * 256; i += kThreads) gh[i] = s_hist[i];
-    if (tid < kMaxRows) trans_part[(uint64_t)wg * kMaxRows + tid] = s_trans[tid];
+    for (uint32_t i = tid; i < nunits * 256; i += kThreads) {
+        const uint32_t hv = s_hist[i];
+        if (hv) atomicAdd(&job.hist[i], hv);
+    }
+    if (tid < kMaxRows && s_trans[tid]) atomicAdd(&job.trans[tid], s_trans[tid]);
 }
 
 // f32 fits five waves per SIMD (96 registers) with LDS to spare; f64 keeps
@@ -613,12 +612,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
     __shared__ unsigned long long s_w[512];
     __shared__ int s_parent[512];
     __shared__ int s_sorted[256];
+    __shared__ int s_dp[1024];  // depths and parents while measuring the tree
     __shared__ uint8_t s_len[256];
-    __shared__ uint32_t s_part[16][256];
     __shared__ unsigned long long s_red[kSelThreads / 64];
     __shared__ int s_nl, s_maxlen;
     __shared__ uint32_t s_count[33], s_first[33];
-    __shared__ unsigned long long s_kmax[kKeyStride];
 
     const SelectLevel& lv = levels[blockIdx.y];
     const uint32_t u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -633,7 +631,6 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             lv.lens[u * 256 + tid] = 0;
             lv.codes[u * 256 + tid] = 0;
         }
-        if (u == 0 && tid < kKeyStride) lv.keys[tid] = 0;
         if (tid == 0) {
             UnitInfo ui;
             ui.S = 0;
@@ -660,32 +657,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         return t;
     };
 
-    // ---- byte histogram: 16 slices of the per-workgroup partials; each thread
-    // sums four adjacent bins with 16-byte loads, two loads in flight
-    {
-        const uint32_t q4 = tid & 63, slice = tid >> 6;
-        const auto h = gmem(reinterpret_cast<const u32x4*>(lv.hist + (uint64_t)u * 256) + q4);
-        const uint64_t rowstride = (uint64_t)nunits * 256 / 4;
-        u32x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
-        uint32_t w = slice;
-        for (; w + 16 < grid; w += 32) {
-            const u32x4 p0 = h[(uint64_t)w * rowstride], p1 = h[(uint64_t)(w + 16) * rowstride];
-            a.x += p0.x, a.y += p0.y, a.z += p0.z, a.w += p0.w;
-            b.x += p1.x, b.y += p1.y, b.z += p1.z, b.w += p1.w;
-        }
-        for (; w < grid; w += 16) {
-            const u32x4 p0 = h[(uint64_t)w * rowstride];
-            a.x += p0.x, a.y += p0.y, a.z += p0.z, a.w += p0.w;
-        }
-        s_part[slice][4 * q4 + 0] = a.x + b.x;
-        s_part[slice][4 * q4 + 1] = a.y + b.y;
-        s_part[slice][4 * q4 + 2] = a.z + b.z;
-        s_part[slice][4 * q4 + 3] = a.w + b.w;
-    }
-    __syncthreads();
-    unsigned long long f = 0;
-    if (tid < 256)
-        for (int q = 0; q < 16; ++q) f += s_part[q][tid];
+    // ---- byte histogram (level totals from the encoder)
+    unsigned long long f = tid < 256 ? lv.hist[(uint64_t)u * 256 + tid] : 0;
     unsigned long long nz = block_sum((tid > 0 && tid < 256) ? f : 0);
     if (tid == 0) f = S - nz;  // zero bytes are not counted by the encoder
     if (tid < 256) {
@@ -693,31 +666,34 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         s_f0[tid] = f;
     }
 
-    // ---- runs of equal W-bit words: transitions inside workgroup ranges, at
-    // range boundaries, and between consecutive planes of the group
+    // ---- runs of equal W-bit words: transitions inside workgroup ranges (level
+    // totals from the encoder), at range boundaries, and between consecutive
+    // planes of the group
     const uint32_t nrow = r1 - r0;
-    unsigned long long tr = 0;
-    for (uint32_t i = tid; i < grid * nrow; i += kSelThreads)
-        tr += lv.trans_part[(uint64_t)(i / nrow) * kMaxRows + r0 + i % nrow];
-    if (u == 0) {
-        // error keys: maximum over the encoder's workgroups, every thread
-        // reading consecutive partials (the partials are [grid][kKeyStride])
-        if (tid < kKeyStride) s_kmax[tid] = 0;
-        __syncthreads();
-        const auto kp = gmem(lv.key_part);
-        const uint64_t total = (uint64_t)grid * kKeyStride;
-#pragma unroll 4
-        for (uint64_t i = tid; i < total; i += kSelThreads) atomicMax(&s_kmax[i % kKeyStride], kp[i]);
-        __syncthreads();
-        if (tid < kKeyStride && (tid <= B || tid == kKeyStride - 1)) lv.keys[tid] = s_kmax[tid];
-    }
-    for (uint32_t i = tid; i < (grid - 1) * nrow; i += kSelThreads) {
-        uint32_t w = 1 + i / nrow, r = r0 + i % nrow;
-        const uint32_t* cur = lv.recs + ((uint64_t)w * kMaxRows + r) * 2 * G;
-        const uint32_t* prv = lv.recs + ((uint64_t)(w - 1) * kMaxRows + r) * 2 * G;
-        bool ne = false;
-        for (uint32_t g = 0; g < G; ++g) ne = ne || cur[g] != prv[G + g];
-        tr += ne ? 1 : 0;
+    unsigned long long tr = tid < nrow ? lv.trans[r0 + tid] : 0;
+    {
+        // boundary i: first word(s) of range w = 1 + i / nrow against the last
+        // of range w - 1, row r0 + i % nrow; four boundaries per thread in flight
+        const auto recs = gmem(lv.recs);
+        const uint32_t nbnd = (grid - 1) * nrow;
+        for (uint32_t i0 = tid; i0 < nbnd; i0 += 4 * kSelThreads) {
+            uint32_t cw[4][2], pw[4][2];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t i = min(i0 + k * kSelThreads, nbnd - 1);
+                const uint32_t w = 1 + i / nrow, r = r0 + i % nrow;
+                const uint64_t cur = ((uint64_t)w * kMaxRows + r) * 2 * G;
+                const uint64_t prv = ((uint64_t)(w - 1) * kMaxRows + r) * 2 * G;
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    cw[k][g] = g < (int)G ? recs[cur + g] : 0u;
+                    pw[k][g] = g < (int)G ? recs[prv + G + g] : 0u;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k * kSelThreads < nbnd) tr += (cw[k][0] != pw[k][0] || cw[k][1] != pw[k][1]) ? 1 : 0;
+        }
     }
     for (uint32_t r = r0 + 1 + tid; r < r1; r += kSelThreads) {
         const uint32_t* cur = lv.recs + ((uint64_t)0 * kMaxRows + r) * 2 * G;
@@ -737,15 +713,27 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
     // ---- Huffman code lengths: two-queue tree, depths by pointer jumping, and
     // the per-length count adjustment when the tree is deeper than huf_lmax
     if (need_code) {
-        const unsigned long long ft = tid < 256 ? s_f[tid] : 0;
-        int rank = 0;
-        if (tid < 256 && ft) {
-            for (int q = 0; q < 256; ++q) {
-                unsigned long long fs = s_f[q];
-                rank += (fs && (fs < ft || (fs == ft && q < (int)tid))) ? 1 : 0;
+        // rank of each present symbol in (count, symbol) order: four threads
+        // per symbol, 64 comparisons each
+        {
+            const uint32_t sym = tid & 255, part = tid >> 8;
+            const unsigned long long fsym = s_f[sym];
+            if (tid < 256) s_dp[tid] = 0;
+            if (tid == 0) s_nl = 0;
+            __syncthreads();
+            if (fsym) {
+                int r = 0;
+#pragma unroll 16
+                for (int q = part * 64; q < (int)part * 64 + 64; ++q) {
+                    const unsigned long long fs = s_f[q];
+                    r += (fs && (fs < fsym || (fs == fsym && q < (int)sym))) ? 1 : 0;
+                }
+                if (r) atomicAdd(&s_dp[sym], r);
             }
+            __syncthreads();
         }
-        if (tid == 0) s_nl = 0;
+        const unsigned long long ft = tid < 256 ? s_f[tid] : 0;
+        const int rank = tid < 256 ? s_dp[tid] : 0;
         __syncthreads();
         if (tid < 256 && ft) {
             s_sorted[rank] = (int)tid;
@@ -756,20 +744,40 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         if (tid < nl) s_w[tid] = s_f[s_sorted[tid]];
         __syncthreads();
         if (tid == 0 && nl > 1) {
+            // leaves s_w[0, nl) ascending, merged nodes appended from nl; the
+            // two heads of each queue live in registers (an empty slot holds
+            // ~0, above any weight) and are refilled from LDS one pick ahead.
+            // A tie takes the leaf.
+            constexpr unsigned long long kNone = ~0ull;
             int q1 = 0, q2 = nl, next = nl;
+            unsigned long long l0 = s_w[0], l1 = s_w[1], i0 = kNone, i1 = kNone;
+            auto pick = [&](unsigned long long& wt) -> int {
+                int at;
+                if (l0 <= i0) {
+                    at = q1++;
+                    wt = l0;
+                    l0 = l1;
+                    l1 = q1 + 1 < nl ? s_w[q1 + 1] : kNone;
+                } else {
+                    at = q2++;
+                    wt = i0;
+                    i0 = i1;
+                    i1 = q2 + 1 < next ? s_w[q2 + 1] : kNone;
+                }
+                return at;
+            };
             while ((nl - q1) + (next - q2) > 1) {
-                int a, b;
-                if (q1 < nl && (q2 == next || s_w[q1] <= s_w[q2]))
-                    a = q1++;
-                else
-                    a = q2++;
-                if (q1 < nl && (q2 == next || s_w[q1] <= s_w[q2]))
-                    b = q1++;
-                else
-                    b = q2++;
-                s_w[next] = s_w[a] + s_w[b];
+                unsigned long long wa, wb;
+                const int a = pick(wa);
+                const int b = pick(wb);
+                const unsigned long long sum = wa + wb;
+                s_w[next] = sum;
                 s_parent[a] = next;
                 s_parent[b] = next;
+                if (q2 == next)
+                    i0 = sum;
+                else if (q2 + 1 == next)
+                    i1 = sum;
                 ++next;
             }
             s_parent[next - 1] = next - 1;  // the root points to itself
@@ -777,8 +785,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         __syncthreads();
         // depth of every node: d <- d + d[parent], parent <- parent[parent] (9 rounds for 511 nodes)
         const int nnodes = nl > 1 ? 2 * nl - 1 : 0;
-        int* s_d = reinterpret_cast<int*>(s_part);       // reuse: >= 512 ints
-        int* s_p = reinterpret_cast<int*>(s_part) + 512;
+        int* s_d = s_dp;
+        int* s_p = s_dp + 512;
         if (tid < nnodes) {
             s_p[tid] = s_parent[tid];
             s_d[tid] = (tid == (uint32_t)(nnodes - 1)) ? 0 : 1;
@@ -798,17 +806,13 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             }
             __syncthreads();
         }
-        if (tid == 0) {
-            int maxlen = 0;
-            if (nl == 1) {
-                int s0 = s_sorted[0];
-                s_len[s0] = 1;
-                s_len[s0 == 0 ? 1 : 0] = 1;
-                maxlen = 1;
-            }
-            for (int i = 0; i < nl && nl > 1; ++i) maxlen = s_d[i] > maxlen ? s_d[i] : maxlen;
-            s_maxlen = maxlen;
+        if (tid == 0 && nl == 1) {
+            int s0 = s_sorted[0];
+            s_len[s0] = 1;
+            s_len[s0 == 0 ? 1 : 0] = 1;
+            s_maxlen = 1;
         }
+        if (nl > 1 && tid < nl) atomicMax(&s_maxlen, s_d[tid]);  // leaves are nodes 0 .. nl-1
         __syncthreads();
         if (nl > 1 && s_maxlen <= (int)job.huf_lmax) {
             if (tid < nl) s_len[s_sorted[tid]] = (uint8_t)s_d[tid];
@@ -820,8 +824,25 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             __syncthreads();
             if (tid < nl) atomicAdd(&s_bits[s_d[tid]], 1u);
             __syncthreads();
-            if (tid == 0) {
-                for (int i = s_maxlen; i > (int)job.huf_lmax; --i) {
+            const int maxlen = s_maxlen;
+            if (maxlen < 64) {
+                // one wavefront, lane l holding the count of length l; j is the
+                // longest length below i - 1 with a code
+                if (wave == 0) {
+                    int b = (int)s_bits[lane];
+                    for (int i = maxlen; i > (int)job.huf_lmax; --i) {
+                        while (__builtin_amdgcn_readlane(b, i) > 0) {
+                            const unsigned long long nzm = __ballot(b != 0) & ((1ull << (i - 1)) - 1);
+                            if (!nzm) break;  // cannot happen for a full tree
+                            const int j = 63 - __clzll((long long)nzm);
+                            const int l = (int)lane;
+                            b += (l == i ? -2 : 0) + (l == i - 1 ? 1 : 0) + (l == j + 1 ? 2 : 0) + (l == j ? -1 : 0);
+                        }
+                    }
+                    s_bits[lane] = (uint32_t)b;
+                }
+            } else if (tid == 0) {
+                for (int i = maxlen; i > (int)job.huf_lmax; --i) {
                     while (s_bits[i] > 0) {
                         int j = i - 2;
                         while (s_bits[j] == 0) --j;
@@ -831,9 +852,9 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
                         s_bits[j] -= 1;
                     }
                 }
-                s_maxlen = (int)job.huf_lmax;
             }
             __syncthreads();
+            if (tid == 0) s_maxlen = (int)job.huf_lmax;
             if (tid < nl) {
                 const uint32_t pos = (uint32_t)(nl - 1) - tid;  // 0 = heaviest
                 uint32_t cum = 0, Lh = 1;
@@ -865,6 +886,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         uint32_t code = 0;
         if (L) {
             uint32_t before = 0;
+#pragma unroll 16
             for (uint32_t q = 0; q < tid; ++q) before += s_len[q] == L ? 1u : 0u;
             code = s_first[L] + before;
         }

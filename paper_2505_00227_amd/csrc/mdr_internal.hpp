@@ -61,10 +61,11 @@ struct EncodeJob {
     uint32_t wg_base;       // first workgroup of this job in its launch
     uint32_t* rows;         // [(B+1)][nbd]: row 0 sign, row 1+p plane p (bit B-1-p)
     LevelStats* stats;
-    uint32_t* hist;         // [grid][nunits][256] nonzero-byte counts
-    uint32_t* trans_part;   // [grid][kMaxRows] word transitions inside each workgroup's range
+    // level totals, zeroed before the pass; workgroups add (max) theirs in
+    uint32_t* hist;         // [nunits][256] nonzero-byte counts
+    uint32_t* trans;        // [kMaxRows] word transitions inside workgroup ranges
+    unsigned long long* keys;  // [kKeyStride] max error keys (float/double bits), small
     uint32_t* recs;         // [grid][kMaxRows][2G] first / last words of each workgroup's range
-    unsigned long long* key_part;  // [grid][kKeyStride] max error keys (float/double bits), small
     uint16_t hist_off[kMaxRows];   // row r -> its unit's histogram offset (unit * 256)
 };
 
@@ -73,11 +74,9 @@ struct SelectLevel {
     uint64_t nbd;           // 0 for an empty level
     uint32_t grid;          // workgroups of that level's encode job
     uint32_t pad;
-    const uint32_t* hist;   // [grid][nunits][256]
-    const uint32_t* trans_part;            // [grid][kMaxRows]
+    const uint32_t* hist;   // [nunits][256] level totals from the encoder
+    const uint32_t* trans;  // [kMaxRows] level totals from the encoder
     const uint32_t* recs;   // [grid][kMaxRows][2G]
-    const unsigned long long* key_part;    // [grid][kKeyStride]
-    unsigned long long* keys;              // [kKeyStride] reduced over workgroups
     UnitInfo* units;        // [nunits]
     uint8_t* lens;          // [nunits][256]
     uint32_t* codes;        // [nunits][256]

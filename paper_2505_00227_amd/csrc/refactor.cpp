@@ -103,7 +103,7 @@ struct JobPlan {
     uint32_t nbd = 0, ntiles = 0, tpw = 0, grid_e = 0, grid_s = 0;
     uint32_t wg_base_s = 0, wg_base_e = 0;
     bool vec = false;
-    uint64_t rows_off = 0, hist_off = 0, recs_off = 0, kpart_off = 0, trans_off = 0;
+    uint64_t rows_off = 0, hist_off = 0, recs_off = 0, trans_off = 0;
 };
 
 struct Layout {
@@ -115,7 +115,7 @@ struct Layout {
     // workspace: metadata block (read back in one copy), then scratch
     uint64_t o_stats = 0, o_keys = 0, o_units = 0, o_payoff = 0, o_ubytes = 0, o_counts = 0,
              meta_bytes = 0;
-    uint64_t o_lens = 0, o_codes = 0, o_hist = 0, o_recs = 0, o_kpart = 0, o_trans = 0, o_cbase = 0,
+    uint64_t o_lens = 0, o_codes = 0, o_hist = 0, o_recs = 0, o_trans = 0, o_tot_end = 0, o_cbase = 0,
              o_tbase = 0, o_cwords = 0, o_truns = 0, o_scan = 0, o_desc = 0, ws_bytes = 0;
     // descriptor (uploaded before every pass)
     uint64_t d_sjobs = 0, d_ejobs = 0, d_slev = 0, d_largs = 0, d_map[4] = {}, desc_bytes = 0;
@@ -161,7 +161,7 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
     // every encoder workgroup walks about the same number of tiles, so that a
     // batch of mixed level sizes finishes together
     const uint64_t tpw_all = std::max<uint64_t>(1, ceil_div(total_tiles, std::max<uint32_t>(1, ctx->enc_target_wg)));
-    uint64_t hist = 0, recs = 0, kpart = 0, trans = 0;
+    uint64_t hist = 0, recs = 0, trans = 0;
     for (JobPlan& jp : L.jobs) {
         if (jp.ntiles) {
             jp.tpw = (uint32_t)std::min<uint64_t>(jp.ntiles, tpw_all);
@@ -171,13 +171,11 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
         jp.rows_off = L.rows_bytes;
         L.rows_bytes += align256(4ull * (B + 1) * jp.nbd);
         jp.hist_off = hist;
-        hist += align256(4ull * jp.grid_e * L.nunits * 256);
+        hist += 4ull * L.nunits * 256;
         jp.recs_off = recs;
         recs += align256(4ull * jp.grid_e * kMaxRows * 2 * L.G);
-        jp.kpart_off = kpart;
-        kpart += align256(8ull * jp.grid_e * kKeyStride);
         jp.trans_off = trans;
-        trans += align256(4ull * jp.grid_e * kMaxRows);
+        trans += 4ull * kMaxRows;
         for (uint32_t i = 0; i < L.nunits; ++i) {
             const uint32_t r0 = i == 0 ? 0 : 1 + (i - 1) * L.m;
             const uint32_t r1 = i == 0 ? 1 : std::min(B + 1, r0 + L.m);
@@ -222,10 +220,10 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
     L.meta_bytes = o;
     L.o_lens = take(256ull * L.U);
     L.o_codes = take(1024ull * L.U);
-    L.o_hist = take(hist);
     L.o_recs = take(recs);
-    L.o_kpart = take(kpart);
+    L.o_hist = take(hist);  // level totals: histograms, then transitions, zeroed per pass
     L.o_trans = take(trans);
+    L.o_tot_end = o;
     L.o_cbase = take(4ull * (L.U + 1));
     L.o_tbase = take(4ull * (L.U + 1));
     L.o_cwords = take(4ull * (L.max_chunks + 1));
@@ -299,9 +297,9 @@ void fill_descriptor(const Layout& L, const mdr_codec_params& prm, uint8_t* ws, 
         e.rows = reinterpret_cast<uint32_t*>(rows_base + jp.rows_off);
         e.stats = stats + j;
         e.hist = reinterpret_cast<uint32_t*>(ws + L.o_hist + jp.hist_off);
-        e.trans_part = reinterpret_cast<uint32_t*>(ws + L.o_trans + jp.trans_off);
+        e.trans = reinterpret_cast<uint32_t*>(ws + L.o_trans + jp.trans_off);
         e.recs = reinterpret_cast<uint32_t*>(ws + L.o_recs + jp.recs_off);
-        e.key_part = reinterpret_cast<unsigned long long*>(ws + L.o_kpart + jp.kpart_off);
+        e.keys = reinterpret_cast<unsigned long long*>(ws + L.o_keys) + (uint64_t)j * kKeyStride;
         for (uint32_t r = 0; r <= L.B; ++r)
             e.hist_off[r] = (uint16_t)((r == 0 ? 0 : 1 + (r - 1) / L.m) * 256);
 
@@ -309,10 +307,8 @@ void fill_descriptor(const Layout& L, const mdr_codec_params& prm, uint8_t* ws, 
         s.nbd = jp.nbd;
         s.grid = jp.grid_e;
         s.hist = e.hist;
-        s.trans_part = e.trans_part;
+        s.trans = e.trans;
         s.recs = e.recs;
-        s.key_part = e.key_part;
-        s.keys = reinterpret_cast<unsigned long long*>(ws + L.o_keys) + (uint64_t)j * kKeyStride;
         s.units = reinterpret_cast<UnitInfo*>(ws + L.o_units) + (uint64_t)j * L.nunits;
         s.lens = ws + L.o_lens + (uint64_t)j * L.nunits * 256;
         s.codes = reinterpret_cast<uint32_t*>(ws + L.o_codes) + (uint64_t)j * L.nunits * 256;
@@ -357,6 +353,10 @@ mdr_status enqueue_pass(mdr_context* ctx, const Layout& L, const mdr_codec_param
     {
         StageTimer tm(tctx, MDR_STAGE_STATS, s);
         MDR_HIP(launch_init_stats(reinterpret_cast<LevelStats*>(ws + L.o_stats), (int)L.J, s));
+        // the encoder adds its workgroups' histograms, transitions and key
+        // maxima into zeroed level totals (fill kernels: safe under capture)
+        MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.o_keys), 2ull * kKeyStride * L.J, 0u, s));
+        MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.o_hist), (L.o_tot_end - L.o_hist) / 4, 0u, s));
         MDR_HIP(launch_stats_batch(sj, map[0], (uint32_t)L.map[0].size(), L.f64, false, s));
         MDR_HIP(launch_stats_batch(sj, map[1], (uint32_t)L.map[1].size(), L.f64, true, s));
     }
