@@ -211,7 +211,6 @@ double value_range(const mdr_refactored* r);
 constexpr int kDescSlots = 4;
 struct DescSlot {
     DevBuf dev;
-    DevBuf scratch;  // device-only working memory of the same launches
     void* host = nullptr;
     uint64_t bytes = 0;
     hipEvent_t done = nullptr;

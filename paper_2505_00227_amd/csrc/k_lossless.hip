@@ -512,73 +512,14 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
 }
 
 // ------------------------------------------------------------------ Huffman decode
-// A 2^lmax-entry table maps the next lmax bits to up to four symbols: every
-// code that lies wholly inside the window is decoded by one lookup (codes are
+// One thread per chunk, kThreads chunks per workgroup.  Every workgroup builds
+// the stream's decode table in LDS from the 256 code lengths of the header: a
+// 2^lmax-entry table mapping the next lmax bits to up to four symbols (every
+// code lying wholly inside the window is decoded by that one lookup; codes are
 // prefix-free, so the bits after a whole code do not change it).  Skewed
 // groups, whose frequent symbols have 1-3 bit codes, take a quarter of the
-// dependent lookups of a one-symbol table.  The table is built once per
-// stream (k_huf_table) and copied into LDS by every decoding workgroup.
-__global__ __launch_bounds__(kThreads) void k_huf_table(const DecodeJob* __restrict__ jobs)
-{
-    const DecodeJob& job = jobs[blockIdx.x];
-    const uint8_t* payload = job.payload;
-    const uint32_t lmax = job.lmax;
-    __shared__ uint16_t s_lut[1 << kLutBitsMax];  // (length << 8) | symbol
-    __shared__ uint8_t s_len[256];
-    __shared__ uint32_t s_count[33], s_first[33], s_offset[33];
-    __shared__ uint8_t s_sorted[256];
-    const uint32_t tid = threadIdx.x;
-    s_len[tid] = payload[8 + tid];
-    if (tid < 33) s_count[tid] = 0;
-    __syncthreads();
-    const uint32_t L = s_len[tid];
-    if (L && L <= lmax) atomicAdd(&s_count[L], 1u);
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t c = 0, o = 0;
-        for (int l = 1; l <= 32; ++l) {
-            s_first[l] = c;
-            s_offset[l] = o;
-            o += s_count[l];
-            c = (c + s_count[l]) << 1;
-        }
-    }
-    __syncthreads();
-    if (L && L <= lmax) {
-        uint32_t before = 0;
-        for (uint32_t s = 0; s < tid; ++s) before += s_len[s] == L ? 1u : 0u;
-        s_sorted[s_offset[L] + before] = (uint8_t)tid;
-    }
-    __syncthreads();
-    const uint32_t nent = 1u << lmax, mask = nent - 1;
-    for (uint32_t i = tid; i < nent; i += kThreads) {
-        uint16_t ent = (uint16_t)(lmax << 8);  // invalid prefix: consume lmax bits
-        for (uint32_t l = 1; l <= lmax; ++l) {
-            uint32_t p = i >> (lmax - l);
-            if (s_count[l] && p >= s_first[l] && p - s_first[l] < s_count[l]) {
-                ent = (uint16_t)((l << 8) | s_sorted[s_offset[l] + p - s_first[l]]);
-                break;
-            }
-        }
-        s_lut[i] = ent;
-    }
-    __syncthreads();
-    const auto table = gmem(job.table);
-    for (uint32_t i = tid; i < nent; i += kThreads) {
-        uint32_t syms = 0, k = 0, used = 0;
-        while (k < 4) {
-            const uint32_t e = s_lut[(i << used) & mask];
-            const uint32_t l = e >> 8;
-            if (used + l > lmax) break;  // the next code does not fit in the window
-            syms |= (e & 0xFFu) << (8 * k);
-            ++k;
-            used += l;
-        }
-        table[i] = (unsigned long long)syms | ((unsigned long long)k << 32) | ((unsigned long long)used << 35);
-    }
-}
-
-// One thread per chunk: symbols | count << 32 | bits << 35 per table entry.
+// dependent lookups of a one-symbol table.  Compressed words are loaded eight
+// ahead of their use, and decoded bytes leave in 16-byte stores.
 __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
                                                          const uint32_t* __restrict__ wg_job)
 {
@@ -586,58 +527,159 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     const uint8_t* payload = job.payload;
     const uint64_t S = job.S;
     const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
-    uint8_t* g = job.out;
     __shared__ unsigned long long s_multi[1 << kLutBitsMax];
-    const uint32_t tid = threadIdx.x;
-    {
-        const auto src = gmem(reinterpret_cast<const u32x4*>(job.table));
-        u32x4* dst = reinterpret_cast<u32x4*>(s_multi);
-        for (uint32_t i = tid; i < (1u << lmax) / 2; i += kThreads) dst[i] = src[i];
+    __shared__ uint16_t s_one[1 << kLutBitsMax];  // (length << 8) | symbol of the window's first code
+    __shared__ uint32_t s_wcnt[kThreads / 64][kLutBitsMax + 1];  // codes per length, per wavefront
+    __shared__ uint8_t s_sym[256];                // symbols in canonical (length, symbol) order
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nent = 1u << lmax, mask = nent - 1;
+
+    // ---- canonical code of symbol `tid`: the first code of its length plus
+    // the smaller symbols of that length (wavefront ballots, then the counts
+    // of the earlier wavefronts)
+    const uint32_t L = payload[8 + tid];
+    const bool has = L != 0 && L <= lmax;
+    uint32_t before = 0;
+    for (uint32_t l = 1; l <= lmax; ++l) {
+        const unsigned long long bl = __ballot(has && L == l);
+        if (lane == 0) s_wcnt[wave][l] = (uint32_t)__popcll(bl);
+        if (has && L == l) before = (uint32_t)__popcll(bl & ((1ull << lane) - 1));
     }
     __syncthreads();
+    // per length l (all in registers): lim[l] = end of the lmax-bit windows
+    // whose first code has length <= l (non-decreasing in l); base[l] = index
+    // of the first symbol of length l minus the first code of that length
+    uint32_t lim[kLutBitsMax + 1], base[kLutBitsMax + 1], lim_all = 0;
+    {
+        uint32_t first = 0, idx = 0;
+#pragma unroll
+        for (int l = 1; l <= kLutBitsMax; ++l) {
+            uint32_t cnt = 0;
+            if (l <= (int)lmax)
+                for (uint32_t w = 0; w < kThreads / 64; ++w) cnt += s_wcnt[w][l];
+            if (has && (uint32_t)l == L) {
+                for (uint32_t w = 0; w < wave; ++w) before += s_wcnt[w][l];
+                s_sym[idx + before] = (uint8_t)tid;
+            }
+            base[l] = idx - first;
+            lim[l] = l <= (int)lmax ? (first + cnt) << (lmax - l) : nent;
+            if (l == (int)lmax) lim_all = lim[l];
+            idx += cnt;
+            first = (first + cnt) << 1;
+        }
+    }
+    __syncthreads();
+    // ---- first code of every window (independent entries); a window that
+    // starts with no code (possible only for an incomplete code) consumes
+    // lmax bits as symbol 0
+    for (uint32_t i = tid; i < nent; i += kThreads) {
+        uint32_t Lx = 1, bx = base[1];
+#pragma unroll
+        for (int l = 1; l < kLutBitsMax; ++l) {
+            const bool past = l < (int)lmax && lim[l] <= i;
+            Lx += past ? 1u : 0u;
+            bx = past ? base[l + 1] : bx;
+        }
+        const bool code = i < lim_all;  // then Lx is the leading code's length
+        s_one[i] = code ? (uint16_t)((Lx << 8) | s_sym[bx + (i >> (lmax - Lx))]) : (uint16_t)(lmax << 8);
+    }
+    __syncthreads();
+    // ---- up to four whole codes per window: chains of first-code lookups,
+    // four windows at a time so their LDS latencies overlap
+    for (uint32_t i0 = tid; i0 < nent; i0 += 4 * kThreads) {
+        uint32_t syms[4] = {0, 0, 0, 0}, k[4] = {0, 0, 0, 0}, used[4] = {0, 0, 0, 0};
+        bool open[4] = {true, true, true, true};
+#pragma unroll
+        for (int step = 0; step < 4; ++step) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t i = i0 + q * kThreads;
+                if (!open[q] || i >= nent) continue;
+                const uint32_t e = s_one[(i << used[q]) & mask];
+                const uint32_t l = e >> 8;
+                if (used[q] + l > lmax) {
+                    open[q] = false;  // the next code does not fit in the window
+                    continue;
+                }
+                syms[q] |= (e & 0xFFu) << (8 * step);
+                ++k[q];
+                used[q] += l;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t i = i0 + q * kThreads;
+            if (i < nent)
+                s_multi[i] = (unsigned long long)syms[q] | ((unsigned long long)k[q] << 32) |
+                             ((unsigned long long)used[q] << 35);
+        }
+    }
+    __syncthreads();  // the last barrier
+
     const uint32_t c = (blockIdx.x - job.wg_base) * kThreads + tid;
     if (c >= nchunks) return;
     const auto off = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader));
     const auto words = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1)));
-    uint32_t wp = off[c];
-    const uint32_t wend = off[c + 1];
-    // four compressed words in flight: a refill consumes the oldest and issues
-    // the load of the word four refills ahead (the loads' latency overlaps decoding)
-    auto fetch = [&](uint32_t i) -> uint32_t { return i < wend ? words[i] : 0u; };
-    uint32_t q0 = fetch(wp), q1 = fetch(wp + 1), q2 = fetch(wp + 2), q3 = fetch(wp + 3);
-    wp += 4;
-    uint64_t buf = 0;
-    int nb = 0;
+    const uint32_t wb = off[c], we = off[c + 1];
+    // words past the chunk's end are never decoded: read the last one instead
+    const uint32_t wl = we > wb ? we - 1 : wb;
     const uint64_t lo = (uint64_t)c * chunk;
     const uint32_t cnt = (uint32_t)((lo + chunk <= S) ? chunk : S - lo);  // a multiple of 4
-    const auto dst = gmem(reinterpret_cast<uint32_t*>(g + lo));
-    uint64_t pend = 0;  // decoded bytes not yet stored (fewer than 4 between iterations)
-    uint32_t npend = 0, done = 0, wo = 0;
-    while (done < cnt) {
-        if (nb <= 32) {
-            buf |= (uint64_t)q0 << (32 - nb);
+    const auto dst4 = gmem(reinterpret_cast<u32x4*>(job.out + lo));
+    // eight compressed words in flight: refill j takes q[j] and reloads it with
+    // the word eight refills ahead (registers are never moved, so a refill
+    // waits only for its own, oldest load)
+    uint32_t q[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) q[j] = words[min(wb + j, wl)];
+    uint32_t wp = wb + 8;
+    uint64_t buf = 0;
+    int nb = 0;
+    uint64_t pend = 0;  // decoded bytes not yet in a whole word (fewer than 4 between iterations)
+    uint32_t npend = 0, done = 0, wo = 0, nob = 0;
+    u32x4 ob = {0, 0, 0, 0};  // whole words waiting for a 16-byte store
+    bool more = done < cnt;
+    while (more) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (!more) break;
+            buf |= (uint64_t)q[j] << (32 - nb);
             nb += 32;
-            q0 = q1;
-            q1 = q2;
-            q2 = q3;
-            q3 = fetch(wp);
+            q[j] = words[min(wp, wl)];
             ++wp;
-        }
-        const unsigned long long e = s_multi[buf >> (64 - lmax)];
-        const uint32_t k = min((uint32_t)(e >> 32) & 7u, cnt - done);
-        const uint32_t used = (uint32_t)(e >> 35);
-        const uint64_t syms = (uint64_t)(uint32_t)e & (k == 4 ? 0xFFFFFFFFull : ((1ull << (8 * k)) - 1));
-        pend |= syms << (8 * npend);
-        npend += k;
-        done += k;
-        buf <<= used;
-        nb -= (int)used;
-        if (npend >= 4) {
-            dst[wo++] = (uint32_t)pend;
-            pend >>= 32;
-            npend -= 4;
+            // more than 32 bits in the buffer: a whole window for every lookup
+            while (nb > 32 && done < cnt) {
+                const unsigned long long e = s_multi[buf >> (64 - lmax)];
+                const uint32_t k = min((uint32_t)(e >> 32) & 7u, cnt - done);
+                const uint32_t used = (uint32_t)(e >> 35);
+                const uint64_t syms = (uint64_t)(uint32_t)e & (k == 4 ? 0xFFFFFFFFull : ((1ull << (8 * k)) - 1));
+                pend |= syms << (8 * npend);
+                npend += k;
+                done += k;
+                buf <<= used;
+                nb -= (int)used;
+                if (npend >= 4) {
+                    const uint32_t w = (uint32_t)pend;
+                    ob.x = nob == 0 ? w : ob.x;
+                    ob.y = nob == 1 ? w : ob.y;
+                    ob.z = nob == 2 ? w : ob.z;
+                    ob.w = nob == 3 ? w : ob.w;
+                    pend >>= 32;
+                    npend -= 4;
+                    if (++nob == 4) {
+                        dst4[wo++] = ob;
+                        nob = 0;
+                    }
+                }
+            }
+            more = done < cnt;
         }
     }
+    // a chunk ends on a word; up to three whole words remain
+    const auto dst = gmem(reinterpret_cast<uint32_t*>(job.out + lo)) + 4 * wo;
+    if (nob > 0) dst[0] = ob.x;
+    if (nob > 1) dst[1] = ob.y;
+    if (nob > 2) dst[2] = ob.z;
 }
 
 // ------------------------------------------------------------------ RLE decode
@@ -723,7 +765,6 @@ hipError_t launch_huf_decode_batch(const DecodeJob* jobs, uint32_t njobs, const 
                                    uint32_t grid, hipStream_t s)
 {
     if (grid == 0 || njobs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_huf_table, dim3(njobs), dim3(kThreads), 0, s, jobs);
     hipLaunchKernelGGL(k_huf_decode, dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     return hipGetLastError();
 }

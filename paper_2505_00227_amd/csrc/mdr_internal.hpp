@@ -142,13 +142,11 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
 struct DecodeJob {
     const uint8_t* payload;
     uint8_t* out;           // S decoded bytes
-    unsigned long long* table;  // kDecodeTableBytes of scratch: the job's decode table
     uint64_t S;
     uint32_t nchunks, chunk, lmax;
     uint32_t wg_base;       // first workgroup of this job in the launch
 };
-constexpr uint64_t kDecodeTableBytes = 8ull << kLutBitsMax;
-// builds every job's table (one workgroup per job), then decodes (kThreads chunks per workgroup)
+// kThreads chunks per workgroup; each workgroup builds its job's decode table
 hipError_t launch_huf_decode_batch(const DecodeJob* jobs, uint32_t njobs, const uint32_t* wg_job,
                                    uint32_t grid, hipStream_t s);
 // RLE decode: payload u32 nruns | u32 wbytes | symbols[nruns] | u32 lengths[nruns]

@@ -15,7 +15,7 @@ namespace {
 
 // A descriptor slot: pinned host staging plus its device copy.  A slot is
 // reused only after the event recorded behind the kernels that read it.
-DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st, uint64_t scratch_bytes = 0)
+DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st)
 {
     DescSlot& d = ctx->ring[ctx->ring_next++ % kDescSlots];
     st = MDR_OK;
@@ -50,13 +50,6 @@ DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st, uint64_
             return nullptr;
         }
         d.bytes = want;
-    }
-    if (d.scratch.bytes < scratch_bytes) {
-        hipError_t e = d.scratch.alloc(scratch_bytes + scratch_bytes / 2);
-        if (e != hipSuccess) {
-            st = hip_fail(e, "hipMalloc(decode tables)");
-            return nullptr;
-        }
     }
     return &d;
 }
@@ -234,12 +227,8 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
     const uint64_t o_m1 = take(4 * map_r[1].size());
     if (o) {
         mdr_status st;
-        // decode tables: one per Huffman job, built once and copied by its workgroups
-        DescSlot* slot = acquire_slot(ctx, o, st, (uint64_t)dec.size() * kDecodeTableBytes);
+        DescSlot* slot = acquire_slot(ctx, o, st);
         if (!slot) return st;
-        for (size_t i = 0; i < dec.size(); ++i)
-            dec[i].table = reinterpret_cast<unsigned long long*>(static_cast<uint8_t*>(slot->scratch.p) +
-                                                                 i * kDecodeTableBytes);
         uint8_t* h = static_cast<uint8_t*>(slot->host);
         uint8_t* dv = static_cast<uint8_t*>(slot->dev.p);
         auto put = [&](uint64_t at, const void* src, uint64_t bytes) {
