@@ -162,8 +162,29 @@ __global__ __launch_bounds__(1024) void k_unit_plan(const LosslessArgs* __restri
     }
 }
 
-// code bits of every Huffman chunk -> chunk_words[c] (words), one wavefront per
-// chunk; each lane owns huf_chunk / 64 consecutive symbols (a multiple of 4 bytes)
+// Huffman chunks are split among wavefronts in contiguous shares; a wavefront
+// walks its share in batches of 64-word groups (a chunk of huf_chunk symbols is
+// huf_chunk / 256 groups; lane l holds word l of a group), eight groups in
+// flight, never crossing a unit.  Code lengths and codes of the current unit
+// are cached in LDS.
+constexpr uint32_t kHufGroups = 8;  // 64-word groups per batch
+
+__device__ __forceinline__ void wave_share(uint32_t total, uint32_t& c0, uint32_t& c1)
+{
+    const uint32_t nw = gridDim.x * (kThreads / 64), w = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const uint32_t per = (total + nw - 1) / nw;
+    c0 = min(w * per, total);
+    c1 = min(c0 + per, total);
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// code bits of every Huffman chunk -> chunk_words[c] (words)
 __global__ __launch_bounds__(kThreads) void k_huf_count(const LosslessArgs* __restrict__ Ap)
 {
     __shared__ uint32_t s_len[kThreads / 64][256];
@@ -172,32 +193,53 @@ __global__ __launch_bounds__(kThreads) void k_huf_count(const LosslessArgs* __re
     const uint32_t total = A.counts[0];
     if (blockIdx.x == 0 && tid == 0) A.chunk_words[total] = 0;
     uint32_t* L = s_len[wave];
-    uint32_t cached = 0xFFFFFFFFu, cb_lo = 1, cb_hi = 0;  // chunks [cb_lo, cb_hi) belong to `cached`
-    const uint32_t chunk = A.huf_chunk, per = chunk / 64;
-    for (uint32_t c = blockIdx.x * (kThreads / 64) + wave; c < total; c += gridDim.x * (kThreads / 64)) {
-        uint32_t u = cached;
+    const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;  // words, groups per chunk
+    const uint32_t cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;   // whole chunks per batch
+    uint32_t c0, c1;
+    wave_share(total, c0, c1);
+    uint32_t u = 0, cb_lo = 1, cb_hi = 0;  // chunks [cb_lo, cb_hi) belong to unit u
+    uint64_t nwu = 0;                      // words of unit u
+    for (uint32_t c = c0; c < c1;) {
         if (c < cb_lo || c >= cb_hi) {
             u = find_unit(A.chunk_base, A.U, c);
             cb_lo = A.chunk_base[u];
             cb_hi = A.chunk_base[u + 1];
+            nwu = A.units[u].S / 4;
             for (uint32_t k = lane; k < 256; k += 64) L[k] = A.lens[(uint64_t)u * 256 + k];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            cached = u;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         const auto g = gmem(unit_rows(A, u));
-        const uint64_t S = A.units[u].S;
-        const uint64_t lo = (uint64_t)(c - cb_lo) * chunk + (uint64_t)lane * per;
-        uint32_t bits = 0;
-        for (uint32_t q = 0; q < per; q += 4) {
-            if (lo + q >= S) break;
-            uint32_t w = g[(lo + q) / 4];
-            bits += L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
-        }
+        const uint32_t nbt = min(cpb, min(c1, cb_hi) - c);  // chunks in this batch
+        // one chunk of more than kHufGroups groups goes in several rounds
+        uint32_t acc = 0;
+        for (uint32_t r0 = 0; r0 < (wpl > kHufGroups ? wpl : 1); r0 += kHufGroups) {
+            const uint32_t ng = wpl > kHufGroups ? min(kHufGroups, wpl - r0) : nbt * wpl;
+            const uint64_t w0 = (uint64_t)(c - cb_lo) * cw + (uint64_t)r0 * 64 + lane;
+            uint32_t bits[kHufGroups];
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) bits += __shfl_xor(bits, o, 64);
-        if (lane == 0) A.chunk_words[c] = (bits + 31) / 32;
-        __builtin_amdgcn_wave_barrier();
+            for (uint32_t q = 0; q < kHufGroups; ++q) {
+                const uint64_t wi = w0 + q * 64;
+                const bool ok = q < ng && wi < nwu;
+                const uint32_t w = ok ? g[wi] : 0u;
+                bits[q] = ok ? L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24] : 0u;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < kHufGroups; ++q) bits[q] = wave_sum_u32(bits[q]);
+            if (wpl > kHufGroups) {
+#pragma unroll
+                for (uint32_t q = 0; q < kHufGroups; ++q) acc += bits[q];
+            } else {
+                // lane j < nbt: chunk c + j = groups [j wpl, (j + 1) wpl)
+                uint32_t tot = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < kHufGroups; ++q) tot += (q >= lane * wpl && q < (lane + 1) * wpl) ? bits[q] : 0u;
+                if (lane < nbt) A.chunk_words[c + lane] = (tot + 31) / 32;
+            }
+        }
+        if (wpl > kHufGroups && lane == 0) A.chunk_words[c] = (acc + 31) / 32;
+        c += nbt;
     }
 }
 
@@ -365,86 +407,116 @@ __global__ __launch_bounds__(1024) void k_unit_sizes(const LosslessArgs* __restr
     }
 }
 
-// Huffman payloads: one wavefront per chunk packs its codes in an LDS buffer
-// with atomic ORs, then stores the chunk's words; the first chunk's wave writes
-// the header and the last one the closing offset
+// Huffman payloads.  Per batch every chunk gets an LDS buffer: a lane's bits
+// start at the exclusive scan of its group plus the bits of the chunk's earlier
+// groups, codes go in with atomic ORs, and each chunk's words leave coalesced.
+// A chunk's wavefront writes its offset; the first chunk's the header, the last
+// one's the closing offset.
 __global__ __launch_bounds__(kThreads) void k_huf_write(const LosslessArgs* __restrict__ Ap,
                                                         uint32_t buf_words)
 {
-    extern __shared__ uint32_t s_buf[];  // [4][buf_words]
+    extern __shared__ uint32_t s_buf[];  // [kThreads / 64][cpb][buf_words]
     __shared__ uint32_t s_len[kThreads / 64][256], s_code[kThreads / 64][256];
     const LosslessArgs& A = *Ap;
     if (A.counts[2]) return;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = A.counts[0];
-    uint32_t* buf = s_buf + wave * buf_words;
     uint32_t* L = s_len[wave];
     uint32_t* C = s_code[wave];
-    uint32_t cached = 0xFFFFFFFFu, cb_lo = 1, cb_hi = 0;
-    const uint32_t chunk = A.huf_chunk, per = chunk / 64;
-    for (uint32_t c = blockIdx.x * (kThreads / 64) + wave; c < total; c += gridDim.x * (kThreads / 64)) {
-        uint32_t u = cached;
+    const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;
+    const uint32_t cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;
+    uint32_t* bufs = s_buf + wave * cpb * buf_words;
+    uint32_t c0, c1;
+    wave_share(total, c0, c1);
+    uint32_t u = 0, cb_lo = 1, cb_hi = 0;
+    uint64_t nwu = 0;
+    auto sync_wave = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (uint32_t c = c0; c < c1;) {
         if (c < cb_lo || c >= cb_hi) {
             u = find_unit(A.chunk_base, A.U, c);
             cb_lo = A.chunk_base[u];
             cb_hi = A.chunk_base[u + 1];
+            nwu = A.units[u].S / 4;
             for (uint32_t k = lane; k < 256; k += 64) {
                 L[k] = A.lens[(uint64_t)u * 256 + k];
                 C[k] = A.codes[(uint64_t)u * 256 + k];
             }
-            cached = u;
         }
-        for (uint32_t i = lane; i < buf_words; i += 64) buf[i] = 0;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-
+        const uint32_t nbt = min(cpb, min(c1, cb_hi) - c);
+        for (uint32_t i = lane; i < nbt * buf_words; i += 64) bufs[i] = 0;
+        sync_wave();
+        const auto g = gmem(unit_rows(A, u));
+        uint32_t run = 0;  // bits of the current chunk's earlier groups (wpl > kHufGroups)
+        for (uint32_t r0 = 0; r0 < (wpl > kHufGroups ? wpl : 1); r0 += kHufGroups) {
+            const uint32_t ng = wpl > kHufGroups ? min(kHufGroups, wpl - r0) : nbt * wpl;
+            const uint64_t w0 = (uint64_t)(c - cb_lo) * cw + (uint64_t)r0 * 64 + lane;
+            uint32_t wv[kHufGroups], pos[kHufGroups];
+            bool ok[kHufGroups];
+#pragma unroll
+            for (uint32_t q = 0; q < kHufGroups; ++q) {
+                const uint64_t wi = w0 + q * 64;
+                ok[q] = q < ng && wi < nwu;
+                wv[q] = ok[q] ? g[wi] : 0u;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < kHufGroups; ++q) {
+                const uint32_t w = wv[q];
+                const uint32_t bits = ok[q] ? L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24] : 0u;
+                const uint32_t inc = wave_incl_scan(bits, lane);
+                pos[q] = inc - bits;
+                const uint32_t gt = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);  // the group's bits
+                // group q starts a chunk when q is a multiple of wpl (batches of whole chunks)
+                if (wpl <= kHufGroups && q % wpl == 0) run = 0;
+                pos[q] += run;
+                run += gt;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < kHufGroups; ++q) {
+                if (!ok[q]) continue;
+                uint32_t* buf = bufs + (wpl <= kHufGroups ? (q / wpl) * buf_words : 0);
+                uint32_t p = pos[q];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const uint32_t sym = (wv[q] >> (8 * b)) & 0xFF;
+                    const uint32_t Ls = L[sym], cd = C[sym];
+                    const uint32_t wi = p >> 5, o = p & 31;
+                    if (o + Ls <= 32) {
+                        atomicOr(&buf[wi], cd << (32 - o - Ls));
+                    } else {
+                        atomicOr(&buf[wi], cd >> (o + Ls - 32));
+                        atomicOr(&buf[wi + 1], cd << (64 - o - Ls));
+                    }
+                    p += Ls;
+                }
+            }
+        }
+        sync_wave();
         const UnitInfo& ui = A.units[u];
-        const uint64_t S = ui.S;
-        const uint32_t nch = ui.nchunks, first = cb_lo, lc = c - first;
+        const uint32_t nch = ui.nchunks, first = cb_lo;
         uint8_t* pay = A.arena + A.pay_off[u];
         const auto off = gmem(reinterpret_cast<uint32_t*>(pay + kHufHeader));
         const auto words = off + nch + 1;
         const uint32_t base = A.chunk_words[first];
-        const uint32_t w0 = A.chunk_words[c] - base, nw = A.chunk_words[c + 1] - A.chunk_words[c];
-        const auto g = gmem(unit_rows(A, u));
-        const uint64_t lo = (uint64_t)lc * chunk + (uint64_t)lane * per;
-        uint32_t bits = 0;
-        for (uint32_t q = 0; q < per; q += 4) {
-            if (lo + q >= S) break;
-            uint32_t w = g[(lo + q) / 4];
-            bits += L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
-        }
-        uint32_t pos = wave_incl_scan(bits, lane) - bits;
-        for (uint32_t q = 0; q < per; q += 4) {
-            if (lo + q >= S) break;
-            uint32_t w = g[(lo + q) / 4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const uint32_t sym = (w >> (8 * b)) & 0xFF;
-                const uint32_t Ls = L[sym], cd = C[sym];
-                const uint32_t wi = pos >> 5, o = pos & 31;
-                if (o + Ls <= 32) {
-                    atomicOr(&buf[wi], cd << (32 - o - Ls));
-                } else {
-                    atomicOr(&buf[wi], cd >> (o + Ls - 32));
-                    atomicOr(&buf[wi + 1], cd << (64 - o - Ls));
-                }
-                pos += Ls;
+        for (uint32_t j = 0; j < nbt; ++j) {
+            const uint32_t cc = c + j, lc = cc - first;
+            const uint32_t w0 = A.chunk_words[cc] - base, nw = A.chunk_words[cc + 1] - A.chunk_words[cc];
+            const uint32_t* buf = bufs + j * buf_words;
+            for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = buf[i];
+            if (lane == 0) off[lc] = w0;
+            if (lc + 1 == nch && lane == 0) off[nch] = A.chunk_words[first + nch] - base;
+            if (lc == 0) {
+                if (lane == 0) *reinterpret_cast<uint64_t*>(pay) = ui.S;
+                const uint32_t b4 = lane * 4;
+                reinterpret_cast<uint32_t*>(pay + 8)[lane] =
+                    L[b4] | (L[b4 + 1] << 8) | (L[b4 + 2] << 16) | (L[b4 + 3] << 24);
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = buf[i];
-        if (lane == 0) off[lc] = w0;
-        if (lc + 1 == nch && lane == 0) off[nch] = A.chunk_words[first + nch] - base;
-        if (lc == 0) {
-            if (lane == 0) *reinterpret_cast<uint64_t*>(pay) = S;
-            const uint32_t b4 = lane * 4;
-            reinterpret_cast<uint32_t*>(pay + 8)[lane] =
-                L[b4] | (L[b4 + 1] << 8) | (L[b4 + 2] << 16) | (L[b4 + 3] << 24);
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        sync_wave();  // the buffers are cleared again by the next batch
+        c += nbt;
     }
 }
 
@@ -754,7 +826,8 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
     hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, a.tile_runs, a.counts + 1, part2);
     hipLaunchKernelGGL(k_unit_sizes, dim3(1), dim3(1024), 0, s, a_dev);
     const uint32_t buf_words = (a.huf_chunk * kLutBitsMax + 31) / 32 + 2;
-    const size_t shmem = 4ull * buf_words * sizeof(uint32_t);
+    const uint32_t wpl = a.huf_chunk / 256, cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;
+    const size_t shmem = (size_t)(kThreads / 64) * cpb * buf_words * sizeof(uint32_t);
     hipLaunchKernelGGL(k_huf_write, P, T, shmem, s, a_dev, buf_words);
     hipLaunchKernelGGL((k_rle_pass<false>), P, T, 0, s, a_dev);
     hipLaunchKernelGGL((k_rle_pass<true>), P, T, 0, s, a_dev);
