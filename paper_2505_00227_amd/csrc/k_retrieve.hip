@@ -76,6 +76,26 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
             v[t] = ((sgn >> t) & 1u) ? -a : a;
         }
     }
+    if constexpr (!F64) {
+        // a workgroup of full blocks writes its 8192 consecutive values through
+        // LDS, so that every store instruction covers 1 KiB of contiguous output
+        // (rows padded to 33 values: conflict-free on both sides)
+        __shared__ float s_out[kThreads * 33];
+        const uint32_t wblk0 = (blockIdx.x - j.wg_base) * kThreads;
+        if (vec && (uint64_t)(wblk0 + kThreads) * 32 <= n) {  // uniform; no thread returned early
+#pragma unroll
+            for (int t = 0; t < 32; ++t) s_out[threadIdx.x * 33 + t] = v[t];
+            __syncthreads();
+            const auto p = gmem(reinterpret_cast<f32x4*>(static_cast<float*>(j.out) + (uint64_t)wblk0 * 32));
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t i4 = q * kThreads + threadIdx.x;  // 16-byte slot of the workgroup's output
+                const uint32_t b = i4 >> 3, t = (i4 & 7) * 4;     // its block and first value
+                p[i4] = f32x4{s_out[b * 33 + t], s_out[b * 33 + t + 1], s_out[b * 33 + t + 2], s_out[b * 33 + t + 3]};
+            }
+            return;
+        }
+    }
     if (vec && cnt == 32) {
         if constexpr (F64) {
             const auto p = gmem(reinterpret_cast<f64x2*>(outg));
