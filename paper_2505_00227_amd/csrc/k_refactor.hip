@@ -255,6 +255,10 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     const uint32_t t0 = wg * tpw;
     const uint32_t t1 = min(ntiles, t0 + tpw);
     const uint32_t last_blk = min(nbd, t1 * kTileBlocks) - 1;
+    // the zeroed histograms and key maxima must be visible to every wave
+    // before any reads or updates them (the fast path has no barrier at the
+    // top of a tile)
+    __syncthreads();
 
     // ---- 32 consecutive values of tile tt (zeros past the level's end)
     auto load_tile = [&](uint32_t tt, T (&vv)[32]) {
