@@ -586,11 +586,12 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
 // ------------------------------------------------------------------ Huffman decode
 // One thread per chunk, kThreads chunks per workgroup.  Every workgroup builds
 // the stream's decode table in LDS from the 256 code lengths of the header: a
-// 2^lmax-entry table mapping the next lmax bits to up to four symbols (every
+// 2^lmax-entry table mapping the next lmax bits to up to three symbols (every
 // code lying wholly inside the window is decoded by that one lookup; codes are
 // prefix-free, so the bits after a whole code do not change it).  Skewed
-// groups, whose frequent symbols have 1-3 bit codes, take a quarter of the
-// dependent lookups of a one-symbol table.  Compressed words are loaded eight
+// groups, whose frequent symbols have 1-3 bit codes, take a third of the
+// dependent lookups of a one-symbol table; a 4-byte entry keeps the table at
+// 16 KiB, so that six workgroups fit a CU.  Compressed words are loaded eight
 // ahead of their use, and decoded bytes leave in 16-byte stores.
 __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
                                                          const uint32_t* __restrict__ wg_job)
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     const uint8_t* payload = job.payload;
     const uint64_t S = job.S;
     const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
-    __shared__ unsigned long long s_multi[1 << kLutBitsMax];
+    __shared__ uint32_t s_multi[1 << kLutBitsMax];  // symbols | count << 24 | bits << 26
     __shared__ uint16_t s_one[1 << kLutBitsMax];  // (length << 8) | symbol of the window's first code
     __shared__ uint32_t s_wcnt[kThreads / 64][kLutBitsMax + 1];  // codes per length, per wavefront
     __shared__ uint8_t s_sym[256];                // symbols in canonical (length, symbol) order
@@ -656,13 +657,13 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
         s_one[i] = code ? (uint16_t)((Lx << 8) | s_sym[bx + (i >> (lmax - Lx))]) : (uint16_t)(lmax << 8);
     }
     __syncthreads();
-    // ---- up to four whole codes per window: chains of first-code lookups,
+    // ---- up to three whole codes per window: chains of first-code lookups,
     // four windows at a time so their LDS latencies overlap
     for (uint32_t i0 = tid; i0 < nent; i0 += 4 * kThreads) {
         uint32_t syms[4] = {0, 0, 0, 0}, k[4] = {0, 0, 0, 0}, used[4] = {0, 0, 0, 0};
         bool open[4] = {true, true, true, true};
 #pragma unroll
-        for (int step = 0; step < 4; ++step) {
+        for (int step = 0; step < 3; ++step) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const uint32_t i = i0 + q * kThreads;
@@ -681,9 +682,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t i = i0 + q * kThreads;
-            if (i < nent)
-                s_multi[i] = (unsigned long long)syms[q] | ((unsigned long long)k[q] << 32) |
-                             ((unsigned long long)used[q] << 35);
+            if (i < nent) s_multi[i] = syms[q] | (k[q] << 24) | (used[q] << 26);
         }
     }
     __syncthreads();  // the last barrier
@@ -719,23 +718,19 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
             nb += 32;
             q[j] = words[min(wp, wl)];
             ++wp;
-            // more than 32 bits in the buffer: a whole window for every lookup
+            // more than 32 bits in the buffer: a whole window for every lookup.
+            // The last lookup may decode up to two symbols past the chunk's
+            // end; they never complete a word, so they are never stored.
             while (nb > 32 && done < cnt) {
-                const unsigned long long e = s_multi[buf >> (64 - lmax)];
-                const uint32_t k = min((uint32_t)(e >> 32) & 7u, cnt - done);
-                const uint32_t used = (uint32_t)(e >> 35);
-                const uint64_t syms = (uint64_t)(uint32_t)e & (k == 4 ? 0xFFFFFFFFull : ((1ull << (8 * k)) - 1));
-                pend |= syms << (8 * npend);
+                const uint32_t e = s_multi[buf >> (64 - lmax)];
+                const uint32_t k = (e >> 24) & 3u, used = e >> 26;
+                pend |= (uint64_t)(e & 0xFFFFFFu) << (8 * npend);  // bytes past the k symbols are 0
                 npend += k;
                 done += k;
                 buf <<= used;
                 nb -= (int)used;
                 if (npend >= 4) {
-                    const uint32_t w = (uint32_t)pend;
-                    ob.x = nob == 0 ? w : ob.x;
-                    ob.y = nob == 1 ? w : ob.y;
-                    ob.z = nob == 2 ? w : ob.z;
-                    ob.w = nob == 3 ? w : ob.w;
+                    ob = u32x4{ob.y, ob.z, ob.w, (uint32_t)pend};  // oldest word first once full
                     pend >>= 32;
                     npend -= 4;
                     if (++nob == 4) {
@@ -747,11 +742,19 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
             more = done < cnt;
         }
     }
-    // a chunk ends on a word; up to three whole words remain
+    // a chunk ends on a word; up to three whole words remain, the newest
+    // nob of ob (in order)
     const auto dst = gmem(reinterpret_cast<uint32_t*>(job.out + lo)) + 4 * wo;
-    if (nob > 0) dst[0] = ob.x;
-    if (nob > 1) dst[1] = ob.y;
-    if (nob > 2) dst[2] = ob.z;
+    if (nob == 3) {
+        dst[0] = ob.y;
+        dst[1] = ob.z;
+        dst[2] = ob.w;
+    } else if (nob == 2) {
+        dst[0] = ob.z;
+        dst[1] = ob.w;
+    } else if (nob == 1) {
+        dst[0] = ob.w;
+    }
 }
 
 // ------------------------------------------------------------------ RLE decode

@@ -342,6 +342,9 @@ void fill_descriptor(const Layout& L, const mdr_codec_params& prm, uint8_t* ws, 
 mdr_status enqueue_pass(mdr_context* ctx, const Layout& L, const mdr_codec_params& prm, uint8_t* ws,
                         uint8_t* stage, hipStream_t s, bool timed)
 {
+    // the launch checks read the thread's last HIP error: drop one left by a
+    // call outside this library (another runtime client on the thread)
+    (void)hipGetLastError();
     mdr_context* tctx = timed ? ctx : nullptr;
     uint8_t* desc = ws + L.o_desc;
     MDR_HIP(hipMemcpyAsync(desc, stage, L.desc_bytes, hipMemcpyHostToDevice, s));

@@ -71,6 +71,7 @@ DescSlot::~DescSlot()
 mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, hipStream_t s,
                          const ReconOnly* extra, size_t nextra)
 {
+    (void)hipGetLastError();  // as in enqueue_pass: only this call's launches are checked
     MDR_HIP(hipSetDevice(ctx->device));
     for (size_t t = 0; t < ntasks; ++t) {
         const mdr_refactored* r = tasks[t].rt->r;
@@ -280,6 +281,7 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
 mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const std::vector<bool>& f64,
                        unsigned long long* acc0, uint32_t nacc, hipStream_t s)
 {
+    (void)hipGetLastError();
     MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(acc0), 2ull * nacc, 0u, s));
     std::vector<QoiJob> js[2];
     std::vector<uint32_t> maps[2];
