@@ -65,6 +65,16 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t count, uint32_t value)
         p[i] = value;
 }
 
+// Copy from pinned host memory, read through its device address, into device
+// memory on the stream's own queue.  System-scope loads go past any cache the
+// host's writes could miss.
+__global__ void k_copy_in(const uint64_t* src, uint64_t* __restrict__ dst, uint64_t count)
+{
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void k_init_stats(LevelStats* st, int count)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -946,6 +956,19 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStrea
     if (count == 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(count, kThreads, 4096)), dim3(kThreads), 0, s, p,
                        count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_in(void* dst, const void* host, uint64_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 8) return hipErrorInvalidValue;
+    void* src = nullptr;
+    hipError_t e = hipHostGetDevicePointer(&src, const_cast<void*>(host), 0);
+    if (e != hipSuccess) return e;
+    const uint64_t count = bytes / 8;
+    hipLaunchKernelGGL(k_copy_in, dim3(grid_for(count, kThreads, 1024)), dim3(kThreads), 0, s,
+                       static_cast<const uint64_t*>(src), static_cast<uint64_t*>(dst), count);
     return hipGetLastError();
 }
 

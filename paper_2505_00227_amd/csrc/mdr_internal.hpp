@@ -115,6 +115,11 @@ struct LosslessArgs {
 
 // ---- launchers (k_refactor.hip) ----
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+// copy `bytes` (a multiple of 8) from pinned host memory (hipHostMalloc) to
+// device memory with a kernel on `s`: no copy-engine transfer, so the kernels
+// behind it start without waiting on another engine; under capture the kernel
+// reads the host memory at every replay
+hipError_t launch_copy_in(void* dst, const void* host, uint64_t bytes, hipStream_t s);
 hipError_t launch_init_stats(LevelStats* st, int count, hipStream_t s);
 // statistics of every job; wg_job maps each of `grid` workgroups to its job
 hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,

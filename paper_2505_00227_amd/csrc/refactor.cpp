@@ -347,7 +347,7 @@ mdr_status enqueue_pass(mdr_context* ctx, const Layout& L, const mdr_codec_param
     (void)hipGetLastError();
     mdr_context* tctx = timed ? ctx : nullptr;
     uint8_t* desc = ws + L.o_desc;
-    MDR_HIP(hipMemcpyAsync(desc, stage, L.desc_bytes, hipMemcpyHostToDevice, s));
+    MDR_HIP(launch_copy_in(desc, stage, L.desc_bytes, s));
     const StatsJob* sj = reinterpret_cast<const StatsJob*>(desc + L.d_sjobs);
     const EncodeJob* ej = reinterpret_cast<const EncodeJob*>(desc + L.d_ejobs);
     const SelectLevel* sl = reinterpret_cast<const SelectLevel*>(desc + L.d_slev);

@@ -241,7 +241,7 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
         put(o_md, map_dec.data(), 4 * map_dec.size());
         put(o_m0, map_r[0].data(), 4 * map_r[0].size());
         put(o_m1, map_r[1].data(), 4 * map_r[1].size());
-        MDR_HIP(hipMemcpyAsync(dv, h, o, hipMemcpyHostToDevice, s));
+        MDR_HIP(launch_copy_in(dv, h, o, s));
         if (!map_dec.empty()) {
             StageTimer tm(ctx, MDR_STAGE_HUF_DECODE, s);
             MDR_HIP(launch_huf_decode_batch(reinterpret_cast<const DecodeJob*>(dv + o_dec), (uint32_t)dec.size(),
@@ -312,7 +312,7 @@ mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const 
         if (!js[d].empty()) std::memcpy(h + oj[d], js[d].data(), sizeof(QoiJob) * js[d].size());
         if (!maps[d].empty()) std::memcpy(h + om[d], maps[d].data(), 4 * maps[d].size());
     }
-    MDR_HIP(hipMemcpyAsync(dv, h, o, hipMemcpyHostToDevice, s));
+    MDR_HIP(launch_copy_in(dv, h, o, s));
     for (int d = 0; d < 2; ++d)
         MDR_HIP(launch_qoi_vtotal_batch(reinterpret_cast<const QoiJob*>(dv + oj[d]),
                                         reinterpret_cast<const uint32_t*>(dv + om[d]), (uint32_t)maps[d].size(),
