@@ -299,7 +299,10 @@ void mdr_pipeline_destroy(mdr_pipeline* p);
  * result depends only on its own tolerance and starting planes: it is the same,
  * bit for bit, alone or in any mix, and equal to mdr_retrieve /
  * mdr_retrieve_qoi_vtotal from the same planes.  The server uses a context of
- * its own on ctx's device; fields must outlive the server.
+ * its own on ctx's device; fields must outlive the server.  Each output
+ * component is one device block (one field's reconstruction); released blocks
+ * are kept for the next request and reused, so the device memory the server
+ * holds for outputs never exceeds hbm_budget and steady serving allocates none.
  */
 typedef struct mdr_server mdr_server;
 
@@ -333,6 +336,7 @@ typedef struct {
     uint64_t steps;          /* engine steps so far                                                */
     uint64_t step_requests;  /* sum over steps of the requests advanced (batching depth)           */
     uint64_t hbm_in_use, hbm_budget;
+    uint64_t hbm_held;       /* output blocks allocated (in use, or kept for reuse): <= hbm_budget */
 } mdr_server_info;
 
 mdr_status mdr_server_create(mdr_context* ctx, uint64_t hbm_budget, uint32_t max_slots, mdr_server** out);

@@ -89,7 +89,7 @@ class mdr_completion(C.Structure):
 class mdr_server_info(C.Structure):
     _fields_ = [("pending", C.c_uint32), ("active", C.c_uint32), ("completed_unreleased", C.c_uint32),
                 ("pad", C.c_uint32), ("steps", C.c_uint64), ("step_requests", C.c_uint64),
-                ("hbm_in_use", C.c_uint64), ("hbm_budget", C.c_uint64)]
+                ("hbm_in_use", C.c_uint64), ("hbm_budget", C.c_uint64), ("hbm_held", C.c_uint64)]
 
 
 class mdr_pipeline_info(C.Structure):

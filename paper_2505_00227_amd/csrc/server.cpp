@@ -42,8 +42,8 @@ struct Req {
     std::vector<uint32_t> k[3];      // planes per level (current plan)
     std::vector<uint32_t> kdone[3];  // planes already in the output
     std::vector<uint32_t> kstart[3]; // planes held by the parent session at the start
-    PoolBuf out;
-    uint64_t need = 0;               // budget charged for the outputs
+    void* out[3] = {nullptr, nullptr, nullptr};  // one device block per component
+    uint64_t need = 0;               // budget charged for the outputs (all blocks)
     std::vector<void*> outp[3];
     double tol_abs = 0.0, eps[3] = {0, 0, 0}, est = 0.0;
     uint32_t it = 0;
@@ -77,12 +77,24 @@ struct mdr_server {
     std::deque<mdr_completion> completions;      // not yet polled
     std::unordered_map<uint64_t, int> state;     // ticket -> 0 pending, 1 active, 2 done/released
     std::unordered_map<uint64_t, std::vector<uint32_t>> final_k;  // ticket -> planes at completion (3 x nlevels)
+    // Output blocks (one component's reconstruction each) of released
+    // requests, kept by size for the next block of that size: serving then
+    // allocates and frees no device memory in steady state (a free would also
+    // wait for the whole device).  `held` counts every output block, in use or
+    // kept; it never exceeds the budget.
+    std::multimap<uint64_t, void*> spare;
+    uint64_t held = 0;
     uint64_t steps = 0, step_requests = 0;
     DevBuf acc;                                  // V_total accumulators, one per active request
     void* acc_host = nullptr;
 };
 
 namespace {
+
+// bytes of one component's output block (all levels, each 256-byte aligned)
+uint64_t block_bytes(const mdr_server* S, uint32_t field) { return S->fields[field].out_bytes; }
+
+void keep_blocks(mdr_server* S, Req* q);
 
 void complete(mdr_server* S, Req* q, mdr_status st)
 {
@@ -99,7 +111,7 @@ void complete(mdr_server* S, Req* q, mdr_status st)
     S->completions.push_back(q->c);
     if (st != MDR_OK) {
         S->in_use -= q->need;
-        q->out.reset();
+        keep_blocks(S, q);
         delete q;
     } else {
         S->done[q->ticket] = q;
@@ -107,18 +119,63 @@ void complete(mdr_server* S, Req* q, mdr_status st)
     S->cv.notify_all();
 }
 
+// a request's blocks back to the kept ones (caller holds the mutex)
+void keep_blocks(mdr_server* S, Req* q)
+{
+    for (int c = 0; c < 3; ++c)
+        if (q->out[c]) {
+            S->spare.emplace(block_bytes(S, q->field[c]), q->out[c]);
+            q->out[c] = nullptr;
+        }
+}
+
+// an output block of `need` bytes: a kept one of that size, else a new one
+// after giving back kept blocks (largest first) until it fits the budget
+mdr_status take_block(mdr_server* S, uint64_t need, void** p)
+{
+    *p = nullptr;
+    std::vector<void*> drop;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->spare.find(need);
+        if (it != S->spare.end()) {
+            *p = it->second;
+            S->spare.erase(it);
+            return MDR_OK;
+        }
+        while (S->held + need > S->budget && !S->spare.empty()) {
+            auto last = std::prev(S->spare.end());
+            S->held -= last->first;
+            drop.push_back(last->second);
+            S->spare.erase(last);
+        }
+        S->held += need;  // the blocks in use are the admitted outputs: within the budget
+    }
+    for (void* d : drop) (void)hipFree(d);
+    hipError_t e = hipMalloc(p, need);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->held -= need;
+        return hip_fail(e, "hipMalloc(request outputs)");
+    }
+    return MDR_OK;
+}
+
 // set up a request at admission: outputs, starting planes, first plan
 mdr_status start(mdr_server* S, Req* q)
 {
     const Field& f0 = S->fields[q->field[0]];
     const size_t nl = f0.r->levels.size();
-    hipError_t e = q->out.alloc(S->ctx->pool, f0.out_bytes * q->ncomp);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(request outputs)");
-    uint8_t* base = static_cast<uint8_t*>(q->out.p);
+    for (int c = 0; c < q->ncomp; ++c) {
+        mdr_status bst = take_block(S, block_bytes(S, q->field[c]), &q->out[c]);
+        if (bst) return bst;
+    }
     for (int c = 0; c < q->ncomp; ++c) {
         const mdr_refactored* r = S->fields[q->field[c]].r;
+        uint8_t* base = static_cast<uint8_t*>(q->out[c]);
         q->outp[c].resize(nl);
-        uint64_t o = f0.out_bytes * c;
+        uint64_t o = 0;
         for (size_t l = 0; l < nl; ++l) {
             q->outp[c][l] = base + o;
             o += align256(r->levels[l].n * (r->dtype == MDR_F64 ? 8 : 4));
@@ -319,7 +376,8 @@ void engine_main(mdr_server* S)
                     ++it;
                     continue;
                 }
-                const uint64_t need = align256(S->fields[q->field[0]].out_bytes * q->ncomp);
+                uint64_t need = 0;
+                for (int c = 0; c < q->ncomp; ++c) need += block_bytes(S, q->field[c]);
                 if (S->in_use + need > S->budget) break;
                 S->in_use += need;
                 q->need = need;
@@ -433,7 +491,8 @@ mdr_status mdr_server_submit(mdr_server* S, const mdr_request* rq, uint64_t* tic
                     return fail(MDR_ERR_INVALID_ARG, "QoI fields must hold the same points per level");
         }
     }
-    const uint64_t need = align256(S->fields[rq->field[0]].out_bytes * ncomp);
+    uint64_t need = 0;
+    for (int c = 0; c < ncomp; ++c) need += block_bytes(S, rq->field[c]);
     if (need > S->budget) return fail(MDR_ERR_INVALID_ARG, "the request's outputs exceed the HBM budget");
     if (rq->parent && !S->state.count(rq->parent)) return fail(MDR_ERR_INVALID_ARG, "unknown parent ticket");
     auto* q = new Req();
@@ -484,7 +543,7 @@ mdr_status mdr_server_release(mdr_server* S, uint64_t ticket)
     if (it == S->done.end()) return fail(MDR_ERR_INVALID_ARG, "no completed, unreleased request with this ticket");
     Req* q = it->second;
     S->in_use -= q->need;
-    q->out.reset();
+    keep_blocks(S, q);
     delete q;
     S->done.erase(it);
     S->cv.notify_all();
@@ -502,6 +561,7 @@ mdr_status mdr_server_stats(mdr_server* S, mdr_server_info* info)
     info->step_requests = S->step_requests;
     info->hbm_in_use = S->in_use;
     info->hbm_budget = S->budget;
+    info->hbm_held = S->held;
     return MDR_OK;
 }
 
@@ -517,8 +577,15 @@ void mdr_server_destroy(mdr_server* S)
     (void)hipSetDevice(S->ctx->device);
     (void)hipStreamSynchronize(S->stream);
     for (Req* q : S->pending) delete q;
-    for (Req* q : S->active) delete q;
-    for (auto& kv : S->done) delete kv.second;
+    for (Req* q : S->active) {
+        keep_blocks(S, q);
+        delete q;
+    }
+    for (auto& kv : S->done) {
+        keep_blocks(S, kv.second);
+        delete kv.second;
+    }
+    for (auto& kv : S->spare) (void)hipFree(kv.second);
     for (Field& f : S->fields) mdr_retriever_destroy(f.cache);
     if (S->acc_host) (void)hipHostFree(S->acc_host);
     S->acc.reset();

@@ -86,7 +86,7 @@ def _wait(mdr, srv, reqs_by_ticket, want, timeout=60.0):
                 srv.release(c["ticket"])
             got[c["ticket"]] = (c, outs)
         st = srv.stats()
-        assert st["hbm_in_use"] <= st["hbm_budget"]
+        assert st["hbm_in_use"] <= st["hbm_budget"] and st["hbm_held"] <= st["hbm_budget"]
         assert time.time() - t0 < timeout, ("server did not finish", len(got), want, st)
         time.sleep(0.001)
     return got
@@ -161,4 +161,24 @@ def test_rejects_requests_beyond_budget(mdr, setup):
     with pytest.raises(mdr.MdrError) as ei:
         srv.submit(mdr.MDR_REQ_FIELD, [0], 1e-3)
     assert ei.value.status == mdr.MDR_ERR_INVALID_ARG
+    srv.close()
+
+
+def test_output_blocks_are_reused(mdr, setup):
+    """Released outputs are kept and reused: serving one request at a time holds
+    one block per component of the largest request so far, and never more than
+    the budget."""
+    ctx, raw, rs, orc = setup
+    block = sum((4 * n + 255) // 256 * 256 for n in SIZES)
+    srv = mdr.Server(ctx, hbm_budget=4 * block, max_slots=4)
+    for r in rs:
+        srv.add_field(r)
+    held = []
+    for i, kind in enumerate(["raw", "raw", "qoi", "raw", "qoi", "raw"]):
+        q = {"kind": kind, "field": i % 4, "tol": 1e-3 if kind == "raw" else 1e-2, "parent": None}
+        t = _submit(mdr, srv, q, [])
+        c, _ = _wait(mdr, srv, {t: q}, 1)[t]
+        assert c["status"] == 0, (q, c)
+        held.append(srv.stats()["hbm_held"])
+    assert held == [block, block, 3 * block, 3 * block, 3 * block, 3 * block], held
     srv.close()
