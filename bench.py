@@ -187,7 +187,7 @@ def bench_batched(args):
         # launch-shape sweep (results are identical for every shape; only time changes)
         best = None
         for tgt in (768, 1536, 2304, 4608, 9216):
-            for sv in (4096, 16384, 65536):
+            for sv in (16384, 65536, 262144):
                 ctx.set_launch(enc_target_wg=tgt, stats_wg_values=sv, graphs=1)
                 t = []
                 for _ in range(2):

@@ -119,7 +119,8 @@ mdr_status mdr_context_timing(mdr_context* ctx, double* ms, uint64_t* launches, 
  * depend on them, bit for bit):
  *   enc_target_wg   encoder workgroups a pass aims for (tiles of 256 blocks are
  *                   split evenly among them); 64..65536, default 2304;
- *   stats_wg_values values per statistics workgroup; 1024..2^24, default 16384.
+ *   stats_wg_values values per statistics workgroup (at most 256 workgroups
+ *                   per level); 1024..2^24, default 65536.
  * Zero leaves a knob unchanged.  `graphs` (0/1, -1 = unchanged): whether
  * mdr_refactor_batch captures and replays HIP graphs (default 1). */
 mdr_status mdr_context_set_launch(mdr_context* ctx, uint32_t enc_target_wg, uint32_t stats_wg_values,

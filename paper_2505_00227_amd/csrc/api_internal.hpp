@@ -256,7 +256,7 @@ struct mdr_context {
     mdr::DevBuf qacc;  // V_total estimate accumulator
     // batch refactor: launch shape and captured graphs
     uint32_t enc_target_wg = 2304;   // encoder workgroups a batch aims for
-    uint32_t stats_wg_values = 16384;  // values per statistics workgroup
+    uint32_t stats_wg_values = 65536;  // values per statistics workgroup (at most kStatsMaxWg per level)
     bool graphs = true;
     hipStream_t capture_stream = nullptr;
     std::vector<std::unique_ptr<mdr::BatchGraph>> graph_cache;

@@ -185,10 +185,9 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 }
 
 // code bits of every Huffman chunk -> chunk_words[c] (words)
-__global__ __launch_bounds__(kThreads) void k_huf_count(const LosslessArgs* __restrict__ Ap)
+__device__ __forceinline__ void huf_count_body(const LosslessArgs& A)
 {
     __shared__ uint32_t s_len[kThreads / 64][256];
-    const LosslessArgs& A = *Ap;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = A.counts[0];
     if (blockIdx.x == 0 && tid == 0) A.chunk_words[total] = 0;
@@ -251,10 +250,9 @@ __device__ __forceinline__ bool word_ne(const uint32_t* g, uint64_t i, uint64_t 
     return ne;
 }
 
-__global__ __launch_bounds__(kThreads) void k_rle_count(const LosslessArgs* __restrict__ Ap)
+__device__ __forceinline__ void rle_count_body(const LosslessArgs& A)
 {
     __shared__ uint32_t s_red[kThreads / 64];
-    const LosslessArgs& A = *Ap;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = A.counts[1];
     if (blockIdx.x == 0 && tid == 0) A.tile_runs[total] = 0;
@@ -284,9 +282,18 @@ __global__ __launch_bounds__(kThreads) void k_rle_count(const LosslessArgs* __re
     }
 }
 
-// Exclusive scan, in place, of the first counts[which] + 1 entries of data, with
-// a fixed grid: per-workgroup range sums, one scan of the sums, then each range
-// rescanned from its base.
+// Both statistics of the planned units in one launch: Huffman chunk sizes, then
+// run counts per run-length tile.
+__global__ __launch_bounds__(kThreads) void k_counts(const LosslessArgs* __restrict__ Ap)
+{
+    const LosslessArgs& A = *Ap;
+    huf_count_body(A);
+    rle_count_body(A);
+}
+
+// Exclusive scans, in place, of the first *count[a] + 1 entries of data[a] for
+// both arrays at once, with a fixed grid: per-workgroup range sums, one scan of
+// the sums, then each range rescanned from its base.
 constexpr int kScanDevTile = kThreads * 4;
 
 __device__ __forceinline__ void dev_range(uint32_t n, uint32_t& lo, uint32_t& hi)
@@ -296,46 +303,55 @@ __device__ __forceinline__ void dev_range(uint32_t n, uint32_t& lo, uint32_t& hi
     hi = min(n, lo + per);
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_dev_part(const uint32_t* __restrict__ data,
-                                                            const uint32_t* __restrict__ count,
-                                                            uint32_t* __restrict__ part)
-{
-    __shared__ uint32_t s_red[kThreads / 64];
-    const uint32_t n = *count + 1;
-    uint32_t lo, hi;
-    dev_range(n, lo, hi);
-    uint32_t sum = 0;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += kThreads) sum += data[i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
-}
+struct ScanPair {
+    uint32_t* data[2];
+    const uint32_t* count[2];
+    uint32_t* part[2];  // [gridDim.x] range sums, then their exclusive scan
+};
 
-__global__ __launch_bounds__(1024) void k_scan_dev_mid(uint32_t* part, uint32_t np)
+__global__ __launch_bounds__(kThreads) void k_scan_dev_part(const ScanPair sp)
 {
-    __shared__ uint64_t s_wave[16];
-    uint64_t carry = 0;
-    for (uint32_t b = 0; b < np; b += 1024) {
-        const uint32_t i = b + threadIdx.x;
-        const uint64_t v = i < np ? part[i] : 0;
-        uint64_t ex;
-        const uint64_t t = block_scan64<1024>(v, s_wave, ex);
-        if (i < np) part[i] = (uint32_t)(carry + ex);
-        carry += t;
+    __shared__ uint32_t s_red[2][kThreads / 64];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const uint32_t n = *sp.count[a] + 1;
+        const uint32_t* data = sp.data[a];
+        uint32_t lo, hi;
+        dev_range(n, lo, hi);
+        uint32_t sum = 0;
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += kThreads) sum += data[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if ((threadIdx.x & 63) == 0) s_red[a][threadIdx.x >> 6] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const uint32_t a = threadIdx.x;
+        sp.part[a][blockIdx.x] = s_red[a][0] + s_red[a][1] + s_red[a][2] + s_red[a][3];
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_scan_dev_fin(uint32_t* __restrict__ data,
-                                                           const uint32_t* __restrict__ count,
-                                                           const uint32_t* __restrict__ part)
+__global__ __launch_bounds__(1024) void k_scan_dev_mid(const ScanPair sp, uint32_t np)
 {
-    __shared__ uint32_t s_wave[kThreads / 64];
-    const uint32_t n = *count + 1;
-    uint32_t lo, hi;
-    dev_range(n, lo, hi);
-    uint32_t carry = part[blockIdx.x];
+    __shared__ uint64_t s_wave[16];
+    for (int a = 0; a < 2; ++a) {
+        uint32_t* part = sp.part[a];
+        uint64_t carry = 0;
+        for (uint32_t b = 0; b < np; b += 1024) {
+            const uint32_t i = b + threadIdx.x;
+            const uint64_t v = i < np ? part[i] : 0;
+            uint64_t ex;
+            const uint64_t t = block_scan64<1024>(v, s_wave, ex);
+            if (i < np) part[i] = (uint32_t)(carry + ex);
+            carry += t;
+        }
+    }
+}
+
+// data[lo, hi) -> its exclusive scan plus carry, a tile of kScanDevTile at a time
+__device__ __forceinline__ void scan_range(uint32_t* __restrict__ data, uint32_t lo, uint32_t hi,
+                                           uint32_t carry, uint32_t* s_wave)
+{
     for (uint32_t b = lo; b < hi; b += kScanDevTile) {
         const uint32_t i0 = b + threadIdx.x * 4;
         uint32_t v[4], sum = 0;
@@ -353,6 +369,19 @@ __global__ __launch_bounds__(kThreads) void k_scan_dev_fin(uint32_t* __restrict_
             excl += v[j];
         }
         carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_dev_fin(const ScanPair sp)
+{
+    __shared__ uint32_t s_wave[kThreads / 64];
+    for (int a = 0; a < 2; ++a) {
+        uint32_t* __restrict__ data = sp.data[a];
+        const uint32_t n = *sp.count[a] + 1;
+        uint32_t lo, hi;
+        dev_range(n, lo, hi);
+        uint32_t carry = sp.part[a][blockIdx.x];
+        scan_range(data, lo, hi, carry, s_wave);
     }
 }
 
@@ -412,12 +441,10 @@ __global__ __launch_bounds__(1024) void k_unit_sizes(const LosslessArgs* __restr
 // groups, codes go in with atomic ORs, and each chunk's words leave coalesced.
 // A chunk's wavefront writes its offset; the first chunk's the header, the last
 // one's the closing offset.
-__global__ __launch_bounds__(kThreads) void k_huf_write(const LosslessArgs* __restrict__ Ap,
-                                                        uint32_t buf_words)
+__device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t buf_words)
 {
     extern __shared__ uint32_t s_buf[];  // [kThreads / 64][cpb][buf_words]
     __shared__ uint32_t s_len[kThreads / 64][256], s_code[kThreads / 64][256];
-    const LosslessArgs& A = *Ap;
     if (A.counts[2]) return;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = A.counts[0];
@@ -527,10 +554,9 @@ __global__ __launch_bounds__(kThreads) void k_huf_write(const LosslessArgs* __re
 constexpr int kRlePer = kRleTileWords / kThreads;  // consecutive words per thread
 
 template <bool LEN>
-__global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __restrict__ Ap)
+__device__ __forceinline__ void rle_pass_body(const LosslessArgs& A)
 {
     __shared__ uint32_t s_wave[kThreads / 64];
-    const LosslessArgs& A = *Ap;
     if (A.counts[2]) return;
     const uint32_t tid = threadIdx.x;
     const uint32_t total = A.counts[1], G = A.G;
@@ -581,6 +607,21 @@ __global__ __launch_bounds__(kThreads) void k_rle_pass(const LosslessArgs* __res
             }
         }
     }
+}
+
+// Payload writes: Huffman streams, then the first run-length pass (the two
+// touch different units).
+__global__ __launch_bounds__(kThreads) void k_write(const LosslessArgs* __restrict__ Ap, uint32_t buf_words)
+{
+    const LosslessArgs& A = *Ap;
+    huf_write_body(A, buf_words);
+    rle_pass_body<false>(A);
+}
+
+// the second run-length pass (lengths); it reads starts other workgroups wrote
+__global__ __launch_bounds__(kThreads) void k_rle_len(const LosslessArgs* __restrict__ Ap)
+{
+    rle_pass_body<true>(*Ap);
 }
 
 // ------------------------------------------------------------------ Huffman decode
@@ -818,22 +859,23 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
     if (a.U == 0) return hipSuccess;
     const dim3 P(kPersistWg), T(kThreads);
     hipLaunchKernelGGL(k_unit_plan, dim3(1), dim3(1024), 0, s, a_dev);
-    hipLaunchKernelGGL(k_huf_count, P, T, 0, s, a_dev);
-    hipLaunchKernelGGL(k_scan_dev_part, P, T, 0, s, a.chunk_words, a.counts + 0, scan_part);
-    hipLaunchKernelGGL(k_scan_dev_mid, dim3(1), dim3(1024), 0, s, scan_part, kPersistWg);
-    hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, a.chunk_words, a.counts + 0, scan_part);
-    hipLaunchKernelGGL(k_rle_count, P, T, 0, s, a_dev);
-    uint32_t* part2 = scan_part + kPersistWg + 32;
-    hipLaunchKernelGGL(k_scan_dev_part, P, T, 0, s, a.tile_runs, a.counts + 1, part2);
-    hipLaunchKernelGGL(k_scan_dev_mid, dim3(1), dim3(1024), 0, s, part2, kPersistWg);
-    hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, a.tile_runs, a.counts + 1, part2);
+    hipLaunchKernelGGL(k_counts, P, T, 0, s, a_dev);
+    ScanPair sp{};
+    sp.data[0] = a.chunk_words;
+    sp.count[0] = a.counts + 0;
+    sp.part[0] = scan_part;
+    sp.data[1] = a.tile_runs;
+    sp.count[1] = a.counts + 1;
+    sp.part[1] = scan_part + kPersistWg + 32;
+    hipLaunchKernelGGL(k_scan_dev_part, P, T, 0, s, sp);
+    hipLaunchKernelGGL(k_scan_dev_mid, dim3(1), dim3(1024), 0, s, sp, kPersistWg);
+    hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, sp);
     hipLaunchKernelGGL(k_unit_sizes, dim3(1), dim3(1024), 0, s, a_dev);
     const uint32_t buf_words = (a.huf_chunk * kLutBitsMax + 31) / 32 + 2;
     const uint32_t wpl = a.huf_chunk / 256, cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;
     const size_t shmem = (size_t)(kThreads / 64) * cpb * buf_words * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_huf_write, P, T, shmem, s, a_dev, buf_words);
-    hipLaunchKernelGGL((k_rle_pass<false>), P, T, 0, s, a_dev);
-    hipLaunchKernelGGL((k_rle_pass<true>), P, T, 0, s, a_dev);
+    hipLaunchKernelGGL(k_write, P, T, shmem, s, a_dev, buf_words);
+    hipLaunchKernelGGL(k_rle_len, P, T, 0, s, a_dev);
     return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // Refactor kernels for gfx950: level statistics, bitplane encoding with the
 // per-plane error table and per-group lossless statistics, and the device-side
 // hybrid selection of Alg. 2 (Sec. 4.2) with its Huffman codebook.
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -75,24 +76,29 @@ __global__ void k_copy_in(const uint64_t* src, uint64_t* __restrict__ dst, uint6
         dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-__global__ void k_init_stats(LevelStats* st, int count)
+// Start of a refactor pass: the level statistics to their neutral values and
+// two regions of accumulators to zero, in one launch.
+__global__ void k_init_pass(LevelStats* st, uint32_t count, uint32_t* z0, uint64_t n0, uint32_t* z1,
+                            uint64_t n1)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    st[i].emax = INT_MIN;
-    st[i].nonfinite = 0;
-    st[i].minkey = ~0ull;
-    st[i].maxkey = 0;
-    st[i].maxabs_bits = 0;
+    const uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    if (i0 < count) {
+        st[i0].minkey = ~0ull;
+        st[i0].maxkey = 0;
+        st[i0].maxabs_bits = 0;
+    }
+    for (uint64_t i = i0; i < n0; i += stride) z0[i] = 0;
+    for (uint64_t i = i0; i < n1; i += stride) z1[i] = 0;
 }
 
 // ------------------------------------------------------------------ level statistics
-// One streaming pass: largest frexp exponent of the nonzero values (Alg. 1's
-// alignment exponent), min / max / max|x|, and a non-finite flag.  Each thread
-// folds 16-byte vectors, the workgroup reduces in LDS, and one lane per
-// workgroup publishes with device atomics (few workgroups -> little contention).
-// Per thread: the largest |x| bit pattern (which also gives the largest frexp
-// exponent and reveals NaN / Inf, whose patterns are the largest) and the float
+// One streaming pass: min / max / max|x| (max |x| gives Alg. 1's alignment
+// exponent and the non-finite check).  Each thread folds 16-byte vectors, the
+// workgroup reduces in LDS, and one lane per workgroup publishes with three
+// device atomics.  Atomics on one address serialize in the memory system, so
+// a level gets few large workgroups (kStatsThreads threads, at most
+// kStatsMaxWg of them).  Per thread: the largest |x| bit pattern and the float
 // minimum / maximum (zeros of either sign are reported as +0.0, so their order
 // does not matter).
 template <bool F64>
@@ -115,7 +121,7 @@ struct StatAcc {
 // One launch covers every level of a batch: workgroup -> job through wg_job,
 // then a grid-stride loop over that level with the job's own workgroup count.
 template <bool F64, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__ jobs,
+__global__ __launch_bounds__(kStatsThreads) void k_stats(const StatsJob* __restrict__ jobs,
                                                     const uint32_t* __restrict__ wg_job)
 {
     using U = typename StatAcc<F64>::U;
@@ -149,8 +155,8 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
     }
     for (uint64_t i = done + tid0; i < n; i += stride) acc.add(x[i]);
 
-    __shared__ unsigned long long s_amax[kThreads / 64];
-    __shared__ T s_min[kThreads / 64], s_max[kThreads / 64];
+    __shared__ unsigned long long s_amax[kStatsThreads / 64];
+    __shared__ T s_min[kStatsThreads / 64], s_max[kStatsThreads / 64];
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint64_t amax = wave_max((uint64_t)acc.amax);
     T vmin = wave_min(acc.vmin), vmax = wave_max(acc.vmax);
@@ -161,26 +167,19 @@ __global__ __launch_bounds__(kThreads) void k_stats(const StatsJob* __restrict__
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kThreads / 64; ++w) {
+        for (int w = 1; w < kStatsThreads / 64; ++w) {
             amax = s_amax[w] > amax ? s_amax[w] : amax;
             vmin = s_min[w] < vmin ? s_min[w] : vmin;
             vmax = s_max[w] > vmax ? s_max[w] : vmax;
         }
-        const bool bad = F64 ? amax >= 0x7FF0000000000000ull : amax >= 0x7F800000u;
-        if (bad) {
-            atomicOr(&st->nonfinite, 1u);
-        } else {
-            U bmin, bmax;
-            __builtin_memcpy(&bmin, &vmin, sizeof(T));
-            __builtin_memcpy(&bmax, &vmax, sizeof(T));
-            const uint64_t kmin = F64 ? order_key_f64(bmin) : order_key_f32((uint32_t)bmin);
-            const uint64_t kmax = F64 ? order_key_f64(bmax) : order_key_f32((uint32_t)bmax);
-            const int e = amax == 0 ? INT_MIN : (F64 ? frexp_exp_f64(amax) : frexp_exp_f32((uint32_t)amax));
-            if (e != INT_MIN) atomicMax(&st->emax, e);
-            atomicMin((unsigned long long*)&st->minkey, (unsigned long long)kmin);
-            atomicMax((unsigned long long*)&st->maxkey, (unsigned long long)kmax);
-            atomicMax((unsigned long long*)&st->maxabs_bits, (unsigned long long)amax);
-        }
+        U bmin, bmax;
+        __builtin_memcpy(&bmin, &vmin, sizeof(T));
+        __builtin_memcpy(&bmax, &vmax, sizeof(T));
+        const uint64_t kmin = F64 ? order_key_f64(bmin) : order_key_f32((uint32_t)bmin);
+        const uint64_t kmax = F64 ? order_key_f64(bmax) : order_key_f32((uint32_t)bmax);
+        atomicMin((unsigned long long*)&st->minkey, (unsigned long long)kmin);
+        atomicMax((unsigned long long*)&st->maxkey, (unsigned long long)kmax);
+        if (amax) atomicMax((unsigned long long*)&st->maxabs_bits, (unsigned long long)amax);
     }
 }
 
@@ -239,8 +238,8 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     const uint32_t B = job.B, nbd = job.nbd, m = job.m, nunits = job.nunits;
     const uint32_t ntiles = job.ntiles, tpw = job.tiles_per_wg;
     const uint64_t n = job.n;
-    const int emax = job.stats->emax;
-    const int e = emax == INT_MIN ? 0 : emax;
+    const uint64_t amax = job.stats->maxabs_bits;  // 0: every value is zero
+    const int e = amax == 0 ? 0 : (F64 ? frexp_exp_f64(amax) : frexp_exp_f32((uint32_t)amax));
     const T* xg = static_cast<const T*>(job.x);
     const auto x = gmem(xg);
     const auto rows = gmem(job.rows);
@@ -972,10 +971,13 @@ hipError_t launch_copy_in(void* dst, const void* host, uint64_t bytes, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_init_stats(LevelStats* st, int count, hipStream_t s)
+hipError_t launch_init_pass(LevelStats* st, uint32_t count, uint32_t* z0, uint64_t n0, uint32_t* z1,
+                            uint64_t n1, hipStream_t s)
 {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_stats, dim3((count + 63) / 64), dim3(64), 0, s, st, count);
+    const uint64_t most = std::max<uint64_t>(count, std::max(n0, n1));
+    if (most == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_pass, dim3(grid_for(most, kThreads, 4096)), dim3(kThreads), 0, s, st, count, z0,
+                       n0, z1, n1);
     return hipGetLastError();
 }
 
@@ -985,14 +987,14 @@ hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint
     if (grid == 0) return hipSuccess;
     if (f64) {
         if (vec)
-            hipLaunchKernelGGL((k_stats<true, true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+            hipLaunchKernelGGL((k_stats<true, true>), dim3(grid), dim3(kStatsThreads), 0, s, jobs, wg_job);
         else
-            hipLaunchKernelGGL((k_stats<true, false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+            hipLaunchKernelGGL((k_stats<true, false>), dim3(grid), dim3(kStatsThreads), 0, s, jobs, wg_job);
     } else {
         if (vec)
-            hipLaunchKernelGGL((k_stats<false, true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+            hipLaunchKernelGGL((k_stats<false, true>), dim3(grid), dim3(kStatsThreads), 0, s, jobs, wg_job);
         else
-            hipLaunchKernelGGL((k_stats<false, false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+            hipLaunchKernelGGL((k_stats<false, false>), dim3(grid), dim3(kStatsThreads), 0, s, jobs, wg_job);
     }
     return hipGetLastError();
 }

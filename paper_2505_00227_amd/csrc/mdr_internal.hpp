@@ -16,14 +16,20 @@ constexpr int kLutBitsMax = 12;   // Huffman decode table: 2^lmax entries
 constexpr int kKeyStride = 66;    // error keys k = 0..64, then [65] = max |x| below 2^(e-B)
 
 // Per-level statistics gathered on the device (zeroed by k_fill before use).
+// The bit pattern of max |x| also gives the alignment exponent (the largest
+// frexp exponent over nonzero values is that of max |x|; 0 when all are zero)
+// and reveals NaN / Inf, whose patterns are the largest.
 struct LevelStats {
-    int32_t emax;          // largest frexp exponent over nonzero values (INT32_MIN: none)
-    uint32_t nonfinite;    // nonzero if a NaN / Inf was seen
     uint64_t minkey;       // order-preserving integer key of the minimum
     uint64_t maxkey;       // order-preserving integer key of the maximum
     uint64_t maxabs_bits;  // bit pattern of max |x|
-    uint64_t pad[4];
+    uint64_t pad[5];
 };
+
+// statistics workgroups: threads, and at most this many per level (each
+// publishes with three device atomics when it ends)
+constexpr uint32_t kStatsThreads = 1024;
+constexpr uint32_t kStatsMaxWg = 256;
 
 // Selection result of one lossless unit (sign plane, or a group of m planes).
 struct UnitInfo {
@@ -120,7 +126,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStrea
 // behind it start without waiting on another engine; under capture the kernel
 // reads the host memory at every replay
 hipError_t launch_copy_in(void* dst, const void* host, uint64_t bytes, hipStream_t s);
-hipError_t launch_init_stats(LevelStats* st, int count, hipStream_t s);
+// level statistics [count] to their neutral values, z0[n0] and z1[n1] to zero
+hipError_t launch_init_pass(LevelStats* st, uint32_t count, uint32_t* z0, uint64_t n0, uint32_t* z1,
+                            uint64_t n1, hipStream_t s);
 // statistics of every job; wg_job maps each of `grid` workgroups to its job
 hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                               bool vec, hipStream_t s);

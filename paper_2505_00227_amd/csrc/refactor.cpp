@@ -166,7 +166,7 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
         if (jp.ntiles) {
             jp.tpw = (uint32_t)std::min<uint64_t>(jp.ntiles, tpw_all);
             jp.grid_e = (uint32_t)ceil_div(jp.ntiles, jp.tpw);
-            jp.grid_s = (uint32_t)std::min<uint64_t>(1024, ceil_div(jp.n, std::max<uint32_t>(1024, ctx->stats_wg_values)));
+            jp.grid_s = (uint32_t)std::min<uint64_t>(kStatsMaxWg, ceil_div(jp.n, std::max<uint32_t>(1024, ctx->stats_wg_values)));
         }
         jp.rows_off = L.rows_bytes;
         L.rows_bytes += align256(4ull * (B + 1) * jp.nbd);
@@ -355,11 +355,11 @@ mdr_status enqueue_pass(mdr_context* ctx, const Layout& L, const mdr_codec_param
     for (int k = 0; k < 4; ++k) map[k] = reinterpret_cast<const uint32_t*>(desc + L.d_map[k]);
     {
         StageTimer tm(tctx, MDR_STAGE_STATS, s);
-        MDR_HIP(launch_init_stats(reinterpret_cast<LevelStats*>(ws + L.o_stats), (int)L.J, s));
         // the encoder adds its workgroups' histograms, transitions and key
-        // maxima into zeroed level totals (fill kernels: safe under capture)
-        MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.o_keys), 2ull * kKeyStride * L.J, 0u, s));
-        MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ws + L.o_hist), (L.o_tot_end - L.o_hist) / 4, 0u, s));
+        // maxima into zeroed level totals (a kernel: safe under capture)
+        MDR_HIP(launch_init_pass(reinterpret_cast<LevelStats*>(ws + L.o_stats), L.J,
+                                 reinterpret_cast<uint32_t*>(ws + L.o_keys), 2ull * kKeyStride * L.J,
+                                 reinterpret_cast<uint32_t*>(ws + L.o_hist), (L.o_tot_end - L.o_hist) / 4, s));
         MDR_HIP(launch_stats_batch(sj, map[0], (uint32_t)L.map[0].size(), L.f64, false, s));
         MDR_HIP(launch_stats_batch(sj, map[1], (uint32_t)L.map[1].size(), L.f64, true, s));
     }
@@ -412,8 +412,9 @@ mdr_status assemble(mdr_context* ctx, const Layout& L, mdr_dtype dtype, const md
     const uint64_t* hoff = reinterpret_cast<const uint64_t*>(meta + L.o_payoff);
     const uint64_t* hbytes = reinterpret_cast<const uint64_t*>(meta + L.o_ubytes);
     const uint32_t* hcnt = reinterpret_cast<const uint32_t*>(meta + L.o_counts);
+    const uint64_t inf_bits = L.f64 ? 0x7FF0000000000000ull : 0x7F800000ull;
     for (uint32_t j = 0; j < L.J; ++j)
-        if (L.jobs[j].n && hst[j].nonfinite)
+        if (L.jobs[j].n && hst[j].maxabs_bits >= inf_bits)
             return fail(MDR_ERR_INVALID_ARG, "variable " + std::to_string(L.jobs[j].var) + " level " +
                                                  std::to_string(L.jobs[j].level) + " holds NaN or Inf");
     if (hcnt[2]) return fail(MDR_ERR_HIP, "internal: lossless streams exceed their arena");
@@ -442,10 +443,12 @@ mdr_status assemble(mdr_context* ctx, const Layout& L, mdr_dtype dtype, const md
             LR.E.assign(L.B + 1, 0.0);
             if (jp.n) {
                 const LevelStats& ls = hst[j];
-                LR.e = ls.emax == INT_MIN ? 0 : ls.emax;
                 LR.vmin = key_value(ls.minkey, L.f64);
                 LR.vmax = key_value(ls.maxkey, L.f64);
                 LR.vmaxabs = bits_value(ls.maxabs_bits, L.f64);
+                // alignment exponent: frexp's of max |x| (exact in double), 0 if all zero
+                LR.e = 0;
+                if (LR.vmaxabs != 0.0) (void)std::frexp(LR.vmaxabs, &LR.e);
                 const unsigned long long* keys = hek + (uint64_t)j * kKeyStride;
                 const double small = bits_value(keys[kKeyStride - 1], L.f64);
                 LR.E[0] = LR.vmaxabs;  // nothing fetched: the error is max |x|

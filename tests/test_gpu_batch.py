@@ -96,7 +96,7 @@ def test_batch_launch_shapes_do_not_change_results(mdr, ctx):
         if ref is None:
             ref = blobs
         assert blobs == ref, ("launch shape", tgt, sv)
-    ctx.set_launch(enc_target_wg=2304, stats_wg_values=16384, graphs=1)
+    ctx.set_launch(enc_target_wg=2304, stats_wg_values=65536, graphs=1)
 
 
 def test_batch_rejects_nonfinite(mdr, ctx):
