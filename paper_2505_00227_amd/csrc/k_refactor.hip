@@ -365,6 +365,21 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
             // the longest run in {12, 8, 4, 2, 1} that its M_c allows; cuts with
             // M_c < 1/2 take the direct maximum.  Lane l decides cut l+1.
             uint32_t S1, S2, S4, S8, S12;
+            if (t == t0 && B > 1) {
+                // Seed the workgroup's running maxima before its first tile:
+                // lane l takes the exact maximum over its own 32 values for
+                // one cut, so every cut starts from the largest of about 256
+                // actual keys.  Without it every cut would take the direct
+                // maximum below (about three times the work of a pruned tile);
+                // seeds are keys of actual values, so the pruning stays exact.
+                const int c = (int)(lane % (B - 1)) + 1;
+                float km = 0.0f;
+#pragma unroll
+                for (int j = 0; j < 32; ++j)
+                    km = fmaxf(km, __builtin_amdgcn_fractf(__builtin_amdgcn_ldexpf(v[j], -c)));
+                atomicMax(&s_key32[B - c], __float_as_uint(km));
+                __syncthreads();
+            }
             {
                 const uint32_t c = lane + 1;
                 uint32_t tl = 0;
