@@ -258,7 +258,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
             s_key32[tid] = 0;
     }
 
-    float frac_max = 0.0f;  // f32: max fract(y) = the k = B key
+    uint32_t frac_max = 0;  // f32: bits of max fract(y) = the k = B key (nonnegative: bits order as values)
     T small = 0;
 
     const uint32_t t0 = wg * tpw;
@@ -397,7 +397,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
             const uint32_t strong = S1 | S2 | S4 | S8 | S12;
             auto one = [&](float y) {
                 const float f = __builtin_amdgcn_fractf(y);
-                frac_max = fmaxf(frac_max, f);
+                frac_max = max(frac_max, __float_as_uint(f));
                 asm volatile("" : "+v"(frac_max));  // fold in now, not at the end
                 const uint64_t Y = ((uint64_t)(uint32_t)y << 32) | (uint32_t)(f * 0x1p32f);
                 const uint64_t r2 = Y & (Y << 1);    // bit p: bits p, p-1 are ones
@@ -588,7 +588,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     } else {
         frac_max = wave_max(frac_max);
         if (lane == 0) {
-            atomicMax(&s_key32[B], __float_as_uint(frac_max));
+            atomicMax(&s_key32[B], frac_max);
             atomicMax(&s_key32[kKeyStride - 1], __float_as_uint(small));
         }
     }
