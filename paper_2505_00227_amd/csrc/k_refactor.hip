@@ -259,6 +259,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     }
 
     uint32_t frac_max = 0;  // f32: bits of max fract(y) = the k = B key (nonnegative: bits order as values)
+    uint64_t frac_max64 = 0;  // the same for f64
     T small = 0;
 
     const uint32_t t0 = wg * tpw;
@@ -318,14 +319,9 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 sgn |= (uint32_t)(bits >> 63) << j;
                 double a = __longlong_as_double((long long)(bits & 0x7FFFFFFFFFFFFFFFull));
                 double y = __builtin_amdgcn_ldexp(a, (int)B - e);
-                double yh = __builtin_trunc(y * 0x1p-32);
-                uint32_t h = (uint32_t)yh;
-                uint32_t l = (uint32_t)(y - yh * 0x1p32);
-                bool tiny = (h | l) == 0;
+                bool tiny = y < 1.0;  // mag = floor(y) = 0
                 small = (tiny && a > small) ? a : small;
                 v[j] = tiny ? 0.0 : y;
-                hi[j] = h;
-                lo[j] = l;
             } else {
                 uint32_t bits = __float_as_uint(v[j]);
                 sgn |= (bits >> 31) << j;
@@ -337,25 +333,92 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
             }
         }
 
-        if constexpr (!F64) {
-            // materialise y and the running `small` here, so the raw values die
-            // before the key loop instead of being carried through it
+        // materialise y and the running `small` here, so the raw values die
+        // before the key loop instead of being carried through it
 #pragma unroll
-            for (int j = 0; j < 32; ++j) asm volatile("" : "+v"(v[j]));
-            asm volatile("" : "+v"(small));
-        }
+        for (int j = 0; j < 32; ++j) asm volatile("" : "+v"(v[j]));
+        asm volatile("" : "+v"(small));
         // ---- exact error keys, k = 0..B
         if constexpr (F64) {
-            // direct per-block maximum, folded per wave into LDS
-            for (int k = 1; k <= (int)B; ++k) {  // k = 0 is max |x|, known from the statistics
+            // The f32 pruning below on the 128-bit fixed point of y: words
+            // X3:X2 = magnitude (hi[j]:lo[j]), X1 = the top 32 fraction bits.
+            // Cut c (1..B-1) is bit 64+c-1; a tested run is at most 12 bits
+            // long, so it never reaches below bit 53 and the word below X1 is
+            // not needed (the runs computed for X1's low bits, which take
+            // zeros from below, are never used).  Lane l decides cut l+1.
+            uint64_t S1, S2, S4, S8, S12;
+            if (t == t0 && B > 1) {
+                const int c = (int)(lane % (B - 1)) + 1;  // seeds, as for f32
                 double km = 0.0;
 #pragma unroll
                 for (int j = 0; j < 32; ++j) {
-                    double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(v[j], k - (int)B));
+                    const double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(v[j], -c));
+                    km = key > km ? key : km;
+                }
+                atomicMax(&s_key64[B - c], (unsigned long long)__double_as_longlong(km));
+                __syncthreads();
+            }
+            {
+                const uint32_t c = lane + 1;
+                uint32_t tl = 0;
+                if (c < B) {
+                    const double M = __longlong_as_double((long long)s_key64[B - c]);
+                    if (M >= 0.5) tl = __clz(~(uint32_t)(M * 0x1p32));
+                }
+                const bool live = c < B;
+                S12 = __ballot(live && tl >= 12);
+                S8 = __ballot(live && tl >= 8 && tl < 12);
+                S4 = __ballot(live && tl >= 4 && tl < 8);
+                S2 = __ballot(live && tl >= 2 && tl < 4);
+                S1 = __ballot(live && tl == 1);
+            }
+            const uint64_t strong = S1 | S2 | S4 | S8 | S12;
+            const uint32_t S1l = (uint32_t)S1, S2l = (uint32_t)S2, S4l = (uint32_t)S4, S8l = (uint32_t)S8,
+                           S12l = (uint32_t)S12;
+            const uint32_t S1h = (uint32_t)(S1 >> 32), S2h = (uint32_t)(S2 >> 32), S4h = (uint32_t)(S4 >> 32),
+                           S8h = (uint32_t)(S8 >> 32), S12h = (uint32_t)(S12 >> 32);
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                const double y = v[j];
+                const double f = __builtin_amdgcn_fract(y);
+                frac_max64 = max(frac_max64, (uint64_t)__double_as_longlong(f));
+                const double yh = __builtin_trunc(y * 0x1p-32);
+                const uint32_t X3 = (uint32_t)yh, X2 = (uint32_t)(y - yh * 0x1p32), X1 = (uint32_t)(f * 0x1p32);
+                // (word << k) = alignbit(word, word below, 32 - k)
+                const uint32_t r2_3 = X3 & __builtin_amdgcn_alignbit(X3, X2, 31);
+                const uint32_t r2_2 = X2 & __builtin_amdgcn_alignbit(X2, X1, 31);
+                const uint32_t r2_1 = X1 & (X1 << 1);
+                const uint32_t r4_3 = r2_3 & __builtin_amdgcn_alignbit(r2_3, r2_2, 30);
+                const uint32_t r4_2 = r2_2 & __builtin_amdgcn_alignbit(r2_2, r2_1, 30);
+                const uint32_t r4_1 = r2_1 & (r2_1 << 2);
+                const uint32_t r8_3 = r4_3 & __builtin_amdgcn_alignbit(r4_3, r4_2, 28);
+                const uint32_t r8_2 = r4_2 & __builtin_amdgcn_alignbit(r4_2, r4_1, 28);
+                const uint32_t r8_1 = r4_1 & (r4_1 << 4);
+                const uint32_t r12_3 = r8_3 & __builtin_amdgcn_alignbit(r8_3, r8_2, 28);
+                const uint32_t r12_2 = r8_2 & __builtin_amdgcn_alignbit(r8_2, r8_1, 28);
+                const uint32_t ca = (X2 & S1l) | (r2_2 & S2l) | (r4_2 & S4l) | (r8_2 & S8l) | (r12_2 & S12l);
+                const uint32_t cb = (X3 & S1h) | (r2_3 & S2h) | (r4_3 & S4h) | (r8_3 & S8h) | (r12_3 & S12h);
+                uint64_t cand = ((uint64_t)cb << 32) | ca;  // bit c-1: cut c
+                while (cand) {
+                    const int c = __ffsll((unsigned long long)cand);
+                    cand &= cand - 1;
+                    const double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(y, -c));
+                    atomicMax(&s_key64[B - c], (unsigned long long)__double_as_longlong(key));
+                }
+            }
+            const uint64_t all = B > 1 ? (1ull << (B - 1)) - 1ull : 0ull;  // cuts 1 .. B-1
+            uint64_t weak = all & ~strong;
+            while (weak) {
+                const int c = __ffsll((unsigned long long)weak);
+                weak &= weak - 1;
+                double km = 0.0;
+#pragma unroll
+                for (int j = 0; j < 32; ++j) {
+                    const double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(v[j], -c));
                     km = key > km ? key : km;
                 }
                 km = wave_max(km);
-                if (lane == 0) atomicMax(&s_key64[k], (unsigned long long)__double_as_longlong(km));
+                if (lane == 0) atomicMax(&s_key64[B - c], (unsigned long long)__double_as_longlong(km));
             }
         } else {
             // Cut c = B - k (k = 1..B-1) is bit c-1 of y; k = B is the fraction
@@ -437,6 +500,15 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
             for (int j = 0; j < 32; ++j) {
                 asm volatile("" : "+v"(v[j]));
                 lo[j] = (uint32_t)v[j];
+            }
+        } else {
+            // the same for f64: mag = hi:lo (0 when tiny)
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                asm volatile("" : "+v"(v[j]));
+                const double yh = __builtin_trunc(v[j] * 0x1p-32);
+                hi[j] = (uint32_t)yh;
+                lo[j] = (uint32_t)(v[j] - yh * 0x1p32);
             }
         }
         // ---- bit transpose: lo[c] (and hi[c]) become the plane words of bit c (32 + c);
@@ -584,7 +656,11 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     }
     small = wave_max(small);
     if constexpr (F64) {
-        if (lane == 0) atomicMax(&s_key64[kKeyStride - 1], (unsigned long long)__double_as_longlong(small));
+        frac_max64 = wave_max(frac_max64);
+        if (lane == 0) {
+            atomicMax(&s_key64[B], (unsigned long long)frac_max64);
+            atomicMax(&s_key64[kKeyStride - 1], (unsigned long long)__double_as_longlong(small));
+        }
     } else {
         frac_max = wave_max(frac_max);
         if (lane == 0) {
@@ -607,8 +683,8 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     if (tid < kMaxRows && s_trans[tid]) atomicAdd(&job.trans[tid], s_trans[tid]);
 }
 
-// f32 fits five waves per SIMD (96 registers) with LDS to spare; f64 keeps
-// the default budget
+// f32 fits five waves per SIMD (96 registers) with LDS to spare; f64 two
+// (256 registers, without spills: left alone the compiler takes 259 and one)
 template <bool VEC, bool FAST>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_encode_f32(
     const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
@@ -618,8 +694,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
 }
 
 template <bool VEC>
-__global__ __launch_bounds__(kThreads) void k_encode_f64(const EncodeJob* __restrict__ jobs,
-                                                         const uint32_t* __restrict__ wg_job)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_encode_f64(
+    const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
 {
     const EncodeJob& job = jobs[wg_job[blockIdx.x]];
     encode_body<true, VEC, false>(job, blockIdx.x - job.wg_base);
