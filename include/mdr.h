@@ -251,6 +251,34 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
                                    void* const* out_x, void* const* out_y, void* const* out_z,
                                    void* stream, mdr_qoi_info* info);
 
+/*
+ * The three next-bound estimators of Sec. 5.2 for the loop above:
+ *   MDR_QOI_MAPE  the loop above (minimal augmentation with proportional estimation);
+ *   MDR_QOI_MA    minimal augmentation only: one more merged group per variable
+ *                 per round (MAPE that never takes the proportional step);
+ *   MDR_QOI_CP    the CPU-porting estimator: at the point with the largest estimate
+ *                 (the first in level-concatenated order among equal ones, found on
+ *                 the device), every bound is multiplied by cp_decay until that
+ *                 point's estimate, evaluated from its current values exactly as
+ *                 tau' is, is within tau (at most 2200 times); each variable is then
+ *                 re-planned to its bound.
+ * For all three, a round whose bounds add no group fetches one more merged group
+ * per variable, as above.
+ */
+typedef enum { MDR_QOI_MAPE = 0, MDR_QOI_MA = 1, MDR_QOI_CP = 2 } mdr_qoi_estimator;
+typedef struct {
+    int32_t estimator;  /* mdr_qoi_estimator                                        */
+    uint32_t pad;
+    double mape_c;      /* MAPE threshold c; <= 0 means 10                            */
+    double cp_decay;    /* CP factor per step, in (0, 1); <= 0 means 1/2              */
+} mdr_qoi_params;
+/* mdr_retrieve_qoi_vtotal with a chosen estimator (params NULL: MAPE, c = 10).
+ * An estimator outside the enum, or cp_decay >= 1, is MDR_ERR_INVALID_ARG. */
+mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, mdr_retriever* vz,
+                                        mdr_bound kind, double tau, const mdr_qoi_params* params,
+                                        void* const* out_x, void* const* out_y, void* const* out_z,
+                                        void* stream, mdr_qoi_info* info);
+
 /* ---------------------------------------------------------------- chunked pipeline */
 /*
  * A field held in host memory as nchunks chunks, each an independent

@@ -98,6 +98,8 @@ def lib():
         L.orc_plan_one_step.argtypes = [u32, u32, u32, vp, vp, vp]
         L.orc_qoi_vtotal_tau.argtypes = [u64, vp, vp, vp, vp]
         L.orc_qoi_vtotal_tau.restype = C.c_double
+        L.orc_qoi_vtotal_argmax.argtypes = [u64, vp, vp, vp, vp]
+        L.orc_qoi_vtotal_argmax.restype = u64
         L.orc_serialize.argtypes = [vp, u32, C.POINTER(_Params), vp, u64, C.POINTER(u64)]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = None
@@ -434,15 +436,52 @@ def qoi_initial_eps(vars3, tau: float):
     return [(tau / qmax) * variable_range(levels) for levels in vars3]
 
 
-def retrieve_qoi_vtotal(vars3, tau: float, c: float = 10.0, k_in=None, max_iter: int = 10000):
-    """Alg. 3 with MAPE (Sec. 5.2): returns (values per var, k per var, tau', met, iterations).
+def qoi_argmax(vx: np.ndarray, vy: np.ndarray, vz: np.ndarray, eps) -> int:
+    """First point (level-concatenated order) with the largest V_total estimate."""
+    a = [np.ascontiguousarray(v, np.float64) for v in (vx, vy, vz)]
+    e = np.ascontiguousarray(eps, np.float64)
+    return int(lib().orc_qoi_vtotal_argmax(a[0].size, _ptr(a[0]), _ptr(a[1]), _ptr(a[2]), _ptr(e)))
+
+
+QOI_INFLATE = 1.0 + 2.0 ** -40
+
+
+def cp_bounds(v, eps, tau: float, decay: float = 0.5, max_steps: int = 2200):
+    """The CP estimator's host step (Sec. 5.2), reading: at the point with the
+    largest estimate, whose current values are v = (|vx|, |vy|, |vz|), every
+    bound is multiplied by `decay` until that point's estimate, evaluated as the
+    global one (same order, same inflation), is within tau."""
+    e = [float(x) for x in eps]
+
+    def est(e):
+        s = 0.0
+        for c in range(3):
+            s = s + e[c] * ((2.0 * v[c]) + e[c])
+        return s * QOI_INFLATE
+
+    steps = 0
+    while est(e) > tau and steps < max_steps:
+        e = [x * decay for x in e]
+        steps += 1
+    return e
+
+
+def retrieve_qoi_vtotal(vars3, tau: float, c: float = 10.0, k_in=None, max_iter: int = 10000,
+                        estimator: str = "mape", decay: float = 0.5):
+    """Alg. 3 (Sec. 5.2): returns (values per var, k per var, tau', met, iterations).
 
     Each iteration recomposes the three variables from the planes held (identity
     recomposition: values are the level-concatenated coefficients), evaluates
     tau' = (1+2^-40) max_p sum_c eps_c (2|v_c| + eps_c), and stops when tau' <= tau.
-    Otherwise with p = tau'/tau: if p > c every eps_c <- eps_c / p and each variable
-    is re-planned; if that adds nothing (or p <= c) one greedy step per variable
-    (minimal augmentation, one more merged group)."""
+    Otherwise the next bounds come from the estimator:
+      "mape": with p = tau'/tau, if p > c every eps_c <- eps_c / p and each
+              variable is re-planned;
+      "ma":   nothing but the step below (minimal augmentation);
+      "cp":   the bounds `cp_bounds` gives at the point with the largest
+              estimate, each variable re-planned to them;
+    and if that adds nothing, one greedy step per variable (one more merged
+    group)."""
+    assert estimator in ("mape", "ma", "cp")
     ks = [list(k_in[i]) if k_in is not None else [0] * len(v) for i, v in enumerate(vars3)]
     eps0 = qoi_initial_eps(vars3, tau)
     for i, levels in enumerate(vars3):
@@ -457,11 +496,18 @@ def retrieve_qoi_vtotal(vars3, tau: float, c: float = 10.0, k_in=None, max_iter:
         full = all(all(k == levels[0].B for k in ks[i]) for i, levels in enumerate(vars3))
         if tprime <= tau or full or it >= max_iter:
             return vals, ks, tprime, tprime <= tau, it
-        p = tprime / tau if tau > 0 else math.inf
+        target = None
+        if estimator == "mape":
+            p = tprime / tau if tau > 0 else math.inf
+            if p > c:
+                target = [e / p for e in eps]
+        elif estimator == "cp":
+            at = qoi_argmax(vals[0], vals[1], vals[2], eps)
+            target = cp_bounds([abs(float(vals[ci][at])) for ci in range(3)], eps, tau, decay)
         moved = False
-        if p > c:
+        if target is not None:
             for i, levels in enumerate(vars3):
-                knew, _ = plan(levels, eps[i] / p, ks[i])
+                knew, _ = plan(levels, target[i], ks[i])
                 moved = moved or knew != ks[i]
                 ks[i] = knew
         if not moved:

@@ -943,6 +943,32 @@ double orc_qoi_vtotal_tau(uint64_t n, const double* vx, const double* vy, const 
     return worst * (1.0 + ldexp(1.0, -40));
 }
 
+/*
+ * The point the CP estimator (Sec. 5.2) works on: the first index (in the
+ * level-concatenated order) whose sum, evaluated exactly as above, is the
+ * largest.  Returns n for n = 0.
+ */
+uint64_t orc_qoi_vtotal_argmax(uint64_t n, const double* vx, const double* vy, const double* vz,
+                               const double eps[3])
+{
+    double worst = -1.0;
+    uint64_t at = n;
+    const double* v[3] = {vx, vy, vz};
+    for (uint64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            double a = fabs(v[c][i]);
+            double t = eps[c] * ((2.0 * a) + eps[c]);
+            s = s + t;
+        }
+        if (s > worst) {
+            worst = s;
+            at = i;
+        }
+    }
+    return at;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sec. 5.1 serialization (container format of this project)                 */
 /* ------------------------------------------------------------------------ */

@@ -52,6 +52,14 @@ class mdr_level_view(C.Structure):
     _fields_ = [("data", C.c_void_p), ("n", C.c_uint64)]
 
 
+class mdr_qoi_params(C.Structure):
+    _fields_ = [("estimator", C.c_int32), ("pad", C.c_uint32), ("mape_c", C.c_double), ("cp_decay", C.c_double)]
+
+
+MDR_QOI_MAPE, MDR_QOI_MA, MDR_QOI_CP = 0, 1, 2
+QOI_ESTIMATORS = {"mape": MDR_QOI_MAPE, "ma": MDR_QOI_MA, "cp": MDR_QOI_CP}
+
+
 class mdr_qoi_info(C.Structure):
     _fields_ = [("tau_abs", C.c_double), ("tau_est", C.c_double), ("eps", C.c_double * 3),
                 ("bytes_fetched", C.c_uint64), ("iterations", C.c_uint32), ("met", C.c_int32)]
@@ -134,6 +142,8 @@ _SIGS = {
                             _P(mdr_retrieve_info)], C.c_int),
     "mdr_retrieve_qoi_vtotal": ([_vp, _vp, _vp, C.c_int, C.c_double, C.c_double, _P(_vp), _P(_vp),
                                  _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
+    "mdr_retrieve_qoi_vtotal_with": ([_vp, _vp, _vp, C.c_int, C.c_double, _P(mdr_qoi_params), _P(_vp),
+                                      _P(_vp), _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
     "mdr_pipeline_create": ([_vp, _u32, _P(_u64), _u32, C.c_int, _u32, _P(mdr_codec_params), _P(_vp)],
                             C.c_int),
     "mdr_pipeline_refactor": ([_vp, _vp, C.c_int, _P(mdr_pipeline_info)], C.c_int),
@@ -408,13 +418,19 @@ def retrieve_batch(rts, tols, outs_per_var, relative: bool = True, stream=None) 
 
 
 def retrieve_qoi_vtotal(rx: Retriever, ry: Retriever, rz: Retriever, tau: float, outs3,
-                        relative: bool = False, mape_c: float = 10.0, stream=None) -> dict:
-    """mdr_retrieve_qoi_vtotal: refine vx, vy, vz until the V_total bound meets tau."""
+                        relative: bool = False, mape_c: float = 10.0, stream=None,
+                        estimator: str = "mape", cp_decay: float = 0.5) -> dict:
+    """mdr_retrieve_qoi_vtotal_with: refine vx, vy, vz until the V_total bound
+    meets tau; estimator "mape" (threshold mape_c), "ma" or "cp" (factor cp_decay)."""
     info = mdr_qoi_info()
+    prm = mdr_qoi_params()
+    prm.estimator = QOI_ESTIMATORS[estimator]
+    prm.mape_c = float(mape_c)
+    prm.cp_decay = float(cp_decay)
     o = [Retriever._outs(outs) for outs in outs3]
-    _check(_lib.mdr_retrieve_qoi_vtotal(rx.handle, ry.handle, rz.handle,
-                                        MDR_REL if relative else MDR_ABS, float(tau), float(mape_c),
-                                        o[0], o[1], o[2], _stream_ptr(stream), C.byref(info)))
+    _check(_lib.mdr_retrieve_qoi_vtotal_with(rx.handle, ry.handle, rz.handle,
+                                             MDR_REL if relative else MDR_ABS, float(tau), C.byref(prm),
+                                             o[0], o[1], o[2], _stream_ptr(stream), C.byref(info)))
     return info.as_dict()
 
 

@@ -495,7 +495,27 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
                                    void* const* out_x, void* const* out_y, void* const* out_z,
                                    void* stream, mdr_qoi_info* info)
 {
+    mdr_qoi_params prm{};
+    prm.estimator = MDR_QOI_MAPE;
+    prm.mape_c = mape_c;
+    return mdr_retrieve_qoi_vtotal_with(vx, vy, vz, kind, tau, &prm, out_x, out_y, out_z, stream, info);
+}
+
+mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, mdr_retriever* vz,
+                                        mdr_bound kind, double tau, const mdr_qoi_params* params,
+                                        void* const* out_x, void* const* out_y, void* const* out_z,
+                                        void* stream, mdr_qoi_info* info)
+{
     g_err.clear();
+    mdr_qoi_params prm{};
+    prm.estimator = MDR_QOI_MAPE;
+    if (params) prm = *params;
+    if (prm.estimator != MDR_QOI_MAPE && prm.estimator != MDR_QOI_MA && prm.estimator != MDR_QOI_CP)
+        return fail(MDR_ERR_INVALID_ARG, "unknown QoI estimator");
+    if (!(prm.cp_decay < 1.0)) return fail(MDR_ERR_INVALID_ARG, "cp_decay must be below 1");
+    const double mape_c = prm.mape_c;
+    const double decay = prm.cp_decay > 0.0 ? prm.cp_decay : 0.5;
+    const bool cp = prm.estimator == MDR_QOI_CP;
     mdr_retriever* rts[3] = {vx, vy, vz};
     void* const* outs[3] = {out_x, out_y, out_z};
     for (int c = 0; c < 3; ++c)
@@ -570,6 +590,7 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
         }
         {
             std::vector<QoiJob> jobs;
+            uint64_t base = 0;
             for (size_t l = 0; l < r0->levels.size(); ++l) {
                 QoiJob j{};
                 j.x = out_x[l];
@@ -578,13 +599,16 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
                 j.n = r0->levels[l].n;
                 for (int c = 0; c < 3; ++c) j.eps[c] = eps[c];
                 j.acc = acc;
+                j.arg = acc + 1;
+                j.base = base;
+                base += j.n;
                 jobs.push_back(j);
             }
-            st = enqueue_qoi(ctx, jobs, std::vector<bool>(jobs.size(), f64), acc, 1, s);
+            st = enqueue_qoi(ctx, jobs, std::vector<bool>(jobs.size(), f64), acc, 1, s, cp);
             if (st) return st;
         }
         unsigned long long* hb = static_cast<unsigned long long*>(ctx->stage);
-        MDR_HIP(hipMemcpyAsync(hb, acc, 8, hipMemcpyDeviceToHost, s));
+        MDR_HIP(hipMemcpyAsync(hb, acc, cp ? 16 : 8, hipMemcpyDeviceToHost, s));
         MDR_HIP(hipStreamSynchronize(s));
         double worst;
         std::memcpy(&worst, hb, 8);
@@ -593,12 +617,54 @@ mdr_status mdr_retrieve_qoi_vtotal(mdr_retriever* vx, mdr_retriever* vy, mdr_ret
         for (int c = 0; c < 3; ++c)
             for (uint32_t kl : ks[c]) full = full && kl == rts[c]->r->B;
         if (tprime <= tau_abs || full) break;
-        const double p = tau_abs > 0.0 ? tprime / tau_abs : INFINITY;
+        // next bounds from the estimator; none: minimal augmentation only
+        bool have_target = false;
+        double target[3] = {0, 0, 0};
+        if (prm.estimator == MDR_QOI_MAPE) {
+            const double p = tau_abs > 0.0 ? tprime / tau_abs : INFINITY;
+            if (p > cmape) {
+                for (int c = 0; c < 3; ++c) target[c] = eps[c] / p;
+                have_target = true;
+            }
+        } else if (cp) {
+            // the worst point's current values, then its bounds decayed until
+            // its own estimate (as tau' is evaluated) is within tau
+            uint64_t at = hb[1];
+            size_t l = 0;
+            while (l < r0->levels.size() && at >= r0->levels[l].n) at -= r0->levels[l++].n;
+            if (l == r0->levels.size()) return fail(MDR_ERR_HIP, "internal: no point attains the estimate");
+            const size_t es = f64 ? 8 : 4;
+            uint8_t* hv = reinterpret_cast<uint8_t*>(hb + 2);
+            for (int c = 0; c < 3; ++c)
+                MDR_HIP(hipMemcpyAsync(hv + 8 * c, static_cast<const uint8_t*>(outs[c][l]) + at * es, es,
+                                       hipMemcpyDeviceToHost, s));
+            MDR_HIP(hipStreamSynchronize(s));
+            double a[3];
+            for (int c = 0; c < 3; ++c) {
+                if (f64) {
+                    std::memcpy(&a[c], hv + 8 * c, 8);
+                } else {
+                    float fv;
+                    std::memcpy(&fv, hv + 8 * c, 4);
+                    a[c] = fv;
+                }
+                a[c] = std::fabs(a[c]);
+                target[c] = eps[c];
+            }
+            auto at_point = [&](const double* e) {
+                double sum = 0.0;
+                for (int c = 0; c < 3; ++c) sum = sum + e[c] * ((2.0 * a[c]) + e[c]);
+                return sum * (1.0 + std::ldexp(1.0, -40));
+            };
+            for (int step = 0; step < 2200 && at_point(target) > tau_abs; ++step)
+                for (int c = 0; c < 3; ++c) target[c] = target[c] * decay;
+            have_target = true;
+        }
         bool moved = false;
-        if (p > cmape) {
+        if (have_target) {
             for (int c = 0; c < 3; ++c) {
                 std::vector<uint32_t> knew = ks[c];
-                plan_to(rts[c]->r, eps[c] / p, knew);
+                plan_to(rts[c]->r, target[c], knew);
                 moved = moved || knew != ks[c];
                 ks[c] = knew;
             }

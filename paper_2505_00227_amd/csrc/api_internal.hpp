@@ -196,9 +196,10 @@ struct ReconOnly {
 mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, hipStream_t s,
                          const ReconOnly* extra = nullptr, size_t nextra = 0);
 // V_total estimates: jobs (acc pointers included) in one launch per dtype,
-// after clearing `nacc` accumulators at acc0.
+// after clearing `nacc` accumulators at acc0.  argmax: also the first point
+// attaining each maximum (jobs' arg pointers, nacc slots from acc0 + nacc).
 mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const std::vector<bool>& f64,
-                       unsigned long long* acc0, uint32_t nacc, hipStream_t s);
+                       unsigned long long* acc0, uint32_t nacc, hipStream_t s, bool argmax = false);
 
 // tolerance planner (greedy over levels, exact error tables)
 double plan_bound(const mdr_refactored* r, const std::vector<uint32_t>& k);

@@ -156,7 +156,56 @@ __global__ __launch_bounds__(kThreads) void k_qoi_vtotal_batch(const QoiJob* __r
     }
 }
 
+// The point the CP estimator works on: the smallest index whose estimate,
+// evaluated exactly as above, has the bit pattern of the maximum the previous
+// launch left in *acc.
+template <bool F64>
+__global__ __launch_bounds__(kThreads) void k_qoi_vtotal_argmax_batch(const QoiJob* __restrict__ jobs,
+                                                                      const uint32_t* __restrict__ wg_job)
+{
+    using T = std::conditional_t<F64, double, float>;
+    const QoiJob& j = jobs[wg_job[blockIdx.x]];
+    const auto x = gmem(static_cast<const T*>(j.x));
+    const auto y = gmem(static_cast<const T*>(j.y));
+    const auto z = gmem(static_cast<const T*>(j.z));
+    const double ex = j.eps[0], ey = j.eps[1], ez = j.eps[2];
+    const unsigned long long target = *j.acc;
+    unsigned long long first = ~0ull;
+    const uint64_t stride = (uint64_t)j.grid * blockDim.x;
+    for (uint64_t i = (uint64_t)(blockIdx.x - j.wg_base) * blockDim.x + threadIdx.x; i < j.n; i += stride) {
+        double ax = fabs((double)x[i]), ay = fabs((double)y[i]), az = fabs((double)z[i]);
+        double tx = ex * ((2.0 * ax) + ex);
+        double ty = ey * ((2.0 * ay) + ey);
+        double tz = ez * ((2.0 * az) + ez);
+        double s = 0.0;
+        s = s + tx;
+        s = s + ty;
+        s = s + tz;
+        if ((unsigned long long)__double_as_longlong(s) == target) {
+            first = j.base + i;  // a thread's indices only grow: its first match is its smallest
+            break;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(first, off, 64);
+        first = o < first ? o : first;
+    }
+    if ((threadIdx.x & 63) == 0 && first != ~0ull) atomicMin(j.arg, first);
+}
+
 }  // namespace
+
+hipError_t launch_qoi_vtotal_argmax_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
+                                          hipStream_t s)
+{
+    if (grid == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL((k_qoi_vtotal_argmax_batch<true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+    else
+        hipLaunchKernelGGL((k_qoi_vtotal_argmax_batch<false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+    return hipGetLastError();
+}
 
 hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                                    hipStream_t s)

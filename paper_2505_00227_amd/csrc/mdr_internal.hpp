@@ -187,9 +187,15 @@ struct QoiJob {
     uint64_t n;
     double eps[3];
     unsigned long long* acc;  // max of the estimate's bit patterns (non-negative doubles)
+    unsigned long long* arg;  // first point attaining it (argmax launch only)
+    uint64_t base;            // index of the job's first point in its variable
     uint32_t wg_base, grid;   // this job's workgroups in the launch
 };
 hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                                    hipStream_t s);
+// after launch_qoi_vtotal_batch on the same jobs: min over points whose estimate
+// equals *acc of base + index, into *arg (which starts at ~0)
+hipError_t launch_qoi_vtotal_argmax_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
+                                          hipStream_t s);
 
 }  // namespace mdr

@@ -279,10 +279,11 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
 }
 
 mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const std::vector<bool>& f64,
-                       unsigned long long* acc0, uint32_t nacc, hipStream_t s)
+                       unsigned long long* acc0, uint32_t nacc, hipStream_t s, bool argmax)
 {
     (void)hipGetLastError();
     MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(acc0), 2ull * nacc, 0u, s));
+    if (argmax) MDR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(acc0 + nacc), 2ull * nacc, ~0u, s));
     std::vector<QoiJob> js[2];
     std::vector<uint32_t> maps[2];
     for (size_t i = 0; i < jobs.size(); ++i) {
@@ -317,6 +318,11 @@ mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const 
         MDR_HIP(launch_qoi_vtotal_batch(reinterpret_cast<const QoiJob*>(dv + oj[d]),
                                         reinterpret_cast<const uint32_t*>(dv + om[d]), (uint32_t)maps[d].size(),
                                         d == 1, s));
+    if (argmax)
+        for (int d = 0; d < 2; ++d)
+            MDR_HIP(launch_qoi_vtotal_argmax_batch(reinterpret_cast<const QoiJob*>(dv + oj[d]),
+                                                   reinterpret_cast<const uint32_t*>(dv + om[d]),
+                                                   (uint32_t)maps[d].size(), d == 1, s));
     MDR_HIP(hipEventRecord(slot->done, s));
     slot->pending = true;
     return MDR_OK;

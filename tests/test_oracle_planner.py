@@ -1,6 +1,7 @@
 """Pins for the oracle's planner (tolerance -> planes) and the V_total QoI loop
 (Sec. 5.2, Alg. 3 with MAPE)."""
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -69,3 +70,74 @@ def test_qoi_vtotal_guarantee(orc):
         assert met and tprime <= tau
         real = np.abs(vals[0] ** 2 + vals[1] ** 2 + vals[2] ** 2 - vt).max()
         assert real <= tprime
+
+
+def test_qoi_argmax_first_of_ties_bruteforce(orc):
+    """The CP estimator's point: the first index with the largest estimate,
+    checked by brute force in plain Python floats on small inputs with planted
+    ties (the maximum copied to earlier and later positions)."""
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        n = int(rng.integers(1, 300))
+        v = [rng.laplace(0, 1, n) for _ in range(3)]
+        eps = [float(x) for x in rng.uniform(1e-4, 1e-1, 3)]
+        if n > 3:
+            src = int(rng.integers(0, n))
+            for dst in rng.choice(n, 2, replace=False):
+                for c in range(3):
+                    v[c][dst] = -v[c][src] if trial % 2 else v[c][src]  # |.| ties
+        best, at = -1.0, n
+        for i in range(n):
+            s = 0.0
+            for c in range(3):
+                s = s + eps[c] * ((2.0 * abs(float(v[c][i]))) + eps[c])
+            if s > best:
+                best, at = s, i
+        assert orc.qoi_argmax(v[0], v[1], v[2], eps) == at
+        assert orc.qoi_tau(v[0], v[1], v[2], eps) == best * (1.0 + 2.0 ** -40)
+
+
+def test_cp_bounds_take_the_fewest_decays(orc):
+    """The CP step stops at the first multiple of the decay that brings the
+    worst point's estimate within tau (one decay fewer would not)."""
+    rng = np.random.default_rng(6)
+    for _ in range(50):
+        v = [abs(float(x)) for x in rng.laplace(0, 4, 3)]
+        eps = [float(x) for x in rng.uniform(1e-3, 1.0, 3)]
+        tau = float(10 ** rng.uniform(-8, 0))
+        decay = float(rng.choice([0.5, 0.25, 0.9]))
+        e = orc.cp_bounds(v, eps, tau, decay)
+
+        def est(b):
+            return sum(b[c] * (2 * v[c] + b[c]) for c in range(3)) * (1 + 2.0 ** -40)
+
+        ratio = e[0] / eps[0]
+        steps = round(math.log(ratio) / math.log(decay)) if ratio > 0 else None
+        assert steps is not None and steps >= 0
+        assert est(e) <= tau
+        if steps > 0:
+            back = [x / decay for x in e]
+            assert est(back) > tau
+
+
+@pytest.mark.parametrize("estimator,c", [("mape", 10.0), ("mape", 2.0), ("ma", 10.0), ("cp", 10.0)])
+def test_qoi_estimators_guarantee(orc, estimator, c):
+    """Every estimator of Sec. 5.2 ends with max real V_total error <= estimate
+    <= requested tolerance (the paper's check), and MA is MAPE that never takes
+    the proportional step (an infinite threshold)."""
+    rng = np.random.default_rng(7)
+    sizes = [8, 56, 448, 3584]
+    raw = [workloads.laplace_levels(sizes, 1.0 + 0.5 * i, rng) for i in range(3)]
+    vars3 = [orc.refactor(levels, 32, orc.Params()) for levels in raw]
+    orig = [np.concatenate([a.astype(np.float64) for a in levels]) for levels in raw]
+    vt = orig[0] ** 2 + orig[1] ** 2 + orig[2] ** 2
+    rng_q = float(vt.max() - vt.min())
+    for rel in (1e-1, 1e-2, 1e-4, 1e-6):
+        tau = rel * rng_q
+        vals, ks, tprime, met, it = orc.retrieve_qoi_vtotal(vars3, tau, c=c, estimator=estimator)
+        assert met and tprime <= tau
+        real = np.abs(vals[0] ** 2 + vals[1] ** 2 + vals[2] ** 2 - vt).max()
+        assert real <= tprime
+        if estimator == "ma":
+            same = orc.retrieve_qoi_vtotal(vars3, tau, c=math.inf, estimator="mape")
+            assert same[1] == ks and same[2] == tprime and same[4] == it
