@@ -323,14 +323,41 @@ def bench_serving(args):
     params = mdr.default_params(group_planes=4)
     fields = []
     nbytes_field = 0
+    level_sizes = []
     for f in range(8):
         levels = workloads.field_levels(seed=50 + f, edge=args.serve_edge, nlevels=9, dtype=np.float32)
         dev = [torch.from_numpy(a).cuda() for a in levels]
         nbytes_field = sum(a.nbytes for a in levels)
+        level_sizes = [a.size for a in levels]
         fields.append(mdr.refactor(ctx, dev, 32, params))
         torch.cuda.synchronize()
         del dev, levels
         progress("field", f, "refactored")
+
+    # The next-bound estimators of Sec. 5.2 on the velocity fields 0..2: bits per
+    # value fetched, rounds and time per V_total tolerance (relative to the
+    # largest V_total the ranges allow), each from fresh retrievers
+    qoi_estimators = {}
+    outs3 = [[torch.empty(n, dtype=torch.float32, device="cuda") for n in level_sizes] for _ in range(3)]
+    nvals_field = sum(level_sizes)
+    for name, est, c in (("CP", "cp", 10.0), ("MA", "ma", 10.0), ("MAPE(c=2)", "mape", 2.0),
+                         ("MAPE(c=10)", "mape", 10.0)):
+        rows = {}
+        for tol in (1e-1, 5e-1, 1e-2, 5e-2, 1e-3, 5e-3, 1e-4, 5e-4, 1e-5, 5e-5):
+            rts = [mdr.Retriever(ctx, fields[i]) for i in range(3)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = mdr.retrieve_qoi_vtotal(*rts, tol, outs3, relative=True, mape_c=c, estimator=est)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows["%.0e" % tol] = {"bitrate": info["bytes_fetched"] * 8.0 / (3 * nvals_field),
+                                  "iterations": info["iterations"], "ms": dt * 1e3,
+                                  "gbps": 3 * nbytes_field / dt / 1e9, "met": info["met"]}
+            for rt in rts:
+                rt.close()
+        qoi_estimators[name] = rows
+        progress("qoi estimator", name, rows)
+    del outs3
 
     def make_requests(rate, n):
         reqs = workloads.serving_requests(seed=58, n=n, nfields=8, rate=rate)
@@ -411,6 +438,7 @@ def bench_serving(args):
         "config": {"workload": "serving-8-fields-%d^3-f32-9-levels" % args.serve_edge,
                    "requests": n, "budget_gib": 16, "slots": 64, "parallelism": "single-gpu"},
         "capacity_req_per_s": capacity,
+        "qoi_estimators": qoi_estimators,
         "latency_ms": {"p50": main_load["batched"]["p50_ms"], "p99": main_load["batched"]["p99_ms"]},
         "loads": loads,
     }
