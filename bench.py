@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--batch-vars", type=int, default=256, help="variables of the batched workload")
     ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the launch-shape sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ablation", action="store_true",
+                    help="encoder-design ablation: 32-bit words <-> 32 planes by each design, 2^20..2^28 words")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22,
                     help="values of the finest level the oracle baseline refactors")
     return ap.parse_args()
@@ -445,12 +447,62 @@ def bench_serving(args):
     print(json.dumps(res))
 
 
+def bench_ablation(args):
+    """Sec. 3's encoding experiment on gfx950: n 32-bit words into 32 bitplanes
+    and back by each parallelisation; GB/s of input words, HIP events on the
+    stream the launches use (median of 10 after 2 warm-ups); every size is
+    checked to round-trip."""
+    import torch
+
+    import paper_2505_00227_amd as mdr
+
+    designs = list(mdr.ABLATION_DESIGNS)
+    table = {}
+    for lg in (20, 22, 24, 26, 28):
+        n = 1 << lg
+        x = torch.randint(-2 ** 31, 2 ** 31 - 1, (n,), dtype=torch.int32, device="cuda")
+        out = torch.empty_like(x)
+        for d in designs:
+            planes = torch.empty(32 * mdr.ablation_plane_words(d, n), dtype=torch.int32, device="cuda")
+            row = {}
+            for kind, fn in (("encode", lambda: mdr.ablation_encode(d, x, planes)),
+                             ("decode", lambda: mdr.ablation_decode(d, planes, out))):
+                for _ in range(2):
+                    fn()
+                ts = []
+                for _ in range(10):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    fn()
+                    e1.record()
+                    e1.synchronize()
+                    ts.append(e0.elapsed_time(e1) / 1e3)
+                t = statistics.median(ts)
+                row[kind + "_gbps"] = 4 * n / t / 1e9
+                row[kind + "_us"] = t * 1e6
+            if not torch.equal(out, x):
+                raise RuntimeError("ablation design %s does not round-trip at n=2^%d" % (d, lg))
+            table.setdefault(d, {})["2^%d" % lg] = row
+            del planes
+            progress("ablation", d, "2^%d" % lg, row)
+        del x, out
+    res = {"metric": "bitplane encode / decode GB/s of 32-bit words by design (32 planes)",
+           "unit": "GB/s", "n_gpus": 1, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "ablation-u32-32-planes", "sizes": ["2^%d" % k for k in (20, 22, 24, 26, 28)],
+                      "designs": designs, "parallelism": "single-gpu"},
+           "ablation": table}
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU component "
               "(variables and chunks shard independently); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.ablation:
+        bench_ablation(args)
+        return
     if args.config == 4:
         bench_batched(args)
         return

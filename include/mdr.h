@@ -387,6 +387,36 @@ mdr_status mdr_server_stats(mdr_server* s, mdr_server_info* info);
 /* Stops the engine (queued requests are dropped) and frees everything. */
 void mdr_server_destroy(mdr_server* s);
 
+/*
+ * Encoder-design ablation (Sec. 3; the encoding experiments of Sec. 6): n 32-bit
+ * words into 32 bitplanes (plane p = bit 31 - p) and back, with no alignment,
+ * error table or lossless stage, by each parallelisation the paper compares:
+ *   MDR_ABL_LOCALITY   a thread per block of 32 contiguous values (the layout
+ *                      the refactor path uses);
+ *   MDR_ABL_BALLOT     a value per lane, one wavefront vote per bit;
+ *   MDR_ABL_SHIFT      a value per lane, a five-round OR tree per bit;
+ *   MDR_ABL_BUTTERFLY  a value per lane, the 32x32 transpose across 32 lanes in
+ *                      five exchange rounds;
+ *   MDR_ABL_REGBLOCK   the register block: lane l of each 2048-value region holds
+ *                      its values l, l+64, ..., l+1984 (coalesced loads).
+ * Layouts: plane-major, mdr_ablation_plane_words(design, n) words per plane.
+ * Every design but the register block: word j holds bit t of value 32j + t.
+ * Register block: word 64r + l holds, at bit k, value 2048r + l + 64k.  Values
+ * past n count as 0.  in / planes / out: device memory, 16-byte aligned, owned
+ * by the caller; work is enqueued on `stream`.  Unknown design, NULL or
+ * misaligned pointers: MDR_ERR_INVALID_ARG.
+ */
+typedef enum {
+    MDR_ABL_LOCALITY = 0,
+    MDR_ABL_BALLOT = 1,
+    MDR_ABL_SHIFT = 2,
+    MDR_ABL_BUTTERFLY = 3,
+    MDR_ABL_REGBLOCK = 4
+} mdr_ablation_design;
+uint64_t mdr_ablation_plane_words(int32_t design, uint64_t n);
+mdr_status mdr_ablation_encode(int32_t design, const uint32_t* in, uint64_t n, uint32_t* planes, void* stream);
+mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t n, uint32_t* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,8 @@ def lib():
         L.orc_plan_one_step.argtypes = [u32, u32, u32, vp, vp, vp]
         L.orc_qoi_vtotal_tau.argtypes = [u64, vp, vp, vp, vp]
         L.orc_qoi_vtotal_tau.restype = C.c_double
+        L.orc_abl_planes.argtypes = [C.c_int, vp, u64, vp, u64]
+        L.orc_abl_planes.restype = None
         L.orc_qoi_vtotal_argmax.argtypes = [u64, vp, vp, vp, vp]
         L.orc_qoi_vtotal_argmax.restype = u64
         L.orc_serialize.argtypes = [vp, u32, C.POINTER(_Params), vp, u64, C.POINTER(u64)]
@@ -170,6 +172,17 @@ def fixed_point(x: np.ndarray, e: int, B: int):
 
 def plane_bytes(n: int, W: int) -> int:
     return int(lib().orc_plane_bytes(n, W))
+
+
+def ablation_planes(x: np.ndarray, interleaved: bool) -> np.ndarray:
+    """Sec. 3's experiment: 32-bit words -> [32][words] planes (plane p = bit
+    31-p); block layout, or the register block's interleaved one."""
+    x = np.ascontiguousarray(x, np.uint32)
+    n = x.size
+    words = (n + 2047) // 2048 * 64 if interleaved else (n + 31) // 32
+    planes = np.zeros((32, words), np.uint32)
+    lib().orc_abl_planes(1 if interleaved else 0, _ptr(x), n, _ptr(planes), words)
+    return planes
 
 
 def bitplanes(mag: np.ndarray, sign: np.ndarray, B: int, W: int) -> np.ndarray:

@@ -169,6 +169,35 @@ void orc_bitplanes(const uint64_t* mag, const uint8_t* sign, uint64_t n, uint32_
     free(bitplane);
 }
 
+/*
+ * Sec. 3's encoding experiment: n 32-bit words into 32 bitplanes, plane p =
+ * bit 31-p, plane-major, `words` 32-bit words per plane, values past n = 0.
+ * interleaved = 0 (locality block, and the register-shuffling designs): bit t of
+ * word j is value 32j + t.  interleaved = 1 (register block): the values of a
+ * 2048-value region r are spread over 64 words, bit k of word 64r + l being
+ * value 2048r + l + 64k.
+ * Pins: single-bit inputs by hand; the block layout equals the magnitude rows
+ * of orc_bitplanes; the interleaved layout is the block layout of the input
+ * reordered region by region.
+ */
+void orc_abl_planes(int interleaved, const uint32_t* in, uint64_t n, uint32_t* planes, uint64_t words)
+{
+    memset(planes, 0, (size_t)(32 * words * 4));
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t word, bit;
+        if (interleaved) {
+            uint64_t r = i / 2048, o = i % 2048;
+            word = 64 * r + o % 64;
+            bit = o / 64;
+        } else {
+            word = i / 32;
+            bit = i % 32;
+        }
+        for (int p = 0; p < 32; ++p)
+            if ((in[i] >> (31 - p)) & 1u) planes[(uint64_t)p * words + word] |= 1u << bit;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* per-plane error table                                                      */
 /* ------------------------------------------------------------------------ */

@@ -93,6 +93,7 @@ int orc_plan(uint32_t nlevels, uint32_t B, uint32_t m, const double* E /* nlevel
              double tol, const uint32_t* k_in, uint32_t* k_out, double* bound);
 int orc_plan_one_step(uint32_t nlevels, uint32_t B, uint32_t m, const double* E,
                       const uint64_t* unit_bytes, uint32_t* k /* in/out */);
+void orc_abl_planes(int interleaved, const uint32_t* in, uint64_t n, uint32_t* planes, uint64_t words);
 uint64_t orc_qoi_vtotal_argmax(uint64_t n, const double* vx, const double* vy, const double* vz,
                                const double eps[3]);
 double orc_qoi_vtotal_tau(uint64_t n, const double* vx, const double* vy, const double* vz,

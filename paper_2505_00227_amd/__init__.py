@@ -144,6 +144,9 @@ _SIGS = {
                                  _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
     "mdr_retrieve_qoi_vtotal_with": ([_vp, _vp, _vp, C.c_int, C.c_double, _P(mdr_qoi_params), _P(_vp),
                                       _P(_vp), _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
+    "mdr_ablation_plane_words": ([C.c_int32, _u64], _u64),
+    "mdr_ablation_encode": ([C.c_int32, _vp, _u64, _vp, _vp], C.c_int),
+    "mdr_ablation_decode": ([C.c_int32, _vp, _u64, _vp, _vp], C.c_int),
     "mdr_pipeline_create": ([_vp, _u32, _P(_u64), _u32, C.c_int, _u32, _P(mdr_codec_params), _P(_vp)],
                             C.c_int),
     "mdr_pipeline_refactor": ([_vp, _vp, C.c_int, _P(mdr_pipeline_info)], C.c_int),
@@ -432,6 +435,27 @@ def retrieve_qoi_vtotal(rx: Retriever, ry: Retriever, rz: Retriever, tau: float,
                                              MDR_REL if relative else MDR_ABS, float(tau), C.byref(prm),
                                              o[0], o[1], o[2], _stream_ptr(stream), C.byref(info)))
     return info.as_dict()
+
+
+# ---------------------------------------------------------------- encoder-design ablation
+ABLATION_DESIGNS = {"locality": 0, "ballot": 1, "shift": 2, "butterfly": 3, "regblock": 4}
+
+
+def ablation_plane_words(design: str, n: int) -> int:
+    """mdr_ablation_plane_words: 32-bit words per plane for n values."""
+    return int(_lib.mdr_ablation_plane_words(ABLATION_DESIGNS[design], int(n)))
+
+
+def ablation_encode(design: str, x, planes, stream=None) -> None:
+    """mdr_ablation_encode: x (n uint32-sized elements, device) -> planes [32][words] (device)."""
+    _check(_lib.mdr_ablation_encode(ABLATION_DESIGNS[design], C.c_void_p(x.data_ptr()), x.numel(),
+                                    C.c_void_p(planes.data_ptr()), _stream_ptr(stream)))
+
+
+def ablation_decode(design: str, planes, out, stream=None) -> None:
+    """mdr_ablation_decode: planes (device) -> out (n uint32-sized elements, device)."""
+    _check(_lib.mdr_ablation_decode(ABLATION_DESIGNS[design], C.c_void_p(planes.data_ptr()), out.numel(),
+                                    C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
 
 
 class Server:

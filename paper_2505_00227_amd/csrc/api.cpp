@@ -721,4 +721,37 @@ mdr_status mdr_retrieve_planes(mdr_retriever* rt, const uint32_t* kreq, void* co
     return retrieve_one(rt, k, level_out, static_cast<hipStream_t>(stream), 0.0, info);
 }
 
+uint64_t mdr_ablation_plane_words(int32_t design, uint64_t n)
+{
+    if (design < MDR_ABL_LOCALITY || design > MDR_ABL_REGBLOCK) return 0;
+    return ablation_plane_words(design, n);
+}
+
+static mdr_status ablation_run(int32_t design, bool encode, const uint32_t* in, uint32_t* planes, uint32_t* out,
+                               uint64_t n, void* stream)
+{
+    g_err.clear();
+    if (design < MDR_ABL_LOCALITY || design > MDR_ABL_REGBLOCK) return fail(MDR_ERR_INVALID_ARG, "unknown design");
+    if (n == 0) return MDR_OK;
+    const void* ptrs[2] = {encode ? static_cast<const void*>(in) : static_cast<const void*>(planes),
+                           encode ? static_cast<const void*>(planes) : static_cast<const void*>(out)};
+    for (const void* p : ptrs) {
+        if (!p) return fail(MDR_ERR_INVALID_ARG, "NULL buffer");
+        if (reinterpret_cast<uintptr_t>(p) % 16) return fail(MDR_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+    }
+    (void)hipGetLastError();
+    MDR_HIP(launch_ablation(design, encode, in, n, planes, out, static_cast<hipStream_t>(stream)));
+    return MDR_OK;
+}
+
+mdr_status mdr_ablation_encode(int32_t design, const uint32_t* in, uint64_t n, uint32_t* planes, void* stream)
+{
+    return ablation_run(design, true, in, planes, nullptr, n, stream);
+}
+
+mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t n, uint32_t* out, void* stream)
+{
+    return ablation_run(design, false, nullptr, const_cast<uint32_t*>(planes), out, n, stream);
+}
+
 }  // extern "C"

@@ -193,6 +193,13 @@ struct QoiJob {
 };
 hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                                    hipStream_t s);
+// ---- encoder-design ablation (k_ablation.hip): 32-bit words <-> 32 planes
+constexpr int kAblLocality = 0, kAblBallot = 1, kAblShift = 2, kAblButterfly = 3, kAblRegBlock = 4;
+uint64_t ablation_plane_words(int design, uint64_t n);
+// encode: in[n] -> planes[32][words]; decode: planes -> out[n]
+hipError_t launch_ablation(int design, bool encode, const uint32_t* in, uint64_t n, uint32_t* planes,
+                           uint32_t* out, hipStream_t s);
+
 // after launch_qoi_vtotal_batch on the same jobs: min over points whose estimate
 // equals *acc of base + index, into *arg (which starts at ~0)
 hipError_t launch_qoi_vtotal_argmax_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,

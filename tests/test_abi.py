@@ -58,3 +58,13 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_ablation_host_side_without_gpu():
+    import paper_2505_00227_amd as mdr
+    assert [mdr.ablation_plane_words("locality", n) for n in (0, 1, 32, 33)] == [0, 1, 1, 2]
+    assert [mdr.ablation_plane_words("regblock", n) for n in (0, 1, 2048, 2049)] == [0, 64, 64, 128]
+    assert mdr.mdr_ablation_plane_words(9, 100) == 0
+    assert mdr.mdr_ablation_encode(9, None, 100, None, None) == mdr.MDR_ERR_INVALID_ARG
+    assert mdr.mdr_ablation_encode(0, None, 0, None, None) == mdr.MDR_OK  # nothing to do
+    assert mdr.mdr_ablation_decode(4, None, 10, None, None) == mdr.MDR_ERR_INVALID_ARG

@@ -284,3 +284,32 @@ def test_bound_after_k_planes(orc):
         for k in range(33):
             y = lv.reconstruct(k).astype(np.float64)
             assert np.abs(x - y).max() <= lv.E[k] <= 2.0 ** (lv.e - k)
+
+
+def test_ablation_layouts(orc):
+    """Sec. 3's encoding experiment (32-bit words -> 32 planes): single bits land
+    where each layout says; the block layout equals the magnitude rows of the
+    refactor path's bitplanes; the register block's interleaved layout is the
+    block layout of the input reordered region by region."""
+    rng = np.random.default_rng(9)
+    for n in (1, 31, 33, 2047, 2049, 5000):
+        for _ in range(5):
+            x = np.zeros(n, np.uint32)
+            i, b = int(rng.integers(0, n)), int(rng.integers(0, 32))
+            x[i] = np.uint32(1) << np.uint32(b)
+            blk = orc.ablation_planes(x, False)
+            assert blk.sum(dtype=np.uint64) == 1 << (i % 32) and blk[31 - b, i // 32] == 1 << (i % 32)
+            itl = orc.ablation_planes(x, True)
+            r, o = divmod(i, 2048)
+            assert itl.sum(dtype=np.uint64) == 1 << (o // 64)
+            assert itl[31 - b, 64 * r + o % 64] == 1 << (o // 64)
+        x = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+        blk = orc.ablation_planes(x, False)
+        rows = orc.bitplanes(x.astype(np.uint64), np.zeros(n, np.uint8), 32, 32)
+        words = rows[1:].copy().view(np.uint32)
+        assert np.array_equal(words, blk)
+        regions = (n + 2047) // 2048
+        xp = np.zeros(regions * 2048, np.uint32)
+        xp[:n] = x
+        y = xp.reshape(regions, 32, 64).transpose(0, 2, 1).reshape(-1)  # y[32(64r+l)+k] = x[2048r+l+64k]
+        assert np.array_equal(orc.ablation_planes(y, False), orc.ablation_planes(x, True))
