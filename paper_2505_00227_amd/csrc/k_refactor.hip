@@ -11,6 +11,9 @@
 namespace mdr {
 namespace {
 
+// rows a general-path encoder workgroup stages in LDS at once
+constexpr uint32_t kPassRows = 33;
+
 // ------------------------------------------------------------------ helpers
 __device__ __forceinline__ int frexp_exp_f32(uint32_t absbits)
 {
@@ -247,7 +250,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     if (tid < kMaxRows) s_hoff[tid] = job.hist_off[tid];
     (void)m;
     uint32_t* s_hist = FAST ? s_hist_fast : s_dyn;
-    uint32_t* s_pl = FAST ? s_dyn : s_dyn + nunits * 256;  // [B+1][256]
+    uint32_t* s_pl = FAST ? s_dyn : s_dyn + nunits * 256;  // [rows of one pass][256]
 
     for (uint32_t i = tid; i < nunits * 256; i += kThreads) s_hist[i] = 0;
     if (tid < kMaxRows) s_trans[tid] = 0;
@@ -580,66 +583,79 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 rows_out(std::false_type{});
             continue;
         }
-        __syncthreads();  // every thread is done with its y values
-        s_pl[tid] = sgn;
-#pragma unroll
-        for (int c = 0; c < 32; ++c)
-            if (c < (int)B) s_pl[(B - c) * kTileBlocks + tid] = lo[c];
-        if constexpr (F64) {
-#pragma unroll
-            for (int c = 0; c < 32; ++c)
-                if (32 + c < (int)B) s_pl[(B - 32 - c) * kTileBlocks + tid] = hi[c];
-        }
-        __syncthreads();
-
-        // ---- per row: coalesced store, byte histogram, word transitions.
-        // Rows go four at a time so their LDS reads overlap; zero bytes are
-        // counted by difference later and go to this thread's sink slot here.
+        // Rows go through LDS in passes of at most kPassRows (f64's 65 rows in
+        // two), so that two f64 workgroups fit a CU.
+        const uint32_t nrows = B + 1;
+        const uint32_t npass = nrows > kPassRows ? 2u : 1u;
+        const uint32_t per = (nrows + npass - 1) / npass;
         const bool have_prev = t > t0;
         const bool lead = valid && (tid % G) == 0 && (tid >= G || have_prev);
-        for (uint32_t r0 = 0; r0 <= B; r0 += 4) {
-            uint32_t w[4], pv[4], pv1[4], nx[4];
+        for (uint32_t pass = 0; pass < npass; ++pass) {
+            const uint32_t rlo = pass * per, rhi = min(nrows, rlo + per);
+            __syncthreads();  // every thread is done with its y values / the previous pass's rows
+            if (rlo == 0) s_pl[tid] = sgn;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t r = min(r0 + i, B);
-                const uint32_t* row = s_pl + r * kTileBlocks;
-                w[i] = row[tid];
-                pv[i] = tid >= G ? row[tid - G] : s_prev[r][tid];
-                if constexpr (G == 2) {
-                    nx[i] = row[tid + 1 < kTileBlocks ? tid + 1 : tid];
-                    pv1[i] = tid >= G ? row[tid - 1] : s_prev[r][1];
+            for (int c = 0; c < 32; ++c) {
+                const uint32_t r = B - (uint32_t)c;  // row of bit c (when c < B)
+                if (c < (int)B && r >= rlo && r < rhi) s_pl[(r - rlo) * kTileBlocks + tid] = lo[c];
+            }
+            if constexpr (F64) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) {
+                    const uint32_t r = B - 32u - (uint32_t)c;  // row of bit 32 + c
+                    if (32 + c < (int)B && r >= rlo && r < rhi) s_pl[(r - rlo) * kTileBlocks + tid] = hi[c];
                 }
             }
+            __syncthreads();
+
+            // ---- per row: coalesced store, byte histogram, word transitions.
+            // Rows go four at a time so their LDS reads overlap; zero bytes are
+            // counted by difference later and go to this thread's sink slot here.
+            for (uint32_t r0 = rlo; r0 < rhi; r0 += 4) {
+                uint32_t w[4], pv[4], pv1[4], nx[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t r = r0 + i;
-                if (r > B) break;
-                if (valid) {
-                    rows[(uint64_t)r * nbd + blk] = w[i];
-                    uint32_t* h = s_hist + s_hoff[r];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t byte = (w[i] >> (8 * q)) & 0xFFu;
-                        atomicAdd(byte ? &h[byte] : &s_zero[tid], 1u);
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t r = min(r0 + i, rhi - 1);
+                    const uint32_t* row = s_pl + (r - rlo) * kTileBlocks;
+                    w[i] = row[tid];
+                    pv[i] = tid >= G ? row[tid - G] : s_prev[r][tid];
+                    if constexpr (G == 2) {
+                        nx[i] = row[tid + 1 < kTileBlocks ? tid + 1 : tid];
+                        pv1[i] = tid >= G ? row[tid - 1] : s_prev[r][1];
                     }
                 }
-                bool flag = w[i] != pv[i];
-                if constexpr (G == 2) flag = flag || nx[i] != pv1[i];
-                unsigned long long bal = __ballot(lead && flag);
-                if (lane == 0 && bal) atomicAdd(&s_trans[r], (uint32_t)__popcll(bal));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t r = r0 + i;
+                    if (r >= rhi) break;
+                    if (valid) {
+                        rows[(uint64_t)r * nbd + blk] = w[i];
+                        uint32_t* h = s_hist + s_hoff[r];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t byte = (w[i] >> (8 * q)) & 0xFFu;
+                            atomicAdd(byte ? &h[byte] : &s_zero[tid], 1u);
+                        }
+                    }
+                    bool flag = w[i] != pv[i];
+                    if constexpr (G == 2) flag = flag || nx[i] != pv1[i];
+                    unsigned long long bal = __ballot(lead && flag);
+                    if (lane == 0 && bal) atomicAdd(&s_trans[r], (uint32_t)__popcll(bal));
+                }
             }
+            // first / last words of this workgroup's range, for the boundaries
+            if (t == t0 && tid < G)
+                for (uint32_t r = rlo; r < rhi; ++r)
+                    recs[((uint64_t)wg * kMaxRows + r) * 2 * G + tid] = s_pl[(r - rlo) * kTileBlocks + tid];
+            if (valid && blk + G > last_blk)
+                for (uint32_t r = rlo; r < rhi; ++r)
+                    recs[((uint64_t)wg * kMaxRows + r) * 2 * G + G + (blk - (last_blk + 1 - G))] =
+                        s_pl[(r - rlo) * kTileBlocks + tid];
+            __syncthreads();
+            if (tid >= kTileBlocks - G)
+                for (uint32_t r = rlo; r < rhi; ++r)
+                    s_prev[r][tid - (kTileBlocks - G)] = s_pl[(r - rlo) * kTileBlocks + tid];
         }
-        // first / last words of this workgroup's range, for the boundaries
-        if (t == t0 && tid < G)
-            for (uint32_t r = 0; r <= B; ++r)
-                recs[((uint64_t)wg * kMaxRows + r) * 2 * G + tid] = s_pl[r * kTileBlocks + tid];
-        if (valid && blk + G > last_blk)
-            for (uint32_t r = 0; r <= B; ++r)
-                recs[((uint64_t)wg * kMaxRows + r) * 2 * G + G + (blk - (last_blk + 1 - G))] =
-                    s_pl[r * kTileBlocks + tid];
-        __syncthreads();
-        if (tid >= kTileBlocks - G)
-            for (uint32_t r = 0; r <= B; ++r) s_prev[r][tid - (kTileBlocks - G)] = s_pl[r * kTileBlocks + tid];
         (void)NROW;
     }
 
@@ -1092,9 +1108,9 @@ hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint
 
 size_t encode_lds_bytes(uint32_t nunits, uint32_t B, uint32_t m, bool f64)
 {
-    (void)f64;
     if (!f64 && B == 32 && m == 4) return 0;  // the fast path: static LDS only
-    const size_t planes = (size_t)(B + 1) * kTileBlocks * sizeof(uint32_t);
+    const uint32_t npass = B + 1 > kPassRows ? 2u : 1u;  // as the kernel stages its rows
+    const size_t planes = (size_t)((B + 1 + npass - 1) / npass) * kTileBlocks * sizeof(uint32_t);
     return (size_t)nunits * 256 * sizeof(uint32_t) + planes;
 }
 
