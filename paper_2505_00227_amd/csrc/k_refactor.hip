@@ -718,11 +718,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
 }
 
 // ------------------------------------------------------------------ hybrid selection
-// One workgroup of 1024 threads per (unit, level) (Alg. 2): gather the byte
+// One workgroup of kSelThreads threads per (unit, level) (Alg. 2): gather the byte
 // histogram and the run count, build length-limited Huffman code lengths with
 // the two-queue construction, canonical codes, both size estimates, and the
 // method decision.  Units that Alg. 2 can only copy (S <= T_s) skip the codebook.
-constexpr int kSelThreads = 1024;
+// 512 threads: the tree is built on one lane, so smaller workgroups let more
+// units build theirs at once (a batch of many variables has thousands; 1024
+// threads made such a batch's selection 3x slower, 256 a single field's 20 %)
+constexpr int kSelThreads = 512;
 
 __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
                                                          const SelectLevel* __restrict__ levels)
@@ -833,9 +836,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
     // ---- Huffman code lengths: two-queue tree, depths by pointer jumping, and
     // the per-length count adjustment when the tree is deeper than huf_lmax
     if (need_code) {
-        // rank of each present symbol in (count, symbol) order: four threads
-        // per symbol, 64 comparisons each
+        // rank of each present symbol in (count, symbol) order: kRankParts
+        // threads per symbol, 256 / kRankParts comparisons each
         {
+            constexpr uint32_t kRankParts = kSelThreads / 256;
+            constexpr int kSpan = 256 / kRankParts;
             const uint32_t sym = tid & 255, part = tid >> 8;
             const unsigned long long fsym = s_f[sym];
             if (tid < 256) s_dp[tid] = 0;
@@ -844,7 +849,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             if (fsym) {
                 int r = 0;
 #pragma unroll 16
-                for (int q = part * 64; q < (int)part * 64 + 64; ++q) {
+                for (int q = (int)part * kSpan; q < (int)part * kSpan + kSpan; ++q) {
                     const unsigned long long fs = s_f[q];
                     r += (fs && (fs < fsym || (fs == fsym && q < (int)sym))) ? 1 : 0;
                 }
@@ -907,22 +912,36 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         const int nnodes = nl > 1 ? 2 * nl - 1 : 0;
         int* s_d = s_dp;
         int* s_p = s_dp + 512;
-        if (tid < nnodes) {
-            s_p[tid] = s_parent[tid];
-            s_d[tid] = (tid == (uint32_t)(nnodes - 1)) ? 0 : 1;
+        constexpr int kNodesPer = (512 + kSelThreads - 1) / kSelThreads;  // nodes per thread
+#pragma unroll
+        for (int h = 0; h < kNodesPer; ++h) {
+            const int v = (int)tid + h * kSelThreads;
+            if (v < nnodes) {
+                s_p[v] = s_parent[v];
+                s_d[v] = (v == nnodes - 1) ? 0 : 1;
+            }
         }
         __syncthreads();
         for (int round = 0; round < 9; ++round) {
-            int nd = 0, np = 0;
-            if (tid < nnodes) {
-                int p = s_p[tid];
-                nd = s_d[tid] + s_d[p];
-                np = s_p[p];
+            int nd[kNodesPer], np[kNodesPer];
+#pragma unroll
+            for (int h = 0; h < kNodesPer; ++h) {
+                const int v = (int)tid + h * kSelThreads;
+                nd[h] = 0, np[h] = 0;
+                if (v < nnodes) {
+                    const int p = s_p[v];
+                    nd[h] = s_d[v] + s_d[p];
+                    np[h] = s_p[p];
+                }
             }
             __syncthreads();
-            if (tid < nnodes) {
-                s_d[tid] = nd;
-                s_p[tid] = np;
+#pragma unroll
+            for (int h = 0; h < kNodesPer; ++h) {
+                const int v = (int)tid + h * kSelThreads;
+                if (v < nnodes) {
+                    s_d[v] = nd[h];
+                    s_p[v] = np[h];
+                }
             }
             __syncthreads();
         }
@@ -940,7 +959,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             // ITU-T T.81 Annex K count adjustment on one lane, then hand the
             // lengths out again: heaviest leaf (last in sorted order) shortest
             uint32_t* s_bits = reinterpret_cast<uint32_t*>(s_parent);  // 256+1 entries
-            if (tid <= 256) s_bits[tid] = 0;
+            for (uint32_t i = tid; i <= 256; i += kSelThreads) s_bits[i] = 0;
             __syncthreads();
             if (tid < nl) atomicAdd(&s_bits[s_d[tid]], 1u);
             __syncthreads();
