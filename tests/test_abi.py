@@ -68,3 +68,18 @@ def test_ablation_host_side_without_gpu():
     assert mdr.mdr_ablation_encode(9, None, 100, None, None) == mdr.MDR_ERR_INVALID_ARG
     assert mdr.mdr_ablation_encode(0, None, 0, None, None) == mdr.MDR_OK  # nothing to do
     assert mdr.mdr_ablation_decode(4, None, 10, None, None) == mdr.MDR_ERR_INVALID_ARG
+
+
+def test_qoi_estimator_validation_without_gpu():
+    import paper_2505_00227_amd as mdr
+    prm = mdr.mdr_qoi_params()
+    prm.estimator = 7
+    info = mdr.mdr_qoi_info()
+    st = mdr.mdr_retrieve_qoi_vtotal_with(None, None, None, mdr.MDR_ABS, 1.0, C.byref(prm), None, None, None,
+                                          None, C.byref(info))
+    assert st == mdr.MDR_ERR_INVALID_ARG and b"estimator" in mdr.mdr_last_error()
+    prm.estimator = mdr.MDR_QOI_CP
+    prm.cp_decay = 1.0
+    st = mdr.mdr_retrieve_qoi_vtotal_with(None, None, None, mdr.MDR_ABS, 1.0, C.byref(prm), None, None, None,
+                                          None, C.byref(info))
+    assert st == mdr.MDR_ERR_INVALID_ARG and b"cp_decay" in mdr.mdr_last_error()
