@@ -194,7 +194,32 @@ __global__ __launch_bounds__(kThreads) void k_qoi_vtotal_argmax_batch(const QoiJ
     if ((threadIdx.x & 63) == 0 && first != ~0ull) atomicMin(j.arg, first);
 }
 
+// Device values into pinned host memory: every thread of the grid walks all
+// spans with one stride, so each span's words go out as consecutive 256-byte
+// wavefront stores; system-scope stores write through to host memory.  Runs
+// on its own stream beside the compute.
+__global__ __launch_bounds__(kThreads) void k_copy_out(const CopySpans sp)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t k = 0; k < sp.n; ++k) {
+        const uint32_t* src = sp.src[k];
+        uint32_t* dst = sp.dst[k];
+        const uint64_t nw = sp.words[k];
+        for (uint64_t i = t; i < nw; i += stride)
+            __hip_atomic_store(dst + i, src[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_copy_out(const CopySpans& sp, hipStream_t s)
+{
+    if (sp.n == 0) return hipSuccess;
+    if (sp.n > kCopySpans) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy_out, dim3(2048), dim3(kThreads), 0, s, sp);
+    return hipGetLastError();
+}
 
 hipError_t launch_qoi_vtotal_argmax_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                                           hipStream_t s)

@@ -193,6 +193,18 @@ struct QoiJob {
 };
 hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                                    hipStream_t s);
+// ---- device values to pinned host memory by a kernel (k_retrieve.hip): up to
+// kCopySpans spans of 4-byte words, each from device memory to the device
+// address of pinned host memory
+constexpr int kCopySpans = 16;
+struct CopySpans {
+    const uint32_t* src[kCopySpans];
+    uint32_t* dst[kCopySpans];
+    uint64_t words[kCopySpans];
+    uint32_t n;
+};
+hipError_t launch_copy_out(const CopySpans& sp, hipStream_t s);
+
 // ---- encoder-design ablation (k_ablation.hip): 32-bit words <-> 32 planes
 constexpr int kAblLocality = 0, kAblBallot = 1, kAblShift = 2, kAblButterfly = 3, kAblRegBlock = 4;
 uint64_t ablation_plane_words(int design, uint64_t n);

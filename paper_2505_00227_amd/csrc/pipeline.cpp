@@ -330,6 +330,17 @@ mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, vo
     // one absolute tolerance for every chunk: relative to the whole field's range
     const double tol_abs = kind == MDR_REL ? tol * (p->value_hi - p->value_lo) : tol;
     uint8_t* out = static_cast<uint8_t*>(host_out);
+    // pinned output: the values leave through a kernel writing the host memory's
+    // device address (the copy engine's downloads slowed to half speed while
+    // the next chunk's streams were uploading); pageable output: copies
+    uint8_t* out_dev = nullptr;
+    {
+        void* dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, host_out, 0) == hipSuccess)
+            out_dev = static_cast<uint8_t*>(dp);
+        else
+            (void)hipGetLastError();
+    }
     const uint32_t N = p->nchunks;
     std::vector<hipEvent_t> h2d_a(N), h2d_b(N), cmp_a(N), cmp_b(N), d2h_a(N), d2h_b(N);
     for (uint32_t c = 0; c < N; ++c) {
@@ -404,12 +415,22 @@ mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, vo
         MDR_HIP(hipEventRecord(d2h_a[c], C));
         o = 0;
         uint64_t ho = (uint64_t)c * p->chunk_bytes;
+        CopySpans sp{};
         for (uint32_t l = 0; l < p->nlevels; ++l) {
             const uint64_t nb = p->sizes[l] * elem(p);
-            if (nb) MDR_HIP(hipMemcpyAsync(out + ho, static_cast<uint8_t*>(p->dev_out[s].p) + o, nb, hipMemcpyDeviceToHost, C));
+            const uint8_t* src = static_cast<uint8_t*>(p->dev_out[s].p) + o;
+            if (nb && out_dev && sp.n < (uint32_t)kCopySpans) {
+                sp.src[sp.n] = reinterpret_cast<const uint32_t*>(src);
+                sp.dst[sp.n] = reinterpret_cast<uint32_t*>(out_dev + ho);
+                sp.words[sp.n] = nb / 4;
+                ++sp.n;
+            } else if (nb) {
+                MDR_HIP(hipMemcpyAsync(out + ho, src, nb, hipMemcpyDeviceToHost, C));
+            }
             ho += nb;
             o += align256(nb);
         }
+        MDR_HIP(launch_copy_out(sp, C));
         MDR_HIP(hipEventRecord(d2h_b[c], C));
         d2h_bytes += p->chunk_bytes;
         if (!overlap) {

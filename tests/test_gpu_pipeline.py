@@ -48,12 +48,17 @@ def test_pipeline_matches_oracle_per_chunk(mdr, ctx, dtype, B):
         assert info["h2d_bytes"] == flat.nbytes
         for c in range(nchunks):
             assert pipe.chunk(c).serialize() == oracle.serialize(orc[c], op), ("chunk", c)
-        for rel in (0.0, 1e-4):
-            pipe.retrieve(rel, out, relative=True, overlap=overlap)
-            got = out.numpy()
-            o = 0
-            for c in range(nchunks):
-                vals, k, bound, met = oracle.retrieve_to(orc[c], rel * (hi - lo), relative=False)
-                ref = np.concatenate(vals)
-                assert_same_bits(got[o:o + ref.size], ref, ("chunk", c, "rel", rel))
-                o += ref.size
+        # pinned output (written by a kernel through its device address) and
+        # pageable output (copies); both start poisoned
+        for pinned in (True, False):
+            dst = out if pinned else torch.empty(flat.size, dtype=tdt)
+            for rel in (0.0, 1e-4):
+                dst.fill_(float("nan"))
+                pipe.retrieve(rel, dst, relative=True, overlap=overlap)
+                got = dst.numpy()
+                o = 0
+                for c in range(nchunks):
+                    vals, k, bound, met = oracle.retrieve_to(orc[c], rel * (hi - lo), relative=False)
+                    ref = np.concatenate(vals)
+                    assert_same_bits(got[o:o + ref.size], ref, ("chunk", c, "rel", rel, "pinned", pinned))
+                    o += ref.size
