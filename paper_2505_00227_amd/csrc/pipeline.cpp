@@ -12,6 +12,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <utility>
 
 #include "api_internal.hpp"
 
@@ -24,6 +25,9 @@ struct HostChunk {
     std::vector<uint64_t> unit_off;  // [level * kMaxRows + slot]: offset in rows (DC) or payload blob
     void* rows = nullptr;            // pinned: plane rows as laid out on the device
     uint64_t rows_bytes = 0;
+    // byte spans of `rows` that direct-copy units occupy, ascending and merged; only these
+    // cross PCIe, since the rows of coded groups are never read once their payloads exist
+    std::vector<std::pair<uint64_t, uint64_t>> dc;
     void* pay = nullptr;             // pinned: compressed payloads
     uint64_t pay_bytes = 0, pay_cap = 0;
     ~HostChunk()
@@ -98,6 +102,7 @@ void keep_meta(const mdr_refactored* R, HostChunk& hc, uint64_t& pay_used)
     const uint8_t* rows0 = reinterpret_cast<const uint8_t*>(R->levels.empty() ? nullptr : R->levels[0].rows);
     const uint8_t* pay0 = static_cast<const uint8_t*>(R->payload_arena->p);
     pay_used = 0;
+    hc.dc.clear();
     for (size_t l = 0; l < R->levels.size(); ++l)
         for (uint32_t s = 0; s <= R->B; ++s) {
             const UnitRec& u = R->levels[l].units[s];
@@ -105,6 +110,7 @@ void keep_meta(const mdr_refactored* R, HostChunk& hc, uint64_t& pay_used)
             uint64_t o;
             if (u.method == MDR_DC) {
                 o = (uint64_t)(u.dev - rows0);
+                if (u.bytes) hc.dc.emplace_back(o, u.bytes);
             } else {
                 o = (uint64_t)(u.dev - pay0);
                 pay_used = std::max(pay_used, o + u.bytes);
@@ -113,6 +119,23 @@ void keep_meta(const mdr_refactored* R, HostChunk& hc, uint64_t& pay_used)
             hc.levels[l].units[s].dev = nullptr;
         }
     for (LevelRec& L : hc.levels) L.rows = nullptr;
+    std::sort(hc.dc.begin(), hc.dc.end());
+    size_t k = 0;
+    for (size_t i = 0; i < hc.dc.size(); ++i) {
+        if (k && hc.dc[k - 1].first + hc.dc[k - 1].second == hc.dc[i].first)
+            hc.dc[k - 1].second += hc.dc[i].second;
+        else
+            hc.dc[k++] = hc.dc[i];
+    }
+    hc.dc.resize(k);
+}
+
+// bytes of a chunk's rows that cross PCIe
+uint64_t dc_bytes(const HostChunk& hc)
+{
+    uint64_t b = 0;
+    for (const auto& d : hc.dc) b += d.second;
+    return b;
 }
 
 double elapsed(hipEvent_t a, hipEvent_t b)
@@ -255,10 +278,13 @@ mdr_status mdr_pipeline_refactor(mdr_pipeline* p, const void* host_values, int o
         hc.pay_bytes = pay_used;
         MDR_HIP(hipStreamWaitEvent(C, cmp_b[c], 0));
         MDR_HIP(hipEventRecord(d2h_a[c], C));
-        MDR_HIP(hipMemcpyAsync(hc.rows, R->rows_arena->p, rows_bytes, hipMemcpyDeviceToHost, C));
+        for (const auto& d : hc.dc)
+            MDR_HIP(hipMemcpyAsync(static_cast<uint8_t*>(hc.rows) + d.first,
+                                   static_cast<const uint8_t*>(R->rows_arena->p) + d.first, d.second,
+                                   hipMemcpyDeviceToHost, C));
         if (pay_used) MDR_HIP(hipMemcpyAsync(hc.pay, R->payload_arena->p, pay_used, hipMemcpyDeviceToHost, C));
         MDR_HIP(hipEventRecord(d2h_b[c], C));
-        d2h_bytes += rows_bytes + pay_used;
+        d2h_bytes += dc_bytes(hc) + pay_used;
         for (const LevelRec& L : R->levels)
             for (uint32_t s = 0; s <= p->B; ++s)
                 if (L.units[s].method != MDR_PLACEHOLDER) stream_bytes += L.units[s].bytes;
@@ -366,11 +392,14 @@ mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, vo
         const int s = c & 1;
         if (c >= 2) MDR_HIP(hipStreamWaitEvent(A, cmp_b[c - 2], 0));  // slot free once chunk c-2 is rebuilt
         MDR_HIP(hipEventRecord(h2d_a[c], A));
-        MDR_HIP(hipMemcpyAsync(p->dev_rows[s].p, hc.rows, hc.rows_bytes, hipMemcpyHostToDevice, A));
+        for (const auto& d : hc.dc)
+            MDR_HIP(hipMemcpyAsync(static_cast<uint8_t*>(p->dev_rows[s].p) + d.first,
+                                   static_cast<const uint8_t*>(hc.rows) + d.first, d.second,
+                                   hipMemcpyHostToDevice, A));
         if (hc.pay_bytes)
             MDR_HIP(hipMemcpyAsync(p->dev_pay[s].p, hc.pay, hc.pay_bytes, hipMemcpyHostToDevice, A));
         MDR_HIP(hipEventRecord(h2d_b[c], A));
-        h2d_bytes += hc.rows_bytes + hc.pay_bytes;
+        h2d_bytes += dc_bytes(hc) + hc.pay_bytes;
         return MDR_OK;
     };
     mdr_status st = h2d(0);
@@ -480,7 +509,9 @@ mdr_status mdr_pipeline_chunk(const mdr_pipeline* p, uint32_t chunk, mdr_context
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(chunk rows)");
     e = pay->alloc(ctx->pool, std::max<uint64_t>(hc.pay_bytes, 256));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(chunk payloads)");
-    MDR_HIP(hipMemcpy(rows->p, hc.rows, hc.rows_bytes, hipMemcpyHostToDevice));
+    for (const auto& d : hc.dc)
+        MDR_HIP(hipMemcpy(static_cast<uint8_t*>(rows->p) + d.first, static_cast<const uint8_t*>(hc.rows) + d.first,
+                          d.second, hipMemcpyHostToDevice));
     if (hc.pay_bytes) MDR_HIP(hipMemcpy(pay->p, hc.pay, hc.pay_bytes, hipMemcpyHostToDevice));
     auto R = device_view(p, hc, static_cast<uint8_t*>(rows->p), static_cast<uint8_t*>(pay->p));
     R->ctx = ctx;
