@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--batch-vars", type=int, default=256, help="variables of the batched workload")
     ap.add_argument("--no-tune", action="store_true", help="batched workload: skip the launch-shape sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--multilevel", action="store_true",
+                    help="multilevel decomposition of the 512^3 field, and the field through the whole path")
     ap.add_argument("--ablation", action="store_true",
                     help="encoder-design ablation: 32-bit words <-> 32 planes by each design, 2^20..2^28 words")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22,
@@ -494,6 +496,97 @@ def bench_ablation(args):
     print(json.dumps(res))
 
 
+def bench_multilevel(args):
+    """Multilevel decomposition of the smooth 512^3 field (8 steps, 9 levels) in
+    float32 and float64: decompose and recompose times (median of 10 after 2
+    warm-ups, HIP events on the stream the launches use), GB/s of field data,
+    and the fraction of HBM peak for 2 * n * s algorithmic bytes per pass (read
+    the field and write the levels, or the reverse); then the field through the
+    whole path: decompose, refactor, and six incremental retrievals from 1e-1
+    to 1e-6 of the field's range, each recomposed."""
+    import torch
+
+    import paper_2505_00227_amd as mdr
+    import workloads
+
+    shape, nsteps = (512, 512, 512), 8
+    n = shape[0] * shape[1] * shape[2]
+    sizes = mdr.level_sizes(shape, nsteps)
+    table = {}
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        ts = []
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        return statistics.median(ts)
+
+    u64 = workloads.smooth_field_tensor(2, shape, "cuda")
+    for name, dt, B in (("f32", torch.float32, 32), ("f64", torch.float64, 64)):
+        u = u64.to(dt)
+        s = u.element_size()
+        c = torch.empty(n, dtype=dt, device="cuda")
+        v = torch.empty_like(u)
+        td = timed(lambda: mdr.decompose(u, nsteps, c))
+        tr = timed(lambda: mdr.recompose(c, nsteps, v))
+        err = float((v.double() - u.double()).abs().max())
+        if err > 4 * nsteps * torch.finfo(dt).eps * float(u.abs().max()):
+            raise RuntimeError("recompose(decompose(u)) is off by %g" % err)
+        row = {"decompose_ms": td * 1e3, "recompose_ms": tr * 1e3,
+               "decompose_gbps": n * s / td / 1e9, "recompose_gbps": n * s / tr / 1e9,
+               "decompose_hbm_frac": 2 * n * s / td / 8e12, "recompose_hbm_frac": 2 * n * s / tr / 8e12,
+               "round_trip_max_err": err}
+        # the field through the whole path
+        ctx = mdr.Context(0)
+        levels = list(torch.split(c, sizes))
+        cat = torch.empty(n, dtype=dt, device="cuda")
+        outs = list(torch.split(cat, sizes))  # retrieved levels land in one buffer
+        rng_u = float(u.max() - u.min())
+        bounds = [10.0 ** -k for k in range(1, 7)]
+
+        def step():
+            mdr.decompose(u, nsteps, c)
+            r = mdr.refactor(ctx, levels, B)
+            rt = mdr.Retriever(ctx, r)
+            worst = 0.0
+            for b in bounds:
+                rt.retrieve(b * rng_u, outs, relative=False)
+                mdr.recompose(cat, nsteps, v)
+            torch.cuda.synchronize()
+            worst = float((v.double() - u.double()).abs().max())
+            rt.close()
+            r.close()
+            return worst
+
+        step()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            worst = step()
+            ts.append(time.perf_counter() - t0)
+        if worst > 1e-6 * rng_u * (1 + 1e-6) + 4 * nsteps * torch.finfo(dt).eps * float(u.abs().max()):
+            raise RuntimeError("field error %g above the 1e-6 bound" % worst)
+        row["path_step_ms"] = statistics.median(ts) * 1e3
+        row["path_gbps"] = n * s / statistics.median(ts) / 1e9
+        row["path_final_max_err_rel"] = worst / rng_u
+        ctx.close()
+        table[name] = row
+        progress("multilevel", name, row)
+        del u, c, v, levels, outs, cat
+    res = {"metric": "multilevel decompose / recompose GB/s of field data (frac of HBM peak)",
+           "unit": "GB/s", "n_gpus": 1, "dtype": "f32,f64", "data": "synthetic",
+           "config": {"workload": "field-512^3-8-steps-9-levels", "level_sizes": sizes,
+                      "parallelism": "single-gpu"},
+           "multilevel": table}
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -502,6 +595,9 @@ def main():
         sys.exit(2)
     if args.ablation:
         bench_ablation(args)
+        return
+    if args.multilevel:
+        bench_multilevel(args)
         return
     if args.config == 4:
         bench_batched(args)

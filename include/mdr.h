@@ -417,6 +417,38 @@ uint64_t mdr_ablation_plane_words(int32_t design, uint64_t n);
 mdr_status mdr_ablation_encode(int32_t design, const uint32_t* in, uint64_t n, uint32_t* planes, void* stream);
 mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t n, uint32_t* out, void* stream);
 
+/* ---- Multilevel decomposition (the coefficient levels of Sec. 2/3) ---------
+ * The method's input is the coefficient levels of a multilevel decomposition
+ * that the paper takes from earlier work without spelling it out.  Reading
+ * used here: hierarchical multilinear interpolation (MGARD's interpolation
+ * step, no L2-projection correction).  The field is row-major n0 x n1 x n2
+ * (n2 fastest).  Step j (j = 0 finest) works on the stride h = 2^j grid; each
+ * of its nodes not on the stride-2h grid gets c = u - P, where P refines the
+ * stride-2h values along n2, then n1, then n0: (a + b) * 0.5 of the two
+ * neighbours on the axis, or the left neighbour alone past the last coarse
+ * node of a line.  Arithmetic is in the field's type, one rounding per
+ * operation.  Level 0 holds the raw values of the stride-2^nsteps grid; level
+ * l (1..nsteps) holds the nodes of step nsteps - l in the row-major order of
+ * their grid.  P is a convex combination, so after recomposition the field's
+ * max error is at most the sum of the levels' max coefficient errors (plus
+ * rounding): a tolerance met on the levels is met on the field.
+ *
+ * mdr_level_sizes: host only; sizes[nsteps + 1] = values per level.
+ * mdr_decompose: field (n0*n1*n2 values) -> coeffs, the levels concatenated
+ *   coarsest first (level l at offset sizes[0] + ... + sizes[l-1]).
+ * mdr_recompose: the inverse; every value of `field` is written.
+ * Both: device memory owned by the caller, aligned to the value size, not
+ * overlapping; work is enqueued on `stream` (one launch to decompose,
+ * nsteps + 1 to recompose).  nsteps <= 30 (steps past the grid's extent give
+ * empty levels); n0, n1 < 65536 and n2 < 2^31, else MDR_ERR_UNSUPPORTED;
+ * NULL, misaligned or overlapping buffers, a bad dtype or nsteps:
+ * MDR_ERR_INVALID_ARG.  An empty grid is a no-op. */
+mdr_status mdr_level_sizes(uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps, uint64_t* sizes);
+mdr_status mdr_decompose(mdr_dtype dtype, const void* field, uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps,
+                         void* coeffs, void* stream);
+mdr_status mdr_recompose(mdr_dtype dtype, const void* coeffs, uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps,
+                         void* field, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

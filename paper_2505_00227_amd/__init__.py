@@ -144,6 +144,9 @@ _SIGS = {
                                  _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
     "mdr_retrieve_qoi_vtotal_with": ([_vp, _vp, _vp, C.c_int, C.c_double, _P(mdr_qoi_params), _P(_vp),
                                       _P(_vp), _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
+    "mdr_level_sizes": ([_u64, _u64, _u64, _u32, _P(_u64)], C.c_int),
+    "mdr_decompose": ([C.c_int, _vp, _u64, _u64, _u64, _u32, _vp, _vp], C.c_int),
+    "mdr_recompose": ([C.c_int, _vp, _u64, _u64, _u64, _u32, _vp, _vp], C.c_int),
     "mdr_ablation_plane_words": ([C.c_int32, _u64], _u64),
     "mdr_ablation_encode": ([C.c_int32, _vp, _u64, _vp, _vp], C.c_int),
     "mdr_ablation_decode": ([C.c_int32, _vp, _u64, _vp, _vp], C.c_int),
@@ -456,6 +459,41 @@ def ablation_decode(design: str, planes, out, stream=None) -> None:
     """mdr_ablation_decode: planes (device) -> out (n uint32-sized elements, device)."""
     _check(_lib.mdr_ablation_decode(ABLATION_DESIGNS[design], C.c_void_p(planes.data_ptr()), out.numel(),
                                     C.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+
+
+# ---------------------------------------------------------------- multilevel decomposition
+def level_sizes(shape, nsteps: int):
+    """mdr_level_sizes: values per level (coarsest first) of an n0 x n1 x n2 grid."""
+    out = (_u64 * (int(nsteps) + 1))()
+    _check(_lib.mdr_level_sizes(int(shape[0]), int(shape[1]), int(shape[2]), int(nsteps), out))
+    return [int(v) for v in out]
+
+
+def _ml_dtype(t) -> int:
+    if t.dtype == torch.float32:
+        return MDR_F32
+    if t.dtype == torch.float64:
+        return MDR_F64
+    raise TypeError("multilevel decomposition takes float32 or float64 tensors")
+
+
+def decompose(field, nsteps: int, coeffs, stream=None) -> None:
+    """mdr_decompose: field (contiguous n0 x n1 x n2 device tensor) -> coeffs
+    (its levels concatenated, coarsest first)."""
+    if field.dim() != 3 or not field.is_contiguous() or coeffs.dtype != field.dtype or coeffs.numel() != field.numel():
+        raise ValueError("decompose: contiguous 3-D field and a coefficient buffer of the same size and dtype")
+    n0, n1, n2 = field.shape
+    _check(_lib.mdr_decompose(_ml_dtype(field), C.c_void_p(field.data_ptr()), n0, n1, n2, int(nsteps),
+                              C.c_void_p(coeffs.data_ptr()), _stream_ptr(stream)))
+
+
+def recompose(coeffs, nsteps: int, field, stream=None) -> None:
+    """mdr_recompose: concatenated levels -> field (contiguous n0 x n1 x n2 device tensor)."""
+    if field.dim() != 3 or not field.is_contiguous() or coeffs.dtype != field.dtype or coeffs.numel() != field.numel():
+        raise ValueError("recompose: contiguous 3-D field and a coefficient buffer of the same size and dtype")
+    n0, n1, n2 = field.shape
+    _check(_lib.mdr_recompose(_ml_dtype(field), C.c_void_p(coeffs.data_ptr()), n0, n1, n2, int(nsteps),
+                              C.c_void_p(field.data_ptr()), _stream_ptr(stream)))
 
 
 class Server:

@@ -755,3 +755,80 @@ mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t 
 }
 
 }  // extern "C"
+
+// ---- multilevel decomposition ----------------------------------------------
+
+static mdr_status ml_check(uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps, mdr::MlOffsets* off,
+                           uint64_t* total)
+{
+    if (nsteps > mdr::kMlMaxSteps) return fail(MDR_ERR_INVALID_ARG, "nsteps must be at most 30");
+    if (n0 > 65535 || n1 > 65535 || n2 > 0x7fffffffull)
+        return fail(MDR_ERR_UNSUPPORTED, "grid too large: n0 and n1 must be below 65536, n2 below 2^31");
+    uint64_t sizes[mdr::kMlMaxSteps + 1];
+    mdr_level_sizes(n0, n1, n2, nsteps, sizes);
+    uint64_t acc = 0;
+    for (uint32_t l = 0; l <= nsteps; ++l) {
+        if (off) off->off[l] = acc;
+        acc += sizes[l];
+    }
+    *total = acc;
+    return MDR_OK;
+}
+
+static bool ranges_overlap(const void* a, const void* b, uint64_t bytes)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+static mdr_status ml_run(bool decompose, mdr_dtype dtype, const void* in, uint64_t n0, uint64_t n1, uint64_t n2,
+                         uint32_t nsteps, void* out, void* stream)
+{
+    g_err.clear();
+    if (dtype != MDR_F32 && dtype != MDR_F64) return fail(MDR_ERR_INVALID_ARG, "dtype must be MDR_F32 or MDR_F64");
+    mdr::MlOffsets off{};
+    uint64_t total = 0;
+    if (mdr_status st = ml_check(n0, n1, n2, nsteps, &off, &total)) return st;
+    if (total == 0) return MDR_OK;
+    const uint64_t w = dtype == MDR_F64 ? 8 : 4;
+    if (!in || !out) return fail(MDR_ERR_INVALID_ARG, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(in) % w || reinterpret_cast<uintptr_t>(out) % w)
+        return fail(MDR_ERR_INVALID_ARG, "buffers must be aligned to the value size");
+    if (ranges_overlap(in, out, total * w)) return fail(MDR_ERR_INVALID_ARG, "input and output overlap");
+    (void)hipGetLastError();
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (decompose)
+        MDR_HIP(mdr::launch_decompose(dtype == MDR_F64, in, (uint32_t)n0, (uint32_t)n1, (uint32_t)n2, nsteps, off, out, s));
+    else
+        MDR_HIP(mdr::launch_recompose(dtype == MDR_F64, in, (uint32_t)n0, (uint32_t)n1, (uint32_t)n2, nsteps, off, out, s));
+    return MDR_OK;
+}
+
+extern "C" {
+
+mdr_status mdr_level_sizes(uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps, uint64_t* sizes)
+{
+    if (!sizes) return fail(MDR_ERR_INVALID_ARG, "sizes is NULL");
+    if (nsteps > mdr::kMlMaxSteps) return fail(MDR_ERR_INVALID_ARG, "nsteps must be at most 30");
+    auto count = [&](uint32_t j) -> uint64_t {
+        auto m = [&](uint64_t n) { return n == 0 ? 0 : ((n - 1) >> j) + 1; };
+        return m(n0) * m(n1) * m(n2);
+    };
+    sizes[0] = count(nsteps);
+    for (uint32_t l = 1; l <= nsteps; ++l) sizes[l] = count(nsteps - l) - count(nsteps - l + 1);
+    return MDR_OK;
+}
+
+mdr_status mdr_decompose(mdr_dtype dtype, const void* field, uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps,
+                         void* coeffs, void* stream)
+{
+    return ml_run(true, dtype, field, n0, n1, n2, nsteps, coeffs, stream);
+}
+
+mdr_status mdr_recompose(mdr_dtype dtype, const void* coeffs, uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps,
+                         void* field, void* stream)
+{
+    return ml_run(false, dtype, coeffs, n0, n1, n2, nsteps, field, stream);
+}
+
+}  // extern "C"

@@ -205,6 +205,17 @@ struct CopySpans {
 };
 hipError_t launch_copy_out(const CopySpans& sp, hipStream_t s);
 
+// ---- multilevel decomposition (k_multilevel.hip): field <-> coefficient levels
+constexpr uint32_t kMlMaxSteps = 30;
+struct MlOffsets {
+    uint64_t off[kMlMaxSteps + 1];  // first value of each level, coarsest first
+};
+// n0, n1 < 65536 (grid y/z); n2 < 2^31; `out` / `u` must not overlap the input
+hipError_t launch_decompose(bool f64, const void* u, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t nsteps,
+                            const MlOffsets& off, void* out, hipStream_t s);
+hipError_t launch_recompose(bool f64, const void* c, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t nsteps,
+                            const MlOffsets& off, void* u, hipStream_t s);
+
 // ---- encoder-design ablation (k_ablation.hip): 32-bit words <-> 32 planes
 constexpr int kAblLocality = 0, kAblBallot = 1, kAblShift = 2, kAblButterfly = 3, kAblRegBlock = 4;
 uint64_t ablation_plane_words(int design, uint64_t n);

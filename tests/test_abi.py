@@ -83,3 +83,26 @@ def test_qoi_estimator_validation_without_gpu():
     st = mdr.mdr_retrieve_qoi_vtotal_with(None, None, None, mdr.MDR_ABS, 1.0, C.byref(prm), None, None, None,
                                           None, C.byref(info))
     assert st == mdr.MDR_ERR_INVALID_ARG and b"cp_decay" in mdr.mdr_last_error()
+
+
+def test_multilevel_host_side_without_gpu():
+    import paper_2505_00227_amd as mdr
+    from oracle import multilevel as ml
+    for shape, nsteps in [((512, 512, 512), 8), ((7, 10, 13), 3), ((1, 1, 6), 2), ((0, 4, 4), 1),
+                          ((3, 3, 3), 30), ((32, 1024, 1024), 8)]:
+        assert mdr.level_sizes(shape, nsteps) == ml.level_sizes(shape, nsteps), (shape, nsteps)
+    sizes = (C.c_uint64 * 32)()
+    assert mdr.mdr_level_sizes(4, 4, 4, 31, sizes) == mdr.MDR_ERR_INVALID_ARG
+    assert mdr.mdr_level_sizes(4, 4, 4, 2, None) == mdr.MDR_ERR_INVALID_ARG
+    fake, other = C.c_void_p(1 << 20), C.c_void_p(1 << 30)
+    for fn in (mdr.mdr_decompose, mdr.mdr_recompose):
+        assert fn(mdr.MDR_F32, fake, 4, 4, 4, 31, other, None) == mdr.MDR_ERR_INVALID_ARG
+        assert fn(mdr.MDR_F32, fake, 70000, 4, 4, 2, other, None) == mdr.MDR_ERR_UNSUPPORTED
+        assert fn(mdr.MDR_F32, fake, 4, 70000, 4, 2, other, None) == mdr.MDR_ERR_UNSUPPORTED
+        assert fn(7, fake, 4, 4, 4, 2, other, None) == mdr.MDR_ERR_INVALID_ARG
+        assert fn(mdr.MDR_F32, None, 4, 4, 4, 2, other, None) == mdr.MDR_ERR_INVALID_ARG
+        assert fn(mdr.MDR_F64, C.c_void_p((1 << 20) + 4), 4, 4, 4, 2, other, None) == mdr.MDR_ERR_INVALID_ARG
+        # 64 values of 4 bytes from 1 MiB overlap a buffer starting 128 bytes later
+        assert fn(mdr.MDR_F32, fake, 4, 4, 4, 2, C.c_void_p((1 << 20) + 128), None) == mdr.MDR_ERR_INVALID_ARG
+        assert b"overlap" in mdr.mdr_last_error()
+        assert fn(mdr.MDR_F32, None, 0, 4, 4, 2, None, None) == mdr.MDR_OK  # empty grid: no-op

@@ -1,0 +1,119 @@
+"""Multilevel decomposition on the GPU (the coefficient levels of Sec. 2/3):
+decomposition and recomposition match the oracle bit for bit in float32 and
+float64, on grids with ragged workgroups, non-dyadic edges, empty levels and
+the 512^3 field at full size; and a field taken through decompose -> refactor
+-> retrieve -> recompose lands within the requested max error."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import say
+from oracle import multilevel as ml
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((33, 17, 70), 3), ((1, 1, 1000), 5), ((65, 129, 257), 6), ((20, 31, 300), 4), ((3, 3, 3), 6),
+         ((9, 8, 7), 0), ((2, 600, 5), 7), ((1, 1, 1), 2), ((40, 1, 513), 9)]
+
+
+@pytest.fixture(scope="module")
+def mdr():
+    import paper_2505_00227_amd as m
+    return m
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view(np.uint32 if a.dtype == np.float32 else np.uint64)
+
+
+def _decompose_gpu(mdr, u, nsteps):
+    import torch
+    f = torch.from_numpy(u).cuda()
+    out = torch.full((u.size,), float("nan"), dtype=f.dtype, device="cuda")  # every value must be written
+    mdr.decompose(f, nsteps, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _recompose_gpu(mdr, coeffs, shape, nsteps):
+    import torch
+    c = torch.from_numpy(np.ascontiguousarray(coeffs)).cuda()
+    out = torch.full(tuple(shape), float("nan"), dtype=c.dtype, device="cuda")
+    mdr.recompose(c, nsteps, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,nsteps", CASES)
+def test_decompose_and_recompose_match_oracle(mdr, dtype, shape, nsteps):
+    say("multilevel", np.dtype(dtype).name, shape, "nsteps", nsteps)
+    u = workloads.smooth_field(11, shape, dtype)
+    assert mdr.level_sizes(shape, nsteps) == ml.level_sizes(shape, nsteps)
+    want = ml.concat(ml.decompose(u, nsteps))
+    got = _decompose_gpu(mdr, u, nsteps)
+    np.testing.assert_array_equal(_bits(got), _bits(want))
+    # recomposition of arbitrary coefficients (not only a decomposition's)
+    rng = np.random.default_rng(12)
+    c = (want + rng.standard_normal(want.size) * 1e-3).astype(dtype)
+    sizes = ml.level_sizes(shape, nsteps)
+    ref = ml.recompose(np.split(c, np.cumsum(sizes)[:-1]), shape, nsteps)
+    np.testing.assert_array_equal(_bits(_recompose_gpu(mdr, c, shape, nsteps)), _bits(ref))
+
+
+def test_special_values_pass_through(mdr):
+    shape, nsteps = (17, 9, 33), 3
+    u = workloads.smooth_field(13, shape, np.float32)
+    u[3, 4, 5] = np.inf
+    u[8, 2, 31] = np.nan
+    u[0, 0, 1] = -0.0
+    u[16, 8, 32] = np.float32(1e-40)  # subnormal: not flushed
+    want = ml.concat(ml.decompose(u, nsteps))
+    np.testing.assert_array_equal(_bits(_decompose_gpu(mdr, u, nsteps)), _bits(want))
+
+
+def test_full_size_field(mdr):
+    shape, nsteps = (512, 512, 512), 8
+    say("multilevel full size", shape)
+    u = workloads.smooth_field(2, shape, np.float32)
+    want = ml.decompose(u, nsteps)
+    got = _decompose_gpu(mdr, u, nsteps)
+    np.testing.assert_array_equal(_bits(got), _bits(ml.concat(want)))
+    back = _recompose_gpu(mdr, got, shape, nsteps)
+    np.testing.assert_array_equal(_bits(back), _bits(ml.recompose(want, shape, nsteps)))
+
+
+@pytest.mark.parametrize("dtype,rel", [(np.float32, 1e-2), (np.float32, 1e-4), (np.float64, 1e-7)])
+def test_field_through_the_path_meets_tolerance(mdr, orc, dtype, rel):
+    import torch
+    shape, nsteps, B = (65, 97, 129), 5, 32 if dtype == np.float32 else 64
+    say("multilevel path", np.dtype(dtype).name, "rel", rel)
+    u = workloads.smooth_field(14, shape, dtype)
+    tol = rel * float(u.max() - u.min())
+    sizes = ml.level_sizes(shape, nsteps)
+    ctx = mdr.Context(0)
+    coeffs = torch.empty(u.size, dtype=torch.float32 if dtype == np.float32 else torch.float64, device="cuda")
+    mdr.decompose(torch.from_numpy(u).cuda(), nsteps, coeffs)
+    levels = list(torch.split(coeffs, sizes))
+    r = mdr.refactor(ctx, levels, B)
+    rt = mdr.Retriever(ctx, r)
+    outs = [torch.empty_like(x) for x in levels]
+    info = rt.retrieve(tol, outs, relative=False)
+    assert info["bound"] <= tol
+    field = torch.empty(shape, dtype=coeffs.dtype, device="cuda")
+    mdr.recompose(torch.cat(outs), nsteps, field)
+    got = field.cpu().numpy()
+    # the oracle's chain gives the same field bit for bit
+    olv = orc.refactor(ml.decompose(u, nsteps), B)
+    rec, k, bound, ok = orc.retrieve_to(olv, tol, relative=False)
+    assert ok and list(k) == list(rt.planes())
+    want = ml.recompose(rec, shape, nsteps)
+    np.testing.assert_array_equal(_bits(got), _bits(want))
+    # field max error: the levels' bound plus recomposition rounding
+    slack = 4 * nsteps * np.finfo(dtype).eps * float(np.abs(u).max())
+    assert np.abs(got.astype(np.float64) - u).max() <= tol + slack
+    rt.close()
+    r.close()
+    ctx.close()

@@ -7,8 +7,9 @@ workloads, so that the oracle and the GPU path can be fed the same buffers.
 The paper's datasets (NYX, LETKF, Miranda, Hurricane ISABEL, JHTDB; Sec. 6.1,
 Table 1) are not available; these generators stand in for them:
 
-* the multilevel decomposition is not part of the path, so a "field" is
-  represented by its coefficient levels directly: level sizes follow the 3D
+* for the refactor/retrieve workloads a "field" is represented by its
+  coefficient levels directly (smooth_field materialises the field itself for
+  the multilevel decomposition): level sizes follow the 3D
   dyadic coarsening rule (each finer level holds the points added by halving
   the grid spacing, i.e. 7/8 of the remaining points for power-of-two edges);
 * coefficients of level l (l = 0 coarsest) are Laplace(0, b0 * 2^-l), drawn in
@@ -55,6 +56,33 @@ def smooth_field_std(seed: int, n_modes: int = 16, noise: float = 0.01) -> float
         amp[k] = amp.get(k, 0j) + a * complex(math.cos(ph), math.sin(ph))
     var = sum(abs(v) ** 2 / 2.0 for v in amp.values())
     return math.sqrt(var * (1.0 + noise * noise))
+
+
+def smooth_field(seed: int, shape, dtype=np.float32, n_modes: int = 16, noise: float = 0.01) -> np.ndarray:
+    """The smooth field itself, for the multilevel decomposition: the 16
+    random-phase sinusoids of smooth_field_std (the same draws, phases along
+    each axis scaled by that axis' length) plus Gaussian noise of 1% of the
+    signal's standard deviation; evaluated in float64, then rounded to dtype."""
+    return smooth_field_tensor(seed, shape, "cpu", n_modes, noise).numpy().astype(dtype)
+
+
+def smooth_field_tensor(seed: int, shape, device, n_modes: int = 16, noise: float = 0.01):
+    """smooth_field as a float64 torch tensor evaluated on `device` (the sines
+    may differ in the last bits between devices)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(1, 9, size=(n_modes, 3))
+    phases = rng.uniform(0.0, 2.0 * math.pi, n_modes)
+    axes = [torch.arange(n, dtype=torch.float64, device=device) * (2.0 * math.pi / max(n, 1)) for n in shape]
+    u = torch.zeros(tuple(shape), dtype=torch.float64, device=device)
+    for k, ph in zip(ks, phases):
+        a = 1.0 / math.sqrt(sum(int(c) * int(c) for c in k))
+        ang = (axes[0] * int(k[0]))[:, None, None] + (axes[1] * int(k[1]))[None, :, None] \
+            + (axes[2] * int(k[2]) + float(ph))[None, None, :]
+        u += a * torch.sin(ang)
+    sd = smooth_field_std(seed, n_modes, 0.0)
+    u += torch.from_numpy(rng.standard_normal(tuple(shape))).to(device) * (noise * sd)
+    return u
 
 
 def laplace_levels(sizes, b0: float, rng: np.random.Generator, dtype=np.float32):
