@@ -7,7 +7,9 @@ library (``paper_2505_00227_amd``) never imports it, and the two share no code.
 The arithmetic lives in ``mdr_oracle.c`` (plain C, one value / one bit at a
 time); this module only marshals numpy arrays through ctypes.  The QoI loop of
 Sec. 5.2 (Alg. 3 with the MAPE estimator) is written here in Python on top of
-the C planner and bound, because it is control flow, not arithmetic.
+the C planner and bound, because it is control flow, not arithmetic.  The
+multilevel decomposition that produces the levels from a field is in
+``multilevel.py`` (numpy, in the field's own dtype).
 """
 from __future__ import annotations
 

@@ -12,9 +12,12 @@
 // field's type, one rounding per operation (no contraction), so coefficients
 // are reproducible bit for bit.
 //
-// Decomposition reads only the input field (no node's coefficient depends on
-// another's), so one launch covers every level; recomposition needs the
-// coarser grid first and runs one launch per step.
+// One launch per level.  A decomposition step reads only the input field, so
+// its launches are independent; a recomposition step reads the nodes of every
+// coarser step, so they run coarsest first.  Within a step a workgroup covers
+// part of one row of the step's grid and a lane an (even, odd) pair of its
+// nodes: the row's parity, coarse rows and output offset are uniform, and
+// consecutive lanes touch consecutive nodes.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -44,83 +47,261 @@ __device__ __forceinline__ uint64_t new_rank(uint64_t a, uint64_t b, uint64_t c,
     return (a * m1 + b) * m2 + c - skipped;
 }
 
-struct Axis {
-    uint32_t lo, hi;
-    bool two;  // mean of lo and hi; otherwise the value at lo
+// The coarse rows a stride-h row (a, b) interpolates from: rows a -/+ 1 when a
+// is odd (one of them past the end of the grid), row a itself when it is even;
+// the same along y.  Uniform across a workgroup, which covers part of one row.
+template <typename T>
+struct CoarseRows {
+    const T* r[2][2];  // [z side][y side]
+    bool z2, y2;       // mean of both sides, else side 0 alone
 };
 
-__device__ __forceinline__ Axis axis_at(uint32_t i, uint32_t j, uint32_t n)
+template <typename T>
+__device__ __forceinline__ CoarseRows<T> coarse_rows(const T* u, uint32_t n1, uint32_t n2, uint64_t a, uint64_t b,
+                                                     uint64_t m0, uint64_t m1, uint32_t j)
 {
-    const uint32_t h = 1u << j;
-    if (!((i >> j) & 1u)) return {i, i, false};
-    const bool two = i + h < n;
-    return {i - h, two ? i + h : i - h, two};
+    CoarseRows<T> cr;
+    const uint64_t z0 = (a & 1) ? a - 1 : a, y0 = (b & 1) ? b - 1 : b;
+    cr.z2 = (a & 1) && a + 1 < m0;
+    cr.y2 = (b & 1) && b + 1 < m1;
+    const uint64_t z1 = cr.z2 ? a + 1 : z0, y1 = cr.y2 ? b + 1 : y0;
+    auto row = [&](uint64_t zz, uint64_t yy) { return u + ((zz << j) * n1 + (yy << j)) * n2; };
+    cr.r[0][0] = row(z0, y0);
+    cr.r[0][1] = row(z0, y1);
+    cr.r[1][0] = row(z1, y0);
+    cr.r[1][1] = row(z1, y1);
+    return cr;
 }
 
-// P at node (i0, i1, i2) of step j from the stride-2h values of u
+// P at the pair of stride-h nodes (2t, 2t + 1) of a row: pe for the even node
+// (no refinement along x), po for the odd one (mean of coarse nodes 2t and
+// 2t + 2, or node 2t alone past the end of the line); then y, then z
 template <typename T>
-__device__ __forceinline__ T predict(const T* __restrict__ u, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t i0,
-                                     uint32_t i1, uint32_t i2, uint32_t j)
+__device__ __forceinline__ void predict_pair(const CoarseRows<T>& cr, uint64_t xe, uint64_t xn, bool x2, T& pe, T& po)
 {
 #pragma clang fp contract(off)
-    const Axis z = axis_at(i0, j, n0), y = axis_at(i1, j, n1), x = axis_at(i2, j, n2);
     const T half = T(0.5);
-    auto along_x = [&](uint32_t zz, uint32_t yy) -> T {
-        const T* r = u + ((uint64_t)zz * n1 + yy) * n2;
-        return x.two ? (r[x.lo] + r[x.hi]) * half : r[x.lo];
-    };
-    auto along_y = [&](uint32_t zz) -> T {
-        return y.two ? (along_x(zz, y.lo) + along_x(zz, y.hi)) * half : along_x(zz, y.lo);
-    };
-    return z.two ? (along_y(z.lo) + along_y(z.hi)) * half : along_y(z.lo);
+    T e[2][2], o[2][2];
+#pragma unroll
+    for (int zi = 0; zi < 2; ++zi)
+#pragma unroll
+        for (int yi = 0; yi < 2; ++yi) {
+            const T* r = cr.r[zi][yi];
+            const T v = r[xe];
+            e[zi][yi] = v;
+            o[zi][yi] = x2 ? (v + r[xn]) * half : v;
+        }
+    T ey[2], oy[2];
+#pragma unroll
+    for (int zi = 0; zi < 2; ++zi) {
+        ey[zi] = cr.y2 ? (e[zi][0] + e[zi][1]) * half : e[zi][0];
+        oy[zi] = cr.y2 ? (o[zi][0] + o[zi][1]) * half : o[zi][0];
+    }
+    pe = cr.z2 ? (ey[0] + ey[1]) * half : ey[0];
+    po = cr.z2 ? (oy[0] + oy[1]) * half : oy[0];
 }
 
-template <typename T>
-__global__ __launch_bounds__(kMl) void k_decompose(const T* __restrict__ u, uint32_t n0, uint32_t n1, uint32_t n2,
-                                                   uint32_t nsteps, MlOffsets off, T* __restrict__ out)
+// Step j of the decomposition (DEC: field -> level) or of the recomposition
+// (field of the coarser steps + level -> field).  Grid: (pairs / kMl, m1, m0)
+// over the stride-h grid; a lane takes the nodes 2t and 2t + 1 of its row.
+// In a row with a or b odd every node is new and the row's coefficients are
+// contiguous from new_rank(a, b, 0); in a row with both even only odd x is new.
+template <typename T, bool DEC>
+__device__ __forceinline__ void ml_step_row(const T* __restrict__ in, T* out, const T* field, uint32_t n1,
+                                            uint32_t n2, uint32_t j, uint64_t m0, uint64_t a)
 {
 #pragma clang fp contract(off)
-    const uint32_t i2 = blockIdx.x * kMl + threadIdx.x;
-    if (i2 >= n2) return;
-    const uint32_t i1 = blockIdx.y, i0 = blockIdx.z;
-    const uint32_t j = (uint32_t)__builtin_ctz(i0 | i1 | i2 | (1u << nsteps));
-    const T v = u[((uint64_t)i0 * n1 + i1) * n2 + i2];
-    if (j == nsteps) {
-        const uint64_t r = ((uint64_t)(i0 >> j) * axis_nodes(n1, j) + (i1 >> j)) * axis_nodes(n2, j) + (i2 >> j);
-        out[off.off[0] + r] = v;
-        return;
+    const uint64_t m1 = axis_nodes(n1, j), m2 = axis_nodes(n2, j);
+    const uint64_t t = (uint64_t)blockIdx.x * kMl + threadIdx.x;
+    if (2 * t >= m2) return;
+    const uint64_t b = blockIdx.y;
+    const bool coarse_row = !((a | b) & 1);
+    const uint64_t base = new_rank(a, b, 0, m1, m2);
+    const CoarseRows<T> cr = coarse_rows(field, n1, n2, a, b, m0, m1, j);
+    const bool has_odd = 2 * t + 1 < m2;
+    const uint64_t xe = (2 * t) << j, xo = (2 * t + 1) << j, xn = (2 * t + 2) << j;
+    T pe, po;
+    predict_pair(cr, xe, xn, 2 * t + 2 < m2, pe, po);
+    const uint64_t self = ((a << j) * n1 + (b << j)) * n2;
+    if (DEC) {
+        const T* u = in + self;
+        if (coarse_row) {
+            if (has_odd) out[base + t] = u[xo] - po;
+        } else {
+            out[base + 2 * t] = u[xe] - pe;
+            if (has_odd) out[base + 2 * t + 1] = u[xo] - po;
+        }
+    } else {
+        T* u = out + self;
+        if (coarse_row) {
+            if (has_odd) u[xo] = in[base + t] + po;
+        } else {
+            u[xe] = in[base + 2 * t] + pe;
+            if (has_odd) u[xo] = in[base + 2 * t + 1] + po;
+        }
     }
-    const uint64_t r = new_rank(i0 >> j, i1 >> j, i2 >> j, axis_nodes(n1, j), axis_nodes(n2, j));
-    out[off.off[nsteps - j] + r] = v - predict(u, n0, n1, n2, i0, i1, i2, j);
 }
 
-// coarsest grid: raw values back in place (grid: x blocks, m1, m0 of stride 2^nsteps)
-template <typename T>
-__global__ __launch_bounds__(kMl) void k_recompose_coarse(const T* __restrict__ c, uint32_t n1, uint32_t n2,
-                                                          uint32_t nsteps, T* __restrict__ u)
+// 16-byte row accesses of 4 consecutive values
+__device__ __forceinline__ void load4(const float* p, float o[4])
+{
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x, o[1] = v.y, o[2] = v.z, o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double o[4])
+{
+    const double2 v0 = reinterpret_cast<const double2*>(p)[0], v1 = reinterpret_cast<const double2*>(p)[1];
+    o[0] = v0.x, o[1] = v0.y, o[2] = v1.x, o[3] = v1.y;
+}
+__device__ __forceinline__ void store4(float* p, const float o[4])
+{
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+}
+__device__ __forceinline__ void store4(double* p, const double o[4])
+{
+    reinterpret_cast<double2*>(p)[0] = make_double2(o[0], o[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(o[2], o[3]);
+}
+
+constexpr uint32_t kFineX = 64, kFineRows = 4;  // workgroup: a wavefront per row, 4 rows
+
+// order LDS traffic between the lanes of one wavefront
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The finest step (j = 0) when rows are whole 16-byte vectors (n2 % 4 == 0,
+// 16-byte aligned field): a lane takes nodes 4t .. 4t + 3 of its row with one
+// vector access per row it reads, the same arithmetic as k_ml_step.  The
+// level side (any alignment) goes through LDS so that its loads and stores are
+// lane-contiguous: the wavefront's coefficients are one contiguous run (256
+// of them, or 128 in a row with both indices even, fewer at a row's end).
+// Grid: (n2 / 4 / kFineX, n1 / kFineRows, n0), block (kFineX, kFineRows); a
+// wavefront covers 256 nodes of one row.
+template <typename T, bool DEC>
+__device__ __forceinline__ void ml_fine_row(const T* __restrict__ in, T* out, const T* field, uint32_t n0,
+                                            uint32_t n1, uint32_t n2, uint64_t a, T* w)
+{
+#pragma clang fp contract(off)
+    const uint32_t lane = threadIdx.x;
+    const uint64_t q = n2 / 4;
+    const uint64_t t = (uint64_t)blockIdx.x * kFineX + lane;
+    const uint64_t b = (uint64_t)blockIdx.y * kFineRows + threadIdx.y;
+    if (b >= n1) return;  // whole wavefront
+    const bool live = t < q;
+    const bool coarse_row = !((a | b) & 1);
+    const uint64_t wnodes = 4 * (q - (uint64_t)blockIdx.x * kFineX < kFineX ? q - (uint64_t)blockIdx.x * kFineX
+                                                                              : kFineX);
+    const uint64_t wcoef = coarse_row ? wnodes / 2 : wnodes;  // this wavefront's run of coefficients
+    const uint64_t wbase = new_rank(a, b, 0, n1, n2) + (coarse_row ? 2 : 4) * (uint64_t)blockIdx.x * kFineX;
+    const uint64_t x = 4 * t;
+    const uint64_t self = (a * n1 + b) * n2 + x;
+    T c[4];  // recomposition: this lane's coefficients (nodes x .. x + 3; odd ones in a coarse row)
+    if (!DEC) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t i = lane + (uint64_t)k * kFineX;
+            if (i < wcoef) w[i] = in[wbase + i];
+        }
+        wave_sync();
+        if (coarse_row) {
+            c[1] = w[2 * lane];
+            c[3] = w[2 * lane + 1];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = w[4 * lane + k];
+        }
+    }
+    T P[4];
+    if (live) {
+        const CoarseRows<T> cr = coarse_rows(field, n1, n2, a, b, n0, n1, 0);
+        const bool x2 = x + 4 < n2;  // node x + 3 has a coarse node on its right
+        const T half = T(0.5);
+        T p[2][2][4];  // per coarse row: P along x of nodes x .. x + 3 (odd ones refined)
+#pragma unroll
+        for (int zi = 0; zi < 2; ++zi)
+#pragma unroll
+            for (int yi = 0; yi < 2; ++yi) {
+                const T* r = cr.r[zi][yi];
+                T v[4];
+                load4(r + x, v);
+                const T nx = x2 ? r[x + 4] : v[2];
+                p[zi][yi][0] = v[0];
+                p[zi][yi][1] = (v[0] + v[2]) * half;
+                p[zi][yi][2] = v[2];
+                p[zi][yi][3] = x2 ? (v[2] + nx) * half : v[2];
+            }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const T y0 = cr.y2 ? (p[0][0][k] + p[0][1][k]) * half : p[0][0][k];
+            const T y1 = cr.y2 ? (p[1][0][k] + p[1][1][k]) * half : p[1][0][k];
+            P[k] = cr.z2 ? (y0 + y1) * half : y0;
+        }
+    }
+    if (DEC) {
+        if (live) {
+            T u[4];
+            load4(in + self, u);
+            if (coarse_row) {
+                w[2 * lane] = u[1] - P[1];
+                w[2 * lane + 1] = u[3] - P[3];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) w[4 * lane + k] = u[k] - P[k];
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t i = lane + (uint64_t)k * kFineX;
+            if (i < wcoef) out[wbase + i] = w[i];
+        }
+    } else if (live) {
+        if (coarse_row) {
+            out[self + 1] = c[1] + P[1];
+            out[self + 3] = c[3] + P[3];
+        } else {
+            T u[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[k] = c[k] + P[k];
+            store4(out + self, u);
+        }
+    }
+}
+
+template <typename T, bool DEC>
+__global__ __launch_bounds__(kMl) void k_ml_step(const T* __restrict__ in, T* out, const T* field,
+                                                 uint32_t n1, uint32_t n2, uint32_t j, uint64_t m0)
+{
+    ml_step_row<T, DEC>(in, out, field, n1, n2, j, m0, blockIdx.z);
+}
+
+template <typename T, bool DEC>
+__global__ __launch_bounds__(kFineX* kFineRows) void k_ml_fine(const T* __restrict__ in, T* out, const T* field,
+                                                               uint32_t n0, uint32_t n1, uint32_t n2)
+{
+    __shared__ T xch[kFineRows][4 * kFineX];
+    ml_fine_row<T, DEC>(in, out, field, n0, n1, n2, blockIdx.z, xch[threadIdx.y]);
+}
+
+// coarsest grid (stride 2^nsteps): DEC copies field -> level 0, else back
+template <typename T, bool DEC>
+__global__ __launch_bounds__(kMl) void k_ml_coarse(const T* __restrict__ in, T* __restrict__ out, uint32_t n1,
+                                                   uint32_t n2, uint32_t nsteps)
 {
     const uint64_t m2 = axis_nodes(n2, nsteps), m1 = axis_nodes(n1, nsteps);
-    const uint32_t b2 = blockIdx.x * kMl + threadIdx.x;
+    const uint64_t b2 = (uint64_t)blockIdx.x * kMl + threadIdx.x;
     if (b2 >= m2) return;
-    const uint32_t b1 = blockIdx.y, b0 = blockIdx.z;
-    const uint64_t idx = ((uint64_t)(b0 << nsteps) * n1 + (b1 << nsteps)) * n2 + (b2 << nsteps);
-    u[idx] = c[((uint64_t)b0 * m1 + b1) * m2 + b2];
-}
-
-// step j: every stride-h node off the stride-2h grid gets c + P
-template <typename T>
-__global__ __launch_bounds__(kMl) void k_recompose_step(const T* __restrict__ c, uint32_t n0, uint32_t n1, uint32_t n2,
-                                                        uint32_t j, T* __restrict__ u)
-{
-#pragma clang fp contract(off)
-    const uint64_t m2 = axis_nodes(n2, j), m1 = axis_nodes(n1, j);
-    const uint32_t b2 = blockIdx.x * kMl + threadIdx.x;
-    if (b2 >= m2) return;
-    const uint32_t b1 = blockIdx.y, b0 = blockIdx.z;
-    if (!((b0 | b1 | b2) & 1u)) return;  // on the coarser grid: already in place
-    const uint32_t i0 = b0 << j, i1 = b1 << j, i2 = b2 << j;
-    const T p = predict(u, n0, n1, n2, i0, i1, i2, j);
-    u[((uint64_t)i0 * n1 + i1) * n2 + i2] = c[new_rank(b0, b1, b2, m1, m2)] + p;
+    const uint64_t b1 = blockIdx.y, b0 = blockIdx.z;
+    const uint64_t f = ((b0 << nsteps) * n1 + (b1 << nsteps)) * n2 + (b2 << nsteps);
+    const uint64_t c = (b0 * m1 + b1) * m2 + b2;
+    if (DEC)
+        out[c] = in[f];
+    else
+        out[f] = in[c];
 }
 
 dim3 line_grid(uint64_t m0, uint64_t m1, uint64_t m2)
@@ -129,25 +310,40 @@ dim3 line_grid(uint64_t m0, uint64_t m1, uint64_t m2)
 }
 
 template <typename T>
-hipError_t decompose_t(const T* u, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t nsteps, const MlOffsets& off,
-                       T* out, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_decompose<T>, line_grid(n0, n1, n2), dim3(kMl), 0, s, u, n0, n1, n2, nsteps, off, out);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t recompose_t(const T* c, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t nsteps, const MlOffsets& off,
-                       T* u, hipStream_t s)
+hipError_t ml_run(bool dec, const T* in, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t nsteps,
+                  const MlOffsets& off, T* out, hipStream_t s)
 {
     auto m = [&](uint32_t n, uint32_t j) { return n == 0 ? 0ull : (uint64_t)((n - 1) >> j) + 1; };
-    hipLaunchKernelGGL(k_recompose_coarse<T>, line_grid(m(n0, nsteps), m(n1, nsteps), m(n2, nsteps)), dim3(kMl), 0,
-                       s, c + off.off[0], n1, n2, nsteps, u);
+    const dim3 gc = line_grid(m(n0, nsteps), m(n1, nsteps), m(n2, nsteps));
+    if (dec)
+        hipLaunchKernelGGL((k_ml_coarse<T, true>), gc, dim3(kMl), 0, s, in, out + off.off[0], n1, n2, nsteps);
+    else
+        hipLaunchKernelGGL((k_ml_coarse<T, false>), gc, dim3(kMl), 0, s, in + off.off[0], out, n1, n2, nsteps);
     hipError_t e = hipGetLastError();
+    // decomposition steps are independent (each reads only the field); the
+    // recomposition needs every coarser step first
+    const T* field = dec ? in : out;
+    const bool fine_vec = n2 % 4 == 0 && reinterpret_cast<uintptr_t>(field) % 16 == 0;
     for (uint32_t l = 1; l <= nsteps && e == hipSuccess; ++l) {
         const uint32_t j = nsteps - l;
-        hipLaunchKernelGGL(k_recompose_step<T>, line_grid(m(n0, j), m(n1, j), m(n2, j)), dim3(kMl), 0, s,
-                           c + off.off[l], n0, n1, n2, j, u);
+        if (j == 0 && fine_vec) {
+            const dim3 g((uint32_t)((n2 / 4 + kFineX - 1) / kFineX), (n1 + kFineRows - 1) / kFineRows, n0);
+            if (dec)
+                hipLaunchKernelGGL((k_ml_fine<T, true>), g, dim3(kFineX, kFineRows), 0, s, in, out + off.off[l], in,
+                                   n0, n1, n2);
+            else
+                hipLaunchKernelGGL((k_ml_fine<T, false>), g, dim3(kFineX, kFineRows), 0, s, in + off.off[l], out,
+                                   out, n0, n1, n2);
+            e = hipGetLastError();
+            continue;
+        }
+        const dim3 g = line_grid(m(n0, j), m(n1, j), (m(n2, j) + 1) / 2);
+        if (dec)
+            hipLaunchKernelGGL((k_ml_step<T, true>), g, dim3(kMl), 0, s, in, out + off.off[l], in, n1, n2, j,
+                               m(n0, j));
+        else
+            hipLaunchKernelGGL((k_ml_step<T, false>), g, dim3(kMl), 0, s, in + off.off[l], out, out, n1, n2, j,
+                               m(n0, j));
         e = hipGetLastError();
     }
     return e;
@@ -159,16 +355,16 @@ hipError_t launch_decompose(bool f64, const void* u, uint32_t n0, uint32_t n1, u
                             const MlOffsets& off, void* out, hipStream_t s)
 {
     if ((uint64_t)n0 * n1 * n2 == 0) return hipSuccess;
-    return f64 ? decompose_t(static_cast<const double*>(u), n0, n1, n2, nsteps, off, static_cast<double*>(out), s)
-               : decompose_t(static_cast<const float*>(u), n0, n1, n2, nsteps, off, static_cast<float*>(out), s);
+    return f64 ? ml_run(true, static_cast<const double*>(u), n0, n1, n2, nsteps, off, static_cast<double*>(out), s)
+               : ml_run(true, static_cast<const float*>(u), n0, n1, n2, nsteps, off, static_cast<float*>(out), s);
 }
 
 hipError_t launch_recompose(bool f64, const void* c, uint32_t n0, uint32_t n1, uint32_t n2, uint32_t nsteps,
                             const MlOffsets& off, void* u, hipStream_t s)
 {
     if ((uint64_t)n0 * n1 * n2 == 0) return hipSuccess;
-    return f64 ? recompose_t(static_cast<const double*>(c), n0, n1, n2, nsteps, off, static_cast<double*>(u), s)
-               : recompose_t(static_cast<const float*>(c), n0, n1, n2, nsteps, off, static_cast<float*>(u), s);
+    return f64 ? ml_run(false, static_cast<const double*>(c), n0, n1, n2, nsteps, off, static_cast<double*>(u), s)
+               : ml_run(false, static_cast<const float*>(c), n0, n1, n2, nsteps, off, static_cast<float*>(u), s);
 }
 
 }  // namespace mdr

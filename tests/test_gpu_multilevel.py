@@ -14,7 +14,9 @@ from oracle import multilevel as ml
 pytestmark = pytest.mark.gpu
 
 CASES = [((33, 17, 70), 3), ((1, 1, 1000), 5), ((65, 129, 257), 6), ((20, 31, 300), 4), ((3, 3, 3), 6),
-         ((9, 8, 7), 0), ((2, 600, 5), 7), ((1, 1, 1), 2), ((40, 1, 513), 9)]
+         ((9, 8, 7), 0), ((2, 600, 5), 7), ((1, 1, 1), 2), ((40, 1, 513), 9),
+         # rows of whole 16-byte vectors: the finest step takes the vector kernel
+         ((7, 9, 68), 3), ((6, 5, 4), 2), ((33, 18, 1024), 4), ((1, 3, 8), 1)]
 
 
 @pytest.fixture(scope="module")
@@ -74,6 +76,22 @@ def test_special_values_pass_through(mdr):
     np.testing.assert_array_equal(_bits(_decompose_gpu(mdr, u, nsteps)), _bits(want))
 
 
+def test_unaligned_field_takes_the_general_step(mdr):
+    import torch
+    shape, nsteps = (9, 10, 64), 3
+    u = workloads.smooth_field(15, shape, np.float32)
+    buf = torch.zeros(u.size + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = torch.from_numpy(u.ravel()).cuda()
+    field = buf[1:].view(shape)  # 4 bytes past a 16-byte boundary
+    out = torch.full((u.size,), float("nan"), dtype=torch.float32, device="cuda")
+    mdr.decompose(field, nsteps, out)
+    want = ml.concat(ml.decompose(u, nsteps))
+    np.testing.assert_array_equal(_bits(out.cpu().numpy()), _bits(want))
+    back = torch.zeros(u.size + 1, dtype=torch.float32, device="cuda")
+    mdr.recompose(out, nsteps, back[1:].view(shape))
+    np.testing.assert_array_equal(_bits(back[1:].cpu().numpy()), _bits(ml.recompose(ml.decompose(u, nsteps), shape, nsteps).ravel()))
+
+
 def test_full_size_field(mdr):
     shape, nsteps = (512, 512, 512), 8
     say("multilevel full size", shape)
@@ -88,7 +106,7 @@ def test_full_size_field(mdr):
 @pytest.mark.parametrize("dtype,rel", [(np.float32, 1e-2), (np.float32, 1e-4), (np.float64, 1e-7)])
 def test_field_through_the_path_meets_tolerance(mdr, orc, dtype, rel):
     import torch
-    shape, nsteps, B = (65, 97, 129), 5, 32 if dtype == np.float32 else 64
+    shape, nsteps, B = (65, 97, 132), 5, 32 if dtype == np.float32 else 64
     say("multilevel path", np.dtype(dtype).name, "rel", rel)
     u = workloads.smooth_field(14, shape, dtype)
     tol = rel * float(u.max() - u.min())
