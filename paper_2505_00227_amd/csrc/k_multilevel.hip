@@ -174,100 +174,151 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // The finest step (j = 0) when rows are whole 16-byte vectors (n2 % 4 == 0,
-// 16-byte aligned field): a lane takes nodes 4t .. 4t + 3 of its row with one
-// vector access per row it reads, the same arithmetic as k_ml_step.  The
-// level side (any alignment) goes through LDS so that its loads and stores are
-// lane-contiguous: the wavefront's coefficients are one contiguous run (256
-// of them, or 128 in a row with both indices even, fewer at a row's end).
-// Grid: (n2 / 4 / kFineX, n1 / kFineRows, n0), block (kFineX, kFineRows); a
-// wavefront covers 256 nodes of one row.
+// 16-byte aligned field): a lane takes kFineG groups of 4 consecutive nodes of
+// its row (group g of lane t: nodes 4(g kFineX + t) .. + 3), every load of
+// every group issued before any arithmetic so that a wavefront keeps more
+// bytes in flight per memory round trip; one 16-byte access per row read per
+// group, the same arithmetic as k_ml_step.  The level side (any alignment)
+// goes through LDS so that its loads and stores are lane-contiguous: the
+// wavefront's coefficients are one contiguous run (4 kFineG kFineX of them, half
+// in a row with both indices even, fewer at a row's end).  A wavefront takes
+// kFineR rows (b, b + kFineRows, ...), loading all of them first.  Grid:
+// (n2 / (4 kFineG kFineX), n1 / (kFineRows kFineR), n0), block (kFineX,
+// kFineRows).
+constexpr uint32_t kFineG = 2;                      // 4-node groups per lane and row
+constexpr uint32_t kFineR = 1;                      // rows per wavefront: b, b + kFineRows, ... (2 was
+                                                    // slower: more registers, no more bytes per round trip)
+constexpr uint32_t kFineRun = 4 * kFineG * kFineX;  // nodes per wavefront and row
+
 template <typename T, bool DEC>
-__device__ __forceinline__ void ml_fine_row(const T* __restrict__ in, T* out, const T* field, uint32_t n0,
-                                            uint32_t n1, uint32_t n2, uint64_t a, T* w)
+__device__ __forceinline__ void ml_fine_rows(const T* __restrict__ in, T* out, const T* field, uint32_t n0,
+                                             uint32_t n1, uint32_t n2, uint64_t a, T (*w)[kFineRun])
 {
 #pragma clang fp contract(off)
     const uint32_t lane = threadIdx.x;
-    const uint64_t q = n2 / 4;
-    const uint64_t t = (uint64_t)blockIdx.x * kFineX + lane;
-    const uint64_t b = (uint64_t)blockIdx.y * kFineRows + threadIdx.y;
-    if (b >= n1) return;  // whole wavefront
-    const bool live = t < q;
-    const bool coarse_row = !((a | b) & 1);
-    const uint64_t wnodes = 4 * (q - (uint64_t)blockIdx.x * kFineX < kFineX ? q - (uint64_t)blockIdx.x * kFineX
-                                                                              : kFineX);
-    const uint64_t wcoef = coarse_row ? wnodes / 2 : wnodes;  // this wavefront's run of coefficients
-    const uint64_t wbase = new_rank(a, b, 0, n1, n2) + (coarse_row ? 2 : 4) * (uint64_t)blockIdx.x * kFineX;
-    const uint64_t x = 4 * t;
-    const uint64_t self = (a * n1 + b) * n2 + x;
-    T c[4];  // recomposition: this lane's coefficients (nodes x .. x + 3; odd ones in a coarse row)
-    if (!DEC) {
+    const uint64_t q = n2 / 4;  // groups per row
+    const uint64_t g0 = (uint64_t)blockIdx.x * (kFineG * kFineX);
+    const uint64_t b0 = (uint64_t)blockIdx.y * (kFineRows * kFineR) + threadIdx.y;
+    if (b0 >= n1) return;  // whole wavefront
+    const uint64_t wgroups = q - g0 < kFineG * kFineX ? q - g0 : kFineG * kFineX;
+    const T half = T(0.5);
+    bool rlive[kFineR], coarse_row[kFineR];
+    uint64_t wcoef[kFineR], wbase[kFineR], row[kFineR];
+    CoarseRows<T> cr[kFineR];
+    T v[kFineR][kFineG][2][2][4], nx[kFineR][kFineG][2][2], u[kFineR][kFineG][4];
+    bool live[kFineG];
+    uint64_t xs[kFineG];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint64_t i = lane + (uint64_t)k * kFineX;
-            if (i < wcoef) w[i] = in[wbase + i];
+    for (uint32_t g = 0; g < kFineG; ++g) {
+        const uint64_t grp = g0 + (uint64_t)g * kFineX + lane;  // each access lane-contiguous
+        live[g] = grp < q;
+        xs[g] = 4 * grp;
+    }
+    // every load of every row and group first
+#pragma unroll
+    for (uint32_t rr = 0; rr < kFineR; ++rr) {
+        const uint64_t b = b0 + (uint64_t)rr * kFineRows;
+        rlive[rr] = b < n1;
+        if (!rlive[rr]) continue;
+        coarse_row[rr] = !((a | b) & 1);
+        wcoef[rr] = coarse_row[rr] ? 2 * wgroups : 4 * wgroups;  // this row's run of coefficients
+        wbase[rr] = new_rank(a, b, 0, n1, n2) + (coarse_row[rr] ? 2 : 4) * g0;
+        row[rr] = (a * n1 + b) * n2;
+        cr[rr] = coarse_rows(field, n1, n2, a, b, n0, n1, 0);
+#pragma unroll
+        for (uint32_t g = 0; g < kFineG; ++g) {
+            if (!live[g]) continue;
+#pragma unroll
+            for (int zi = 0; zi < 2; ++zi)
+#pragma unroll
+                for (int yi = 0; yi < 2; ++yi) {
+                    const T* r = cr[rr].r[zi][yi];
+                    load4(r + xs[g], v[rr][g][zi][yi]);
+                    nx[rr][g][zi][yi] = xs[g] + 4 < n2 ? r[xs[g] + 4] : T(0);
+                }
+            if (DEC) load4(in + row[rr] + xs[g], u[rr][g]);
         }
-        wave_sync();
-        if (coarse_row) {
-            c[1] = w[2 * lane];
-            c[3] = w[2 * lane + 1];
-        } else {
+        if (!DEC) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) c[k] = w[4 * lane + k];
+            for (uint32_t k = 0; k < 4 * kFineG; ++k) {
+                const uint64_t i = lane + (uint64_t)k * kFineX;
+                if (i < wcoef[rr]) w[rr][i] = in[wbase[rr] + i];
+            }
         }
     }
-    T P[4];
-    if (live) {
-        const CoarseRows<T> cr = coarse_rows(field, n1, n2, a, b, n0, n1, 0);
-        const bool x2 = x + 4 < n2;  // node x + 3 has a coarse node on its right
-        const T half = T(0.5);
-        T p[2][2][4];  // per coarse row: P along x of nodes x .. x + 3 (odd ones refined)
+    T c[kFineR][kFineG][4];  // recomposition: coefficients (odd nodes only in a coarse row)
+    if (!DEC) {
+        wave_sync();
 #pragma unroll
-        for (int zi = 0; zi < 2; ++zi)
+        for (uint32_t rr = 0; rr < kFineR; ++rr)
 #pragma unroll
-            for (int yi = 0; yi < 2; ++yi) {
-                const T* r = cr.r[zi][yi];
-                T v[4];
-                load4(r + x, v);
-                const T nx = x2 ? r[x + 4] : v[2];
-                p[zi][yi][0] = v[0];
-                p[zi][yi][1] = (v[0] + v[2]) * half;
-                p[zi][yi][2] = v[2];
-                p[zi][yi][3] = x2 ? (v[2] + nx) * half : v[2];
+            for (uint32_t g = 0; g < kFineG; ++g) {
+                const uint32_t slot = g * kFineX + lane;
+                if (rlive[rr] && coarse_row[rr]) {
+                    c[rr][g][1] = w[rr][2 * slot];
+                    c[rr][g][3] = w[rr][2 * slot + 1];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) c[rr][g][k] = w[rr][4 * slot + k];
+                }
             }
+        wave_sync();  // every lane has its coefficients before LDS is reused
+    }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const T y0 = cr.y2 ? (p[0][0][k] + p[0][1][k]) * half : p[0][0][k];
-            const T y1 = cr.y2 ? (p[1][0][k] + p[1][1][k]) * half : p[1][0][k];
-            P[k] = cr.z2 ? (y0 + y1) * half : y0;
+    for (uint32_t rr = 0; rr < kFineR; ++rr) {
+        if (!rlive[rr]) continue;
+#pragma unroll
+        for (uint32_t g = 0; g < kFineG; ++g) {
+            if (!live[g]) continue;
+            const bool x2 = xs[g] + 4 < n2;  // node x + 3 has a coarse node on its right
+            T p[2][2][4];  // per coarse row: P along x of nodes x .. x + 3 (odd ones refined)
+#pragma unroll
+            for (int zi = 0; zi < 2; ++zi)
+#pragma unroll
+                for (int yi = 0; yi < 2; ++yi) {
+                    const T* vv = v[rr][g][zi][yi];
+                    p[zi][yi][0] = vv[0];
+                    p[zi][yi][1] = (vv[0] + vv[2]) * half;
+                    p[zi][yi][2] = vv[2];
+                    p[zi][yi][3] = x2 ? (vv[2] + nx[rr][g][zi][yi]) * half : vv[2];
+                }
+            T P[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const T y0 = cr[rr].y2 ? (p[0][0][k] + p[0][1][k]) * half : p[0][0][k];
+                const T y1 = cr[rr].y2 ? (p[1][0][k] + p[1][1][k]) * half : p[1][0][k];
+                P[k] = cr[rr].z2 ? (y0 + y1) * half : y0;
+            }
+            const uint32_t slot = g * kFineX + lane;
+            if (DEC) {
+                if (coarse_row[rr]) {
+                    w[rr][2 * slot] = u[rr][g][1] - P[1];
+                    w[rr][2 * slot + 1] = u[rr][g][3] - P[3];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) w[rr][4 * slot + k] = u[rr][g][k] - P[k];
+                }
+            } else if (coarse_row[rr]) {
+                out[row[rr] + xs[g] + 1] = c[rr][g][1] + P[1];
+                out[row[rr] + xs[g] + 3] = c[rr][g][3] + P[3];
+            } else {
+                T o[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) o[k] = c[rr][g][k] + P[k];
+                store4(out + row[rr] + xs[g], o);
+            }
         }
     }
     if (DEC) {
-        if (live) {
-            T u[4];
-            load4(in + self, u);
-            if (coarse_row) {
-                w[2 * lane] = u[1] - P[1];
-                w[2 * lane + 1] = u[3] - P[3];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) w[4 * lane + k] = u[k] - P[k];
-            }
-        }
         wave_sync();
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint64_t i = lane + (uint64_t)k * kFineX;
-            if (i < wcoef) out[wbase + i] = w[i];
-        }
-    } else if (live) {
-        if (coarse_row) {
-            out[self + 1] = c[1] + P[1];
-            out[self + 3] = c[3] + P[3];
-        } else {
-            T u[4];
+        for (uint32_t rr = 0; rr < kFineR; ++rr) {
+            if (!rlive[rr]) continue;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) u[k] = c[k] + P[k];
-            store4(out + self, u);
+            for (uint32_t k = 0; k < 4 * kFineG; ++k) {
+                const uint64_t i = lane + (uint64_t)k * kFineX;
+                if (i < wcoef[rr]) out[wbase[rr] + i] = w[rr][i];
+            }
         }
     }
 }
@@ -283,8 +334,8 @@ template <typename T, bool DEC>
 __global__ __launch_bounds__(kFineX* kFineRows) void k_ml_fine(const T* __restrict__ in, T* out, const T* field,
                                                                uint32_t n0, uint32_t n1, uint32_t n2)
 {
-    __shared__ T xch[kFineRows][4 * kFineX];
-    ml_fine_row<T, DEC>(in, out, field, n0, n1, n2, blockIdx.z, xch[threadIdx.y]);
+    __shared__ T xch[kFineRows][kFineR][kFineRun];
+    ml_fine_rows<T, DEC>(in, out, field, n0, n1, n2, blockIdx.z, xch[threadIdx.y]);
 }
 
 // coarsest grid (stride 2^nsteps): DEC copies field -> level 0, else back
@@ -327,7 +378,8 @@ hipError_t ml_run(bool dec, const T* in, uint32_t n0, uint32_t n1, uint32_t n2, 
     for (uint32_t l = 1; l <= nsteps && e == hipSuccess; ++l) {
         const uint32_t j = nsteps - l;
         if (j == 0 && fine_vec) {
-            const dim3 g((uint32_t)((n2 / 4 + kFineX - 1) / kFineX), (n1 + kFineRows - 1) / kFineRows, n0);
+            const dim3 g((uint32_t)((n2 / 4 + kFineG * kFineX - 1) / (kFineG * kFineX)),
+                         (n1 + kFineRows * kFineR - 1) / (kFineRows * kFineR), n0);
             if (dec)
                 hipLaunchKernelGGL((k_ml_fine<T, true>), g, dim3(kFineX, kFineRows), 0, s, in, out + off.off[l], in,
                                    n0, n1, n2);
