@@ -67,7 +67,7 @@ def parse():
                     help="multilevel decomposition of the 512^3 field, and the field through the whole path")
     ap.add_argument("--ablation", action="store_true",
                     help="encoder-design ablation: 32-bit words <-> 32 planes by each design, 2^20..2^28 words")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22,
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25,
                     help="values of the finest level the oracle baseline refactors")
     return ap.parse_args()
 
