@@ -14,10 +14,10 @@
 //
 // One launch per level.  A decomposition step reads only the input field, so
 // its launches are independent; a recomposition step reads the nodes of every
-// coarser step, so they run coarsest first.  Within a step a workgroup covers
+// coarser step, so they run coarsest first.  Within a step a wavefront covers
 // part of one row of the step's grid and a lane an (even, odd) pair of its
-// nodes: the row's parity, coarse rows and output offset are uniform, and
-// consecutive lanes touch consecutive nodes.
+// nodes (in the finest step, groups of 4): the row's parity, coarse rows and
+// output offset are uniform, and consecutive lanes touch consecutive nodes.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -102,8 +102,12 @@ __device__ __forceinline__ void predict_pair(const CoarseRows<T>& cr, uint64_t x
 }
 
 // Step j of the decomposition (DEC: field -> level) or of the recomposition
-// (field of the coarser steps + level -> field).  Grid: (pairs / kMl, m1, m0)
-// over the stride-h grid; a lane takes the nodes 2t and 2t + 1 of its row.
+// (field of the coarser steps + level -> field).  Grid: (pairs / kStepX,
+// m1 / kStepRows, m0) over the stride-h grid, block (kStepX, kStepRows): a
+// wavefront per row (rows of the coarser steps are short), and a lane takes the
+// nodes 2t and 2t + 1 of its row.
+constexpr uint32_t kStepX = 64, kStepRows = 4;
+
 // In a row with a or b odd every node is new and the row's coefficients are
 // contiguous from new_rank(a, b, 0); in a row with both even only odd x is new.
 template <typename T, bool DEC>
@@ -112,9 +116,9 @@ __device__ __forceinline__ void ml_step_row(const T* __restrict__ in, T* out, co
 {
 #pragma clang fp contract(off)
     const uint64_t m1 = axis_nodes(n1, j), m2 = axis_nodes(n2, j);
-    const uint64_t t = (uint64_t)blockIdx.x * kMl + threadIdx.x;
-    if (2 * t >= m2) return;
-    const uint64_t b = blockIdx.y;
+    const uint64_t t = (uint64_t)blockIdx.x * kStepX + threadIdx.x;
+    const uint64_t b = (uint64_t)blockIdx.y * kStepRows + threadIdx.y;
+    if (2 * t >= m2 || b >= m1) return;
     const bool coarse_row = !((a | b) & 1);
     const uint64_t base = new_rank(a, b, 0, m1, m2);
     const CoarseRows<T> cr = coarse_rows(field, n1, n2, a, b, m0, m1, j);
@@ -324,7 +328,7 @@ __device__ __forceinline__ void ml_fine_rows(const T* __restrict__ in, T* out, c
 }
 
 template <typename T, bool DEC>
-__global__ __launch_bounds__(kMl) void k_ml_step(const T* __restrict__ in, T* out, const T* field,
+__global__ __launch_bounds__(kStepX* kStepRows) void k_ml_step(const T* __restrict__ in, T* out, const T* field,
                                                  uint32_t n1, uint32_t n2, uint32_t j, uint64_t m0)
 {
     ml_step_row<T, DEC>(in, out, field, n1, n2, j, m0, blockIdx.z);
@@ -389,13 +393,14 @@ hipError_t ml_run(bool dec, const T* in, uint32_t n0, uint32_t n1, uint32_t n2, 
             e = hipGetLastError();
             continue;
         }
-        const dim3 g = line_grid(m(n0, j), m(n1, j), (m(n2, j) + 1) / 2);
+        const dim3 g((uint32_t)(((m(n2, j) + 1) / 2 + kStepX - 1) / kStepX),
+                     (uint32_t)((m(n1, j) + kStepRows - 1) / kStepRows), (uint32_t)m(n0, j));
         if (dec)
-            hipLaunchKernelGGL((k_ml_step<T, true>), g, dim3(kMl), 0, s, in, out + off.off[l], in, n1, n2, j,
-                               m(n0, j));
+            hipLaunchKernelGGL((k_ml_step<T, true>), g, dim3(kStepX, kStepRows), 0, s, in, out + off.off[l], in, n1,
+                               n2, j, m(n0, j));
         else
-            hipLaunchKernelGGL((k_ml_step<T, false>), g, dim3(kMl), 0, s, in + off.off[l], out, out, n1, n2, j,
-                               m(n0, j));
+            hipLaunchKernelGGL((k_ml_step<T, false>), g, dim3(kStepX, kStepRows), 0, s, in + off.off[l], out, out,
+                               n1, n2, j, m(n0, j));
         e = hipGetLastError();
     }
     return e;
