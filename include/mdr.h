@@ -441,7 +441,8 @@ mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t 
  * overlapping; work is enqueued on `stream` (one launch to decompose,
  * nsteps + 1 to recompose).  nsteps <= 30 (steps past the grid's extent give
  * empty levels); n0, n1 < 65536 and n2 < 2^31, else MDR_ERR_UNSUPPORTED;
- * NULL, misaligned or overlapping buffers, a bad dtype or nsteps:
+ * NULL, misaligned or overlapping buffers, a buffer that is not inside one
+ * device allocation of at least n0*n1*n2 values, a bad dtype or nsteps:
  * MDR_ERR_INVALID_ARG.  An empty grid is a no-op. */
 mdr_status mdr_level_sizes(uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps, uint64_t* sizes);
 mdr_status mdr_decompose(mdr_dtype dtype, const void* field, uint64_t n0, uint64_t n1, uint64_t n2, uint32_t nsteps,

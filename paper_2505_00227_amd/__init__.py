@@ -477,11 +477,18 @@ def _ml_dtype(t) -> int:
     raise TypeError("multilevel decomposition takes float32 or float64 tensors")
 
 
+def _ml_check(field, coeffs, what: str) -> None:
+    if field.dim() != 3 or not field.is_contiguous() or not coeffs.is_contiguous() \
+            or coeffs.dtype != field.dtype or coeffs.numel() != field.numel():
+        raise ValueError(what + ": contiguous 3-D field and a contiguous coefficient buffer of the same size and dtype")
+    if not (field.is_cuda and coeffs.is_cuda):
+        raise ValueError(what + ": field and coefficients must be device tensors")
+
+
 def decompose(field, nsteps: int, coeffs, stream=None) -> None:
     """mdr_decompose: field (contiguous n0 x n1 x n2 device tensor) -> coeffs
     (its levels concatenated, coarsest first)."""
-    if field.dim() != 3 or not field.is_contiguous() or coeffs.dtype != field.dtype or coeffs.numel() != field.numel():
-        raise ValueError("decompose: contiguous 3-D field and a coefficient buffer of the same size and dtype")
+    _ml_check(field, coeffs, "decompose")
     n0, n1, n2 = field.shape
     _check(_lib.mdr_decompose(_ml_dtype(field), C.c_void_p(field.data_ptr()), n0, n1, n2, int(nsteps),
                               C.c_void_p(coeffs.data_ptr()), _stream_ptr(stream)))
@@ -489,8 +496,7 @@ def decompose(field, nsteps: int, coeffs, stream=None) -> None:
 
 def recompose(coeffs, nsteps: int, field, stream=None) -> None:
     """mdr_recompose: concatenated levels -> field (contiguous n0 x n1 x n2 device tensor)."""
-    if field.dim() != 3 or not field.is_contiguous() or coeffs.dtype != field.dtype or coeffs.numel() != field.numel():
-        raise ValueError("recompose: contiguous 3-D field and a coefficient buffer of the same size and dtype")
+    _ml_check(field, coeffs, "recompose")
     n0, n1, n2 = field.shape
     _check(_lib.mdr_recompose(_ml_dtype(field), C.c_void_p(coeffs.data_ptr()), n0, n1, n2, int(nsteps),
                               C.c_void_p(field.data_ptr()), _stream_ptr(stream)))

@@ -781,6 +781,20 @@ static bool ranges_overlap(const void* a, const void* b, uint64_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
+// [p, p + bytes) inside one device allocation (a host pointer, or a buffer too
+// small for the grid, would fault in the kernels)
+static bool device_range(const void* p, uint64_t bytes)
+{
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base), x = reinterpret_cast<uintptr_t>(p);
+    return x >= b && x - b + bytes <= size;
+}
+
 static mdr_status ml_run(bool decompose, mdr_dtype dtype, const void* in, uint64_t n0, uint64_t n1, uint64_t n2,
                          uint32_t nsteps, void* out, void* stream)
 {
@@ -796,6 +810,8 @@ static mdr_status ml_run(bool decompose, mdr_dtype dtype, const void* in, uint64
         return fail(MDR_ERR_INVALID_ARG, "buffers must be aligned to the value size");
     if (ranges_overlap(in, out, total * w)) return fail(MDR_ERR_INVALID_ARG, "input and output overlap");
     (void)hipGetLastError();
+    if (!device_range(in, total * w) || !device_range(out, total * w))
+        return fail(MDR_ERR_INVALID_ARG, "buffers must be device memory holding n0*n1*n2 values");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     if (decompose)
         MDR_HIP(mdr::launch_decompose(dtype == MDR_F64, in, (uint32_t)n0, (uint32_t)n1, (uint32_t)n2, nsteps, off, out, s));

@@ -92,6 +92,33 @@ def test_unaligned_field_takes_the_general_step(mdr):
     np.testing.assert_array_equal(_bits(back[1:].cpu().numpy()), _bits(ml.recompose(ml.decompose(u, nsteps), shape, nsteps).ravel()))
 
 
+def test_bad_buffers_are_rejected(mdr):
+    import torch
+    shape = (9, 10, 64)
+    n = 9 * 10 * 64
+    field = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    short = torch.zeros(n - 1, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        mdr.decompose(field, 3, short)                     # size
+    with pytest.raises(ValueError):
+        mdr.decompose(field, 3, torch.zeros(n, dtype=torch.float32))  # host tensor
+    with pytest.raises(ValueError):
+        mdr.decompose(field, 3, torch.zeros(2 * n, dtype=torch.float32, device="cuda")[::2])  # strided
+    # through the C ABI: a host buffer, and a device buffer too small for the grid
+    import ctypes as C
+    host = torch.zeros(n, dtype=torch.float32).numpy()
+    st = mdr.mdr_decompose(mdr.MDR_F32, C.c_void_p(field.data_ptr()), 9, 10, 64, 3,
+                           C.c_void_p(host.ctypes.data), None)
+    assert st == mdr.MDR_ERR_INVALID_ARG and b"device memory" in mdr.mdr_last_error()
+    small = torch.cuda.caching_allocator_alloc(1 << 10)  # its own small block
+    try:
+        st = mdr.mdr_recompose(mdr.MDR_F32, C.c_void_p(small), 90, 100, 640, 3,
+                               C.c_void_p(field.data_ptr()), None)
+        assert st == mdr.MDR_ERR_INVALID_ARG
+    finally:
+        torch.cuda.caching_allocator_delete(small)
+
+
 def test_full_size_field(mdr):
     shape, nsteps = (512, 512, 512), 8
     say("multilevel full size", shape)
