@@ -423,6 +423,33 @@ def retrieve(levels, k):
     return [lv.reconstruct(int(kl)) for lv, kl in zip(levels, k)]
 
 
+def l2_table(x: np.ndarray, lv: "Level") -> np.ndarray:
+    """Squared L2 error of a level after k planes, k = 0..B (an MDR option the
+    paper does not use; it controls L-infinity error throughout): E2[k] =
+    sum_i (x_i - xhat_i^(k))^2, with xhat^(k) the oracle's own k-plane
+    reconstruction, each square rounded once in fp64 and the sum exactly
+    rounded (math.fsum)."""
+    x64 = np.asarray(x, np.float64)
+    out = np.zeros(lv.B + 1, np.float64)
+    for k in range(lv.B + 1):
+        r = x64 - lv.reconstruct(k).astype(np.float64)
+        out[k] = math.fsum((r * r).tolist())
+    return out
+
+
+def plan_l2(levels, tables, tol: float, k_in=None):
+    """The greedy planner of `plan` run on squared-L2 tables against tol^2."""
+    L = len(levels)
+    B, m = levels[0].B, levels[0].m
+    kin = np.zeros(L, np.uint32) if k_in is None else np.ascontiguousarray(k_in, np.uint32)
+    kout = np.zeros(L, np.uint32)
+    bound = C.c_double()
+    E2 = np.ascontiguousarray(np.stack([np.asarray(t, np.float64) for t in tables]))
+    lib().orc_plan(L, B, m, _ptr(E2), _ptr(_U_matrix(levels)), tol * tol, _ptr(kin), _ptr(kout),
+                   C.byref(bound))
+    return [int(v) for v in kout], bound.value
+
+
 def retrieve_to(levels, tol: float, relative: bool = True, k_in=None):
     tol_abs = tol * variable_range(levels) if relative else tol
     k, bound = plan(levels, tol_abs, k_in)
