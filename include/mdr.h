@@ -50,7 +50,10 @@ typedef enum { MDR_F32 = 0, MDR_F64 = 1 } mdr_dtype;
 typedef enum { MDR_DC = 0, MDR_RLE = 1, MDR_HUF = 2, MDR_PLACEHOLDER = 3 } mdr_method;
 
 /* MDR_REL: tolerance x (max - min over every coefficient of the variable) */
-typedef enum { MDR_ABS = 0, MDR_REL = 1 } mdr_bound;
+/* MDR_L2: absolute bound on the L2 norm of the variable's coefficient error,
+ * sqrt(sum over levels of E2[k]) <= tol; mdr_retrieve only, after
+ * mdr_l2_table. */
+typedef enum { MDR_ABS = 0, MDR_REL = 1, MDR_L2 = 2 } mdr_bound;
 
 /* Codec parameters of Alg. 2.  Every field is recorded in the serialized form. */
 typedef struct {
@@ -416,6 +419,25 @@ typedef enum {
 uint64_t mdr_ablation_plane_words(int32_t design, uint64_t n);
 mdr_status mdr_ablation_encode(int32_t design, const uint32_t* in, uint64_t n, uint32_t* planes, void* stream);
 mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t n, uint32_t* out, void* stream);
+
+/* ---- Squared-L2 per-plane table (the MDR L2 option) -----------------------
+ * The paper controls L-infinity error throughout; MDR also offers an L2 error
+ * table, which this adds beside the exact L-infinity one.  E2[k] =
+ * sum_i (x_i - xhat_i^(k))^2 over a level, k = 0..nplanes, where xhat^(k) is
+ * the k-plane reconstruction; residuals are exact, squares rounded once, sums
+ * in fp64 in a fixed order (the same on every run).
+ * mdr_l2_table: computes the tables of every level of `r` from the values it
+ * was refactored from (`levels`, nlevels and each n as given to mdr_refactor;
+ * device memory, borrowed), keeps them in `r`, and waits for `stream`.
+ * Mismatched counts or sizes, NULL, misaligned or non-device data:
+ * MDR_ERR_INVALID_ARG.  A deserialized object has no table until this runs.
+ * mdr_refactored_l2: copies level `level`'s table (nplanes + 1 doubles) to
+ * host memory; MDR_ERR_INVALID_ARG if there is none.
+ * With the tables, mdr_retrieve(kind = MDR_L2, tol) plans the fewest groups
+ * (same greedy planner) with sum_l E2_l[k_l] <= tol^2; info->bound is then
+ * the L2 bound sqrt(sum_l E2_l[k_l]). */
+mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, void* stream);
+mdr_status mdr_refactored_l2(const mdr_refactored* r, uint32_t level, double* E2);
 
 /* ---- Multilevel decomposition (the coefficient levels of Sec. 2/3) ---------
  * The method's input is the coefficient levels of a multilevel decomposition

@@ -33,7 +33,7 @@ MDR_OK, MDR_ERR_INVALID_ARG, MDR_ERR_UNSUPPORTED, MDR_ERR_OUT_OF_MEMORY = 0, 1, 
 MDR_ERR_HIP, MDR_ERR_CORRUPT_STREAM, MDR_ERR_BUSY = 4, 5, 6
 MDR_F32, MDR_F64 = 0, 1
 MDR_DC, MDR_RLE, MDR_HUF, MDR_PLACEHOLDER = 0, 1, 2, 3
-MDR_ABS, MDR_REL = 0, 1
+MDR_ABS, MDR_REL, MDR_L2 = 0, 1, 2
 MDR_MAX_PLANES = 64
 STAGES = ["stats", "encode", "select", "lossless", "assemble", "huf_decode", "rle_decode",
           "reconstruct"]
@@ -144,6 +144,8 @@ _SIGS = {
                                  _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
     "mdr_retrieve_qoi_vtotal_with": ([_vp, _vp, _vp, C.c_int, C.c_double, _P(mdr_qoi_params), _P(_vp),
                                       _P(_vp), _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
+    "mdr_l2_table": ([_vp, _P(mdr_level_view), _u32, _vp], C.c_int),
+    "mdr_refactored_l2": ([_vp, _u32, _P(C.c_double)], C.c_int),
     "mdr_level_sizes": ([_u64, _u64, _u64, _u32, _P(_u64)], C.c_int),
     "mdr_decompose": ([C.c_int, _vp, _u64, _u64, _u64, _u32, _vp, _vp], C.c_int),
     "mdr_recompose": ([C.c_int, _vp, _u64, _u64, _u64, _u32, _vp, _vp], C.c_int),
@@ -293,6 +295,17 @@ class Refactored:
     def __del__(self):
         self.close()
 
+    def l2_table(self, levels, stream=None) -> None:
+        """mdr_l2_table: squared-L2 per-plane tables from the levels this was refactored from."""
+        views, _ = _views(levels, self.dtype)
+        _check(_lib.mdr_l2_table(self.handle, views, len(levels), _stream_ptr(stream)))
+
+    def l2(self, level: int):
+        """mdr_refactored_l2: the level's squared-L2 table (nplanes + 1 values)."""
+        out = (C.c_double * (self.nplanes + 1))()
+        _check(_lib.mdr_refactored_l2(self.handle, level, out))
+        return list(out)
+
     def info(self, level: int) -> dict:
         e, n = _i32(), _u64()
         lo, hi = C.c_double(), C.c_double()
@@ -395,6 +408,13 @@ class Retriever:
         info = mdr_retrieve_info()
         _check(_lib.mdr_retrieve(self.handle, MDR_REL if relative else MDR_ABS, float(tol),
                                  self._outs(outs), _stream_ptr(stream), C.byref(info)))
+        return info.as_dict()
+
+    def retrieve_l2(self, tol: float, outs, stream=None) -> dict:
+        """mdr_retrieve with MDR_L2: L2 norm of the coefficient error <= tol."""
+        info = mdr_retrieve_info()
+        _check(_lib.mdr_retrieve(self.handle, MDR_L2, float(tol), self._outs(outs), _stream_ptr(stream),
+                                 C.byref(info)))
         return info.as_dict()
 
     def retrieve_planes(self, k, outs, stream=None) -> dict:

@@ -157,10 +157,10 @@ mdr_status check_params(const mdr_codec_params& p, uint32_t B)
 // merged group in the level of largest (error drop) / (bytes to fetch),
 // ties to the smallest level; when every drop is zero, the level whose
 // current error is largest.
-double plan_bound(const mdr_refactored* r, const std::vector<uint32_t>& k)
+double plan_bound(const mdr_refactored* r, const std::vector<uint32_t>& k, ErrTable tab)
 {
     double s = 0.0;
-    for (size_t l = 0; l < r->levels.size(); ++l) s += r->levels[l].E[k[l]];
+    for (size_t l = 0; l < r->levels.size(); ++l) s += (r->levels[l].*tab)[k[l]];
     return s;
 }
 
@@ -171,7 +171,7 @@ static uint64_t group_cost(const mdr_refactored* r, size_t l, uint32_t kl)
     return c ? c : 1;
 }
 
-bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k)
+bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k, ErrTable tab)
 {
     const uint32_t B = r->B, m = r->m;
     int best = -1;
@@ -179,7 +179,7 @@ bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k)
     for (size_t l = 0; l < r->levels.size(); ++l) {
         if (k[l] >= B) continue;
         uint32_t nxt = std::min(B, k[l] + m);
-        const std::vector<double>& E = r->levels[l].E;
+        const std::vector<double>& E = r->levels[l].*tab;
         double gain = (E[k[l]] - E[nxt]) / (double)group_cost(r, l, k[l]);
         if (best < 0 || gain > best_gain) {
             best = (int)l;
@@ -192,7 +192,7 @@ bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k)
         double worst = 0.0;
         for (size_t l = 0; l < r->levels.size(); ++l) {
             if (k[l] >= B) continue;
-            double el = r->levels[l].E[k[l]];
+            double el = (r->levels[l].*tab)[k[l]];
             if (best < 0 || el > worst) {
                 best = (int)l;
                 worst = el;
@@ -203,12 +203,12 @@ bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k)
     return true;
 }
 
-double plan_to(const mdr_refactored* r, double tol, std::vector<uint32_t>& k)
+double plan_to(const mdr_refactored* r, double tol, std::vector<uint32_t>& k, ErrTable tab)
 {
-    double b = plan_bound(r, k);
+    double b = plan_bound(r, k, tab);
     while (b > tol) {
-        if (!plan_step(r, k)) break;
-        b = plan_bound(r, k);
+        if (!plan_step(r, k, tab)) break;
+        b = plan_bound(r, k, tab);
     }
     return b;
 }
@@ -483,9 +483,20 @@ mdr_status mdr_retrieve(mdr_retriever* rt, mdr_bound kind, double tol, void* con
     g_err.clear();
     if (!rt || !level_out) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
     if (!(tol >= 0.0) || std::isinf(tol)) return fail(MDR_ERR_INVALID_ARG, "tolerance must be finite and >= 0");
-    if (kind != MDR_ABS && kind != MDR_REL) return fail(MDR_ERR_INVALID_ARG, "bad bound kind");
-    double tol_abs = kind == MDR_REL ? tol * value_range(rt->r) : tol;
+    if (kind != MDR_ABS && kind != MDR_REL && kind != MDR_L2) return fail(MDR_ERR_INVALID_ARG, "bad bound kind");
     std::vector<uint32_t> k = rt->k;
+    if (kind == MDR_L2) {
+        for (const LevelRec& L : rt->r->levels)
+            if (L.E2.size() != rt->r->B + 1) return fail(MDR_ERR_INVALID_ARG, "no L2 table: call mdr_l2_table first");
+        plan_to(rt->r, tol * tol, k, &LevelRec::E2);
+        mdr_status st = retrieve_one(rt, k, level_out, static_cast<hipStream_t>(stream), tol, info);
+        if (!st && info) {  // report the L2 bound, not the squared one
+            info->bound = std::sqrt(plan_bound(rt->r, k, &LevelRec::E2));
+            info->met = info->bound <= tol;
+        }
+        return st;
+    }
+    double tol_abs = kind == MDR_REL ? tol * value_range(rt->r) : tol;
     plan_to(rt->r, tol_abs, k);
     return retrieve_one(rt, k, level_out, static_cast<hipStream_t>(stream), tol_abs, info);
 }
@@ -845,6 +856,62 @@ mdr_status mdr_recompose(mdr_dtype dtype, const void* coeffs, uint64_t n0, uint6
                          void* field, void* stream)
 {
     return ml_run(false, dtype, coeffs, n0, n1, n2, nsteps, field, stream);
+}
+
+}  // extern "C"
+
+// ---- squared-L2 per-plane table ---------------------------------------------
+
+extern "C" {
+
+mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, void* stream)
+{
+    g_err.clear();
+    if (!r || (nlevels && !levels)) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
+    if (nlevels != r->levels.size()) return fail(MDR_ERR_INVALID_ARG, "level count differs from the refactored one");
+    const uint64_t w = r->dtype == MDR_F64 ? 8 : 4;
+    uint64_t nmax = 0;
+    for (uint32_t l = 0; l < nlevels; ++l) {
+        if (levels[l].n != r->levels[l].n) return fail(MDR_ERR_INVALID_ARG, "level sizes differ from the refactored ones");
+        if (levels[l].n == 0) continue;
+        if (!levels[l].data || reinterpret_cast<uintptr_t>(levels[l].data) % w)
+            return fail(MDR_ERR_INVALID_ARG, "level data must be non-NULL and aligned to the value size");
+        (void)hipGetLastError();
+        if (!device_range(levels[l].data, levels[l].n * w))
+            return fail(MDR_ERR_INVALID_ARG, "level data must be device memory holding n values");
+        nmax = std::max(nmax, levels[l].n);
+    }
+    const uint32_t B = r->B;
+    MDR_HIP(hipSetDevice(r->ctx->device));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    PoolBuf part, out;
+    MDR_HIP(part.alloc(r->ctx->pool, (uint64_t)l2_table_workgroups(nmax) * (B + 1) * 8));
+    MDR_HIP(out.alloc(r->ctx->pool, (uint64_t)nlevels * (B + 1) * 8));
+    std::vector<double> host((size_t)nlevels * (B + 1), 0.0);
+    for (uint32_t l = 0; l < nlevels; ++l) {
+        if (levels[l].n == 0) continue;
+        MDR_HIP(launch_l2_table(r->dtype == MDR_F64, levels[l].data, levels[l].n, r->levels[l].e, B,
+                                static_cast<double*>(part.p), static_cast<double*>(out.p) + (size_t)l * (B + 1), s));
+        // the next level reuses the partial sums: keep the launches in stream order
+    }
+    for (uint32_t l = 0; l < nlevels; ++l)
+        if (levels[l].n)
+            MDR_HIP(hipMemcpyAsync(host.data() + (size_t)l * (B + 1), static_cast<double*>(out.p) + (size_t)l * (B + 1),
+                                   (B + 1) * 8, hipMemcpyDeviceToHost, s));
+    MDR_HIP(hipStreamSynchronize(s));
+    for (uint32_t l = 0; l < nlevels; ++l)
+        r->levels[l].E2.assign(host.begin() + (size_t)l * (B + 1), host.begin() + (size_t)(l + 1) * (B + 1));
+    return MDR_OK;
+}
+
+mdr_status mdr_refactored_l2(const mdr_refactored* r, uint32_t level, double* E2)
+{
+    if (!r || !E2) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
+    if (level >= r->levels.size()) return fail(MDR_ERR_INVALID_ARG, "no such level");
+    const std::vector<double>& t = r->levels[level].E2;
+    if (t.size() != r->B + 1) return fail(MDR_ERR_INVALID_ARG, "no L2 table: call mdr_l2_table first");
+    std::copy(t.begin(), t.end(), E2);
+    return MDR_OK;
 }
 
 }  // extern "C"

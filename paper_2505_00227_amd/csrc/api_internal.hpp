@@ -115,6 +115,7 @@ struct LevelRec {
     int32_t e = 0;
     double vmin = 0, vmax = 0, vmaxabs = 0;
     std::vector<double> E;      // B+1
+    std::vector<double> E2;     // B+1 squared-L2 errors, once mdr_l2_table has run (else empty)
     uint32_t* rows = nullptr;   // [(B+1)][nbd]
     UnitRec units[kMaxRows];    // slot 0 = sign, 1+p = plane p
 };
@@ -202,9 +203,12 @@ mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const 
                        unsigned long long* acc0, uint32_t nacc, hipStream_t s, bool argmax = false);
 
 // tolerance planner (greedy over levels, exact error tables)
-double plan_bound(const mdr_refactored* r, const std::vector<uint32_t>& k);
-bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k);
-double plan_to(const mdr_refactored* r, double tol, std::vector<uint32_t>& k);
+// the greedy planner over an error table of each level: E (L-infinity, the
+// default) or E2 (squared L2, with tol the squared tolerance)
+using ErrTable = const std::vector<double> LevelRec::*;
+double plan_bound(const mdr_refactored* r, const std::vector<uint32_t>& k, ErrTable tab = &LevelRec::E);
+bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k, ErrTable tab = &LevelRec::E);
+double plan_to(const mdr_refactored* r, double tol, std::vector<uint32_t>& k, ErrTable tab = &LevelRec::E);
 double value_range(const mdr_refactored* r);
 
 // Staging for the job tables of asynchronous launches: pinned host memory and

@@ -1,0 +1,93 @@
+// Squared L2 error of a level after k planes, k = 0..B: the L2 error table
+// that MDR offers beside the L-infinity one (the paper controls L-infinity
+// error throughout).  E2[k] = sum_i (|x_i| - xhat_k(|x_i|))^2 with
+// xhat_k(a) = floor(a 2^(k-e)) 2^(e-k), the magnitude the retrieval rebuilds
+// from k planes of the level aligned to exponent e.  Every residual is exact
+// in fp64 (it is a run of the value's own significand bits); each square is
+// rounded once and the sums run in fp64 in a fixed order (per thread, then a
+// fixed tree per workgroup, then workgroups in index order), so the table is
+// the same on every run.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "mdr_internal.hpp"
+
+namespace mdr {
+namespace {
+
+constexpr uint32_t kL2 = 256;  // threads per workgroup
+
+template <typename T, int KMAX>
+__global__ __launch_bounds__(kL2) void k_l2_partial(const T* __restrict__ x, uint64_t n, int e, uint32_t B,
+                                                    double* __restrict__ part)
+{
+#pragma clang fp contract(off)
+    __shared__ double red[kL2 / 64][KMAX + 1];
+    double acc[KMAX + 1];
+#pragma unroll
+    for (int k = 0; k <= KMAX; ++k) acc[k] = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kL2;
+    for (uint64_t i = (uint64_t)blockIdx.x * kL2 + threadIdx.x; i < n; i += stride) {
+        const double a = std::fabs((double)x[i]);
+#pragma unroll
+        for (int k = 0; k <= KMAX; ++k) {
+            if (k <= (int)B) {
+                // exact power-of-two scalings (a scaled value below 1 may round, its floor is 0 either way)
+                const double r = a - std::ldexp(std::floor(std::ldexp(a, k - e)), e - k);
+                acc[k] += r * r;
+            }
+        }
+    }
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k <= KMAX; ++k) {
+        double v = acc[k];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x <= B) {
+        double v = 0.0;
+#pragma unroll
+        for (uint32_t w = 0; w < kL2 / 64; ++w) v += red[w][threadIdx.x];
+        part[(uint64_t)blockIdx.x * (B + 1) + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_l2_final(const double* __restrict__ part, uint32_t nwg, uint32_t B, double* __restrict__ out)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > B) return;
+    double v = 0.0;
+    for (uint32_t w = 0; w < nwg; ++w) v += part[(uint64_t)w * (B + 1) + k];
+    out[k] = v;
+}
+
+}  // namespace
+
+uint32_t l2_table_workgroups(uint64_t n)
+{
+    const uint64_t w = (n + kL2 * 8 - 1) / (kL2 * 8);
+    return (uint32_t)(w < 1 ? 1 : (w > 1024 ? 1024 : w));
+}
+
+hipError_t launch_l2_table(bool f64, const void* x, uint64_t n, int e, uint32_t B, double* part, double* out,
+                           hipStream_t s)
+{
+    const uint32_t nwg = l2_table_workgroups(n);
+    if (f64)
+        hipLaunchKernelGGL((k_l2_partial<double, 64>), dim3(nwg), dim3(kL2), 0, s, static_cast<const double*>(x), n,
+                           e, B, part);
+    else
+        hipLaunchKernelGGL((k_l2_partial<float, 32>), dim3(nwg), dim3(kL2), 0, s, static_cast<const float*>(x), n,
+                           e, B, part);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(128), 0, s, part, nwg, B, out);
+    return hipGetLastError();
+}
+
+}  // namespace mdr

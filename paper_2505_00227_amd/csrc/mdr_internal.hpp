@@ -205,6 +205,12 @@ struct CopySpans {
 };
 hipError_t launch_copy_out(const CopySpans& sp, hipStream_t s);
 
+// ---- squared-L2 per-plane table (k_l2.hip)
+// part: l2_table_workgroups(n) * (B + 1) doubles; out: B + 1 doubles; B <= 32 for f32, <= 64 for f64
+uint32_t l2_table_workgroups(uint64_t n);
+hipError_t launch_l2_table(bool f64, const void* x, uint64_t n, int e, uint32_t B, double* part, double* out,
+                           hipStream_t s);
+
 // ---- multilevel decomposition (k_multilevel.hip): field <-> coefficient levels
 constexpr uint32_t kMlMaxSteps = 30;
 struct MlOffsets {

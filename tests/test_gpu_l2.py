@@ -1,0 +1,108 @@
+"""Squared-L2 per-plane tables and L2-driven retrieval on the GPU.
+
+Tables: within a relative 1e-12 of the oracle's exactly rounded sums.  Every
+residual and square agree bit for bit; only the summation order differs, and
+the kernel adds non-negative terms in three stages (a thread's own values, a
+64-lane tree plus 4 wavefronts, then at most 1024 workgroups), so its relative
+error is at most (n / (256 nwg) + 1100) 2^-53, below 2e-13 for the sizes here.
+Planning: the GPU's planes equal the oracle planner's on the GPU's tables (the
+integer decision taken on the same inputs), the reconstruction equals the
+oracle's bit for bit, and the coefficients' L2 error is within the tolerance."""
+import numpy as np
+import pytest
+
+import workloads
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 31, 1000, 65536 + 17, 1 << 20, 3_000_001]
+
+
+@pytest.fixture(scope="module")
+def mdr():
+    import paper_2505_00227_amd as m
+    return m
+
+
+def _setup(mdr, orc, dtype, B, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    xs = [(rng.laplace(0, 2.0 ** -l, n)).astype(dtype) for l, n in enumerate(SIZES)]
+    ctx = mdr.Context(0)
+    dev = [torch.from_numpy(x).cuda() for x in xs]
+    r = mdr.refactor(ctx, dev, B)
+    return ctx, xs, dev, r, orc.refactor(xs, B)
+
+
+@pytest.mark.parametrize("dtype,B", [(np.float32, 32), (np.float64, 64), (np.float32, 20)])
+def test_tables_match_oracle_and_repeat(mdr, orc, dtype, B):
+    say("l2 tables", np.dtype(dtype).name, B)
+    ctx, xs, dev, r, olv = _setup(mdr, orc, dtype, B, 21)
+    with pytest.raises(mdr.MdrError):
+        r.l2(0)
+    r.l2_table(dev)
+    first = [r.l2(l) for l in range(len(xs))]
+    for l, (x, lv) in enumerate(zip(xs, olv)):
+        want = orc.l2_table(x, lv)
+        got = np.array(first[l])
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=0, err_msg="level %d" % l)
+    r.l2_table(dev)
+    assert [r.l2(l) for l in range(len(xs))] == first  # fixed summation order
+    r.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype,B", [(np.float32, 32), (np.float64, 64)])
+def test_l2_retrieval_matches_the_oracle_planner(mdr, orc, dtype, B):
+    import torch
+    ctx, xs, dev, r, olv = _setup(mdr, orc, dtype, B, 22)
+    rt = mdr.Retriever(ctx, r)
+    outs = [torch.empty_like(t) for t in dev]
+    with pytest.raises(mdr.MdrError):
+        rt.retrieve_l2(1.0, outs)
+    r.l2_table(dev)
+    tables = [r.l2(l) for l in range(len(xs))]
+    norm = float(np.sqrt(sum(t[0] for t in tables)))
+    fresh = mdr.Retriever(ctx, r)
+    for rel in (1e-1, 1e-2, 1e-4, 1e-7):
+        tol = rel * norm
+        say("l2 retrieve", np.dtype(dtype).name, rel)
+        k_before = rt.planes()
+        rt.retrieve_l2(tol, outs)                   # incremental, from the previous tolerance
+        assert rt.planes() == orc.plan_l2(olv, tables, tol, k_in=k_before)[0]
+        k, bound2 = orc.plan_l2(olv, tables, tol)
+        info2 = fresh.retrieve_l2(tol, outs)        # fresh
+        fresh_k = fresh.planes()
+        assert fresh_k == k
+        assert info2["bound"] == pytest.approx(np.sqrt(bound2), rel=1e-15) and info2["met"] == 1
+        want = orc.retrieve(olv, fresh_k)
+        err2 = 0.0
+        for o, w, x in zip(outs, want, xs):
+            got = o.cpu().numpy()
+            assert got.tobytes() == w.tobytes()
+            d = x.astype(np.float64) - got.astype(np.float64)
+            err2 += float(np.sum(d * d))
+        assert np.sqrt(err2) <= tol * (1 + 1e-9)
+        fresh.close()
+        fresh = mdr.Retriever(ctx, r)
+    fresh.close()
+    rt.close()
+    r.close()
+    ctx.close()
+
+
+def test_l2_table_argument_checks(mdr, orc):
+    import torch
+    ctx, xs, dev, r, olv = _setup(mdr, orc, np.float32, 32, 23)
+    with pytest.raises(mdr.MdrError):
+        r.l2_table(dev[:-1])                                   # level count
+    with pytest.raises(mdr.MdrError):
+        r.l2_table(dev[:-1] + [dev[-1][:-1].contiguous()])     # a size
+    blob = r.serialize()
+    r2 = mdr.Refactored.deserialize(ctx, blob)
+    with pytest.raises(mdr.MdrError):
+        r2.l2(0)                                               # not serialized
+    r2.close()
+    r.close()
+    ctx.close()
