@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import statistics
 import sys
@@ -575,6 +576,24 @@ def bench_multilevel(args):
         row["path_step_ms"] = statistics.median(ts) * 1e3
         row["path_gbps"] = n * s / statistics.median(ts) / 1e9
         row["path_final_max_err_rel"] = worst / rng_u
+        # squared-L2 tables of the 9 levels (the MDR L2 option) and one L2 retrieval
+        r = mdr.refactor(ctx, levels, B)
+        tl = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r.l2_table(levels)          # waits for its stream
+            tl.append(time.perf_counter() - t0)
+        row["l2_table_ms"] = statistics.median(tl) * 1e3
+        row["l2_table_gbps"] = n * s / statistics.median(tl) / 1e9
+        norm = math.sqrt(sum(r.l2(l)[0] for l in range(len(sizes))))
+        rt = mdr.Retriever(ctx, r)
+        info = rt.retrieve_l2(1e-4 * norm, outs)
+        torch.cuda.synchronize()
+        row["l2_retrieve_1e-4_planes"] = rt.planes()
+        row["l2_retrieve_1e-4_bound_rel"] = info["bound"] / norm
+        rt.close()
+        r.close()
         ctx.close()
         table[name] = row
         progress("multilevel", name, row)
