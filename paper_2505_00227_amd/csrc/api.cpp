@@ -894,13 +894,13 @@ mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_
                                 static_cast<double*>(part.p), static_cast<double*>(out.p) + (size_t)l * (B + 1), s));
         // the next level reuses the partial sums: keep the launches in stream order
     }
-    for (uint32_t l = 0; l < nlevels; ++l)
-        if (levels[l].n)
-            MDR_HIP(hipMemcpyAsync(host.data() + (size_t)l * (B + 1), static_cast<double*>(out.p) + (size_t)l * (B + 1),
-                                   (B + 1) * 8, hipMemcpyDeviceToHost, s));
+    // one copy of every level's table (a copy to pageable memory costs a staging round trip each)
+    if (nmax) MDR_HIP(hipMemcpyAsync(host.data(), out.p, host.size() * 8, hipMemcpyDeviceToHost, s));
     MDR_HIP(hipStreamSynchronize(s));
-    for (uint32_t l = 0; l < nlevels; ++l)
+    for (uint32_t l = 0; l < nlevels; ++l) {
+        if (levels[l].n == 0) std::fill(host.begin() + (size_t)l * (B + 1), host.begin() + (size_t)(l + 1) * (B + 1), 0.0);
         r->levels[l].E2.assign(host.begin() + (size_t)l * (B + 1), host.begin() + (size_t)(l + 1) * (B + 1));
+    }
     return MDR_OK;
 }
 
