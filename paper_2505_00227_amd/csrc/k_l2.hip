@@ -19,41 +19,46 @@ namespace {
 
 constexpr uint32_t kL2 = 256;  // threads per workgroup
 
-template <typename T, int KMAX>
+// table entries KLO..KHI (and <= B) of every workgroup's partial row; f64
+// tables run as two launches so that a thread holds at most 33 accumulators
+template <typename T, int KLO, int KHI>
 __global__ __launch_bounds__(kL2) void k_l2_partial(const T* __restrict__ x, uint64_t n, int e, uint32_t B,
                                                     double* __restrict__ part)
 {
 #pragma clang fp contract(off)
-    __shared__ double red[kL2 / 64][KMAX + 1];
-    double acc[KMAX + 1];
+    constexpr int KN = KHI - KLO + 1;
+    __shared__ double red[kL2 / 64][KN];
+    double acc[KN];
 #pragma unroll
-    for (int k = 0; k <= KMAX; ++k) acc[k] = 0.0;
+    for (int j = 0; j < KN; ++j) acc[j] = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * kL2;
     for (uint64_t i = (uint64_t)blockIdx.x * kL2 + threadIdx.x; i < n; i += stride) {
         const double a = std::fabs((double)x[i]);
 #pragma unroll
-        for (int k = 0; k <= KMAX; ++k) {
+        for (int j = 0; j < KN; ++j) {
+            const int k = KLO + j;
             if (k <= (int)B) {
                 // exact power-of-two scalings (a scaled value below 1 may round, its floor is 0 either way)
                 const double r = a - std::ldexp(std::floor(std::ldexp(a, k - e)), e - k);
-                acc[k] += r * r;
+                acc[j] += r * r;
             }
         }
     }
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k <= KMAX; ++k) {
-        double v = acc[k];
+    for (int j = 0; j < KN; ++j) {
+        double v = acc[j];
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == 0) red[wave][k] = v;
+        if (lane == 0) red[wave][j] = v;
     }
     __syncthreads();
-    if (threadIdx.x <= B) {
+    const uint32_t k = KLO + threadIdx.x;
+    if (threadIdx.x < (uint32_t)KN && k <= B) {
         double v = 0.0;
 #pragma unroll
         for (uint32_t w = 0; w < kL2 / 64; ++w) v += red[w][threadIdx.x];
-        part[(uint64_t)blockIdx.x * (B + 1) + threadIdx.x] = v;
+        part[(uint64_t)blockIdx.x * (B + 1) + k] = v;
     }
 }
 
@@ -78,12 +83,16 @@ hipError_t launch_l2_table(bool f64, const void* x, uint64_t n, int e, uint32_t 
                            hipStream_t s)
 {
     const uint32_t nwg = l2_table_workgroups(n);
-    if (f64)
-        hipLaunchKernelGGL((k_l2_partial<double, 64>), dim3(nwg), dim3(kL2), 0, s, static_cast<const double*>(x), n,
+    if (f64) {
+        hipLaunchKernelGGL((k_l2_partial<double, 0, 32>), dim3(nwg), dim3(kL2), 0, s, static_cast<const double*>(x),
+                           n, e, B, part);
+        if (B > 32)
+            hipLaunchKernelGGL((k_l2_partial<double, 33, 64>), dim3(nwg), dim3(kL2), 0, s,
+                               static_cast<const double*>(x), n, e, B, part);
+    } else {
+        hipLaunchKernelGGL((k_l2_partial<float, 0, 32>), dim3(nwg), dim3(kL2), 0, s, static_cast<const float*>(x), n,
                            e, B, part);
-    else
-        hipLaunchKernelGGL((k_l2_partial<float, 32>), dim3(nwg), dim3(kL2), 0, s, static_cast<const float*>(x), n,
-                           e, B, part);
+    }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(128), 0, s, part, nwg, B, out);
