@@ -141,3 +141,66 @@ def test_qoi_estimators_guarantee(orc, estimator, c):
         if estimator == "ma":
             same = orc.retrieve_qoi_vtotal(vars3, tau, c=math.inf, estimator="mape")
             assert same[1] == ks and same[2] == tprime and same[4] == it
+
+
+def _ones_level(orc, vals):
+    """One level of float32 values, 8 planes, one plane per group."""
+    return orc.refactor([np.array(vals, np.float32)], 8, orc.Params(group_planes=1))
+
+
+def test_qoi_initial_bound_and_mape_step_by_hand(orc):
+    """Alg. 3 traced by hand on three variables whose error tables are known in
+    closed form.  Each variable is one level of two values +-a, a = 1 - 2^-8
+    (eight ones below the binary point), so e = 0 and after k planes the tail
+    is E[k] = 2^-k - 2^-8 and the value held is 1 - 2^-k.
+
+    Initial bound (Sec. 5.2): eps_c = (tau / Q_max) * range_c with
+    Q_max = sum_c max|v_c|^2 = 3a^2 and range_c = 2a, so eps = 2 tau / (3a);
+    at tau = 1/16 that is 0.041830...; E[4] = 15/256 is above it and
+    E[5] = 7/256 below, so every variable starts at k = 5 (the reading
+    eps = tau would give k = 4; tau / Q_max or tau * max|v| / Q_max, k = 6).
+
+    First estimate: tau' = 3 * E[5] * (2 (1 - 2^-5) + E[5]) = 10563/65536
+    (exact in binary), times the 1 + 2^-40 rounding cover.  p = tau'/tau =
+    2.579 > c = 2, so MAPE sets eps <- E[5] / p = 0.010604: E[6] = 3/256 is
+    above it, E[7] = 1/256 below, so k = 7 and tau' = 3 * 509 / 65536 <= tau:
+    done after two estimates.  Dividing by p is what reaches k = 7: eps * p
+    adds no plane and neither does skipping the step (p < c read the other way
+    round); both fall back to one more plane (k = 6, tau' = 4563/65536 > tau)
+    and need a third estimate, which is what MA (c = infinity) does."""
+    a = 1.0 - 2.0 ** -8
+    vars3 = [_ones_level(orc, [a, -a]) for _ in range(3)]
+    for lv in vars3:
+        assert list(lv[0].E) == [a] + [2.0 ** -k - 2.0 ** -8 for k in range(1, 9)]
+    tau = 1.0 / 16
+    for e in orc.qoi_initial_eps(vars3, tau):
+        assert abs(e - 2.0 * tau / (3.0 * a)) <= 4e-16 * e
+    inflate = 1.0 + 2.0 ** -40
+    vals, ks, tp, met, it = orc.retrieve_qoi_vtotal(vars3, tau, c=2.0, max_iter=1)
+    assert ks == [[5], [5], [5]] and it == 1 and not met
+    assert tp == (10563.0 / 65536.0) * inflate
+    vals, ks, tp, met, it = orc.retrieve_qoi_vtotal(vars3, tau, c=2.0)
+    assert ks == [[7], [7], [7]] and it == 2 and met
+    assert tp == (3.0 * 509.0 / 65536.0) * inflate
+    # minimal augmentation takes one plane per round: 5 -> 6 -> 7
+    vals, ks, tp, met, it = orc.retrieve_qoi_vtotal(vars3, tau, c=math.inf)
+    assert ks == [[7], [7], [7]] and it == 3 and met
+    vals, ks, tp, met, it = orc.retrieve_qoi_vtotal(vars3, tau, c=math.inf, max_iter=2)
+    assert ks == [[6], [6], [6]] and tp == (4563.0 / 65536.0) * inflate
+
+
+def test_qoi_initial_bound_scales_with_each_range(orc):
+    """Uneven variables: +-a, {a/2, 0} and +-a/4 (a = 1 - 2^-8; exponents 0,
+    -1, -2, so E_x[k] = 2^-k - 2^-8, E_y[k] = 2^-(k+1) - 2^-9,
+    E_z[k] = 2^-(k+2) - 2^-10).  Q_max = a^2 (1 + 1/4 + 1/16) = 21 a^2 / 16 and
+    the ranges are 2a, a/2, a/2, so at tau = 1/16 the initial bounds are
+    2/(21a) = 0.0956 and 1/(42a) = 0.0239 (twice).  The smallest k under them:
+    x: E[3] = 0.121 > 0.0956 >= E[4] = 0.0586, so 4; y: E[4] = 0.0293 > 0.0239
+    >= E[5] = 0.0137, so 5; z: E[3] = 0.0303 > 0.0239 >= E[4] = 0.0146, so 4."""
+    a = 1.0 - 2.0 ** -8
+    vars3 = [_ones_level(orc, [a, -a]), _ones_level(orc, [a / 2, 0.0]), _ones_level(orc, [-a / 4, a / 4])]
+    eps = orc.qoi_initial_eps(vars3, 1.0 / 16)
+    for got, want in zip(eps, [2.0 / (21.0 * a), 1.0 / (42.0 * a), 1.0 / (42.0 * a)]):
+        assert abs(got - want) <= 4e-16 * want
+    vals, ks, tp, met, it = orc.retrieve_qoi_vtotal(vars3, 1.0 / 16, c=2.0, max_iter=1)
+    assert ks == [[4], [5], [4]]

@@ -157,3 +157,34 @@ def serving_requests(seed: int = 58, n: int = 10000, nfields: int = 8, rate: flo
         reqs.append({"id": i, "t": float(t[i]), "kind": str(kinds[i]), "field": int(fields[i]),
                      "tol": float(tols[i]), "parent": parent})
     return reqs
+
+
+def ones_runs_level(seed: int, n: int, dtype=np.float32):
+    """Stress input for the exact error table: values whose significands are
+    runs of ones (2^a - 1) at varied positions, with run lengths that grow along
+    the array, so that every cut's largest tail keeps being raised by later
+    values; a third of the values are Laplace(0, 1) noise."""
+    rng = np.random.default_rng(seed)
+    p = 24 if dtype == np.float32 else 53
+    frac = np.arange(n, dtype=np.float64) / max(n, 1)
+    a = np.clip(1 + np.floor(frac * (p - 1)) + rng.integers(-2, 3, n), 1, p).astype(np.int64)
+    sig = np.ldexp(1.0, a) - 1.0                      # exact: a <= 53 ones
+    q = rng.integers(-40, 2, n) - a                  # the run's top bit below 2^2
+    x = np.ldexp(sig, q) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    noise = rng.random(n) < 1.0 / 3.0
+    x[noise] = rng.laplace(0.0, 1.0, int(noise.sum()))
+    return x.astype(dtype)
+
+
+def piecewise_constant_level(seed: int, n: int, dtype=np.float32):
+    """Stress input for run-length statistics: constant stretches of 1..40000
+    values (zero, or one Laplace draw), so that equal plane words run across
+    many encoder tiles and workgroup ranges."""
+    rng = np.random.default_rng(seed)
+    out = np.empty(n, np.float64)
+    i = 0
+    while i < n:
+        run = int(rng.integers(1, 40001))
+        out[i:i + run] = 0.0 if rng.random() < 0.3 else rng.laplace(0.0, 1.0)
+        i += run
+    return out.astype(dtype)
