@@ -439,6 +439,19 @@ mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t 
 mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, void* stream);
 mdr_status mdr_refactored_l2(const mdr_refactored* r, uint32_t level, double* E2);
 
+/* mdr_l2_table_noalloc: mdr_l2_table for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, tables and errors, computed by the same kernels (bit-identical
+ * tables); the partial sums and tables live in a fixed scratch array of the
+ * library (552,960 bytes per device, resolved once per device by
+ * mdr_context_create and held until the process ends) instead of pool memory,
+ * and no hipMalloc, hipFree or allocating library routine is called.
+ * nlevels above 64: MDR_ERR_UNSUPPORTED.  Every call on one device shares that
+ * scratch, so calls that overlap on one device (other host threads, or other
+ * streams before this call's wait returns) race and must be serialized by the
+ * caller. */
+mdr_status mdr_l2_table_noalloc(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, void* stream);
+
 /* ---- Multilevel decomposition (the coefficient levels of Sec. 2/3) ---------
  * The method's input is the coefficient levels of a multilevel decomposition
  * that the paper takes from earlier work without spelling it out.  Reading

@@ -145,6 +145,7 @@ _SIGS = {
     "mdr_retrieve_qoi_vtotal_with": ([_vp, _vp, _vp, C.c_int, C.c_double, _P(mdr_qoi_params), _P(_vp),
                                       _P(_vp), _P(_vp), _vp, _P(mdr_qoi_info)], C.c_int),
     "mdr_l2_table": ([_vp, _P(mdr_level_view), _u32, _vp], C.c_int),
+    "mdr_l2_table_noalloc": ([_vp, _P(mdr_level_view), _u32, _vp], C.c_int),
     "mdr_refactored_l2": ([_vp, _u32, _P(C.c_double)], C.c_int),
     "mdr_level_sizes": ([_u64, _u64, _u64, _u32, _P(_u64)], C.c_int),
     "mdr_decompose": ([C.c_int, _vp, _u64, _u64, _u64, _u32, _vp, _vp], C.c_int),
@@ -299,6 +300,11 @@ class Refactored:
         """mdr_l2_table: squared-L2 per-plane tables from the levels this was refactored from."""
         views, _ = _views(levels, self.dtype)
         _check(_lib.mdr_l2_table(self.handle, views, len(levels), _stream_ptr(stream)))
+
+    def l2_table_noalloc(self, levels, stream=None) -> None:
+        """mdr_l2_table_noalloc: the same tables through the library's fixed scratch (no device allocation)."""
+        views, _ = _views(levels, self.dtype)
+        _check(_lib.mdr_l2_table_noalloc(self.handle, views, len(levels), _stream_ptr(stream)))
 
     def l2(self, level: int):
         """mdr_refactored_l2: the level's squared-L2 table (nplanes + 1 values)."""

@@ -273,6 +273,7 @@ mdr_status mdr_context_create(int hip_device, mdr_context** out)
     if (hip_device < 0 || hip_device >= count)
         return fail(MDR_ERR_INVALID_ARG, "no such HIP device");
     MDR_HIP(hipSetDevice(hip_device));
+    MDR_HIP(l2_scratch_init(hip_device));  // the fixed scratch of mdr_l2_table_noalloc, on this device
     auto* c = new mdr_context();
     c->device = hip_device;
     c->pool = std::make_shared<DevicePool>(kPoolCacheBytes);
@@ -862,15 +863,15 @@ mdr_status mdr_recompose(mdr_dtype dtype, const void* coeffs, uint64_t n0, uint6
 
 // ---- squared-L2 per-plane table ---------------------------------------------
 
-extern "C" {
+namespace {
 
-mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, void* stream)
+// argument checks shared by both table entry points; nmax = the largest level
+mdr_status l2_check(const mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, uint64_t& nmax)
 {
-    g_err.clear();
     if (!r || (nlevels && !levels)) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
     if (nlevels != r->levels.size()) return fail(MDR_ERR_INVALID_ARG, "level count differs from the refactored one");
     const uint64_t w = r->dtype == MDR_F64 ? 8 : 4;
-    uint64_t nmax = 0;
+    nmax = 0;
     for (uint32_t l = 0; l < nlevels; ++l) {
         if (levels[l].n != r->levels[l].n) return fail(MDR_ERR_INVALID_ARG, "level sizes differ from the refactored ones");
         if (levels[l].n == 0) continue;
@@ -881,27 +882,75 @@ mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_
             return fail(MDR_ERR_INVALID_ARG, "level data must be device memory holding n values");
         nmax = std::max(nmax, levels[l].n);
     }
+    return MDR_OK;
+}
+
+// every level's table into `out` (nlevels * (B + 1) doubles, device) through
+// `part` (partial rows, device), then one copy to `host`; waits for the stream,
+// also when a launch fails, so that no queued kernel outlives the buffers
+mdr_status l2_run(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, uint64_t nmax, double* part,
+                  double* out, double* host, hipStream_t s)
+{
+    const uint32_t B = r->B;
+    hipError_t err = hipSuccess;
+    const char* what = nullptr;
+    for (uint32_t l = 0; l < nlevels && err == hipSuccess; ++l) {
+        if (levels[l].n == 0) continue;
+        // the next level reuses the partial sums: the launches stay in stream order
+        err = launch_l2_table(r->dtype == MDR_F64, levels[l].data, levels[l].n, r->levels[l].e, B, part,
+                              out + (size_t)l * (B + 1), s);
+        what = "launch_l2_table";
+    }
+    // one copy of every level's table (a copy to pageable memory costs a staging round trip each)
+    if (err == hipSuccess && nmax) {
+        err = hipMemcpyAsync(host, out, (size_t)nlevels * (B + 1) * 8, hipMemcpyDeviceToHost, s);
+        what = "hipMemcpyAsync(tables)";
+    }
+    const hipError_t es = hipStreamSynchronize(s);
+    if (err != hipSuccess) return hip_fail(err, what);
+    if (es != hipSuccess) return hip_fail(es, "hipStreamSynchronize");
+    for (uint32_t l = 0; l < nlevels; ++l) {
+        double* t = host + (size_t)l * (B + 1);
+        if (levels[l].n == 0) std::fill(t, t + B + 1, 0.0);
+        r->levels[l].E2.assign(t, t + B + 1);
+    }
+    return MDR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, void* stream)
+{
+    g_err.clear();
+    uint64_t nmax = 0;
+    mdr_status st = l2_check(r, levels, nlevels, nmax);
+    if (st) return st;
     const uint32_t B = r->B;
     MDR_HIP(hipSetDevice(r->ctx->device));
-    const hipStream_t s = static_cast<hipStream_t>(stream);
     PoolBuf part, out;
     MDR_HIP(part.alloc(r->ctx->pool, (uint64_t)l2_table_workgroups(nmax) * (B + 1) * 8));
     MDR_HIP(out.alloc(r->ctx->pool, (uint64_t)nlevels * (B + 1) * 8));
     std::vector<double> host((size_t)nlevels * (B + 1), 0.0);
-    for (uint32_t l = 0; l < nlevels; ++l) {
-        if (levels[l].n == 0) continue;
-        MDR_HIP(launch_l2_table(r->dtype == MDR_F64, levels[l].data, levels[l].n, r->levels[l].e, B,
-                                static_cast<double*>(part.p), static_cast<double*>(out.p) + (size_t)l * (B + 1), s));
-        // the next level reuses the partial sums: keep the launches in stream order
-    }
-    // one copy of every level's table (a copy to pageable memory costs a staging round trip each)
-    if (nmax) MDR_HIP(hipMemcpyAsync(host.data(), out.p, host.size() * 8, hipMemcpyDeviceToHost, s));
-    MDR_HIP(hipStreamSynchronize(s));
-    for (uint32_t l = 0; l < nlevels; ++l) {
-        if (levels[l].n == 0) std::fill(host.begin() + (size_t)l * (B + 1), host.begin() + (size_t)(l + 1) * (B + 1), 0.0);
-        r->levels[l].E2.assign(host.begin() + (size_t)l * (B + 1), host.begin() + (size_t)(l + 1) * (B + 1));
-    }
-    return MDR_OK;
+    return l2_run(r, levels, nlevels, nmax, static_cast<double*>(part.p), static_cast<double*>(out.p), host.data(),
+                  static_cast<hipStream_t>(stream));
+}
+
+mdr_status mdr_l2_table_noalloc(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlevels, void* stream)
+{
+    g_err.clear();
+    uint64_t nmax = 0;
+    mdr_status st = l2_check(r, levels, nlevels, nmax);
+    if (st) return st;
+    if (nlevels > kL2NoAllocLevels)
+        return fail(MDR_ERR_UNSUPPORTED, "mdr_l2_table_noalloc takes at most " + std::to_string(kL2NoAllocLevels) +
+                                             " levels (its fixed scratch); use mdr_l2_table");
+    MDR_HIP(hipSetDevice(r->ctx->device));
+    double *part = nullptr, *out = nullptr;
+    MDR_HIP(l2_scratch(r->ctx->device, &part, &out));
+    double host[kL2NoAllocLevels * 65];  // nlevels * (B + 1) <= 64 * 65
+    return l2_run(r, levels, nlevels, nmax, part, out, host, static_cast<hipStream_t>(stream));
 }
 
 mdr_status mdr_refactored_l2(const mdr_refactored* r, uint32_t level, double* E2)

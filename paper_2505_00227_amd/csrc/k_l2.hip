@@ -11,6 +11,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "mdr_internal.hpp"
 
@@ -71,7 +72,54 @@ __global__ void k_l2_final(const double* __restrict__ part, uint32_t nwg, uint32
     out[k] = v;
 }
 
+// Fixed scratch of mdr_l2_table_noalloc: the partial rows of at most 1024
+// workgroups, then the tables of at most kL2NoAllocLevels levels, 65 entries
+// (B + 1 for B <= 64) each: 552,960 bytes per device, held until the process
+// ends.  Host code never passes this name to a kernel: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, per device.
+constexpr uint64_t kL2PartDoubles = 1024ull * 65;
+constexpr uint64_t kL2ScratchDoubles = kL2PartDoubles + (uint64_t)kL2NoAllocLevels * 65;
+__device__ __align__(256) double scratch[kL2ScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
+
+hipError_t l2_scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) {
+        e = hipSetDevice(device);
+        if (e != hipSuccess) return e;
+    }
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+    return hipSuccess;
+}
+
+hipError_t l2_scratch(int device, double** part, double** out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    double* p;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        p = g_scratch_ptr[device];
+    }
+    if (!p) return hipErrorNotInitialized;
+    *part = p;
+    *out = p + kL2PartDoubles;
+    return hipSuccess;
+}
 
 uint32_t l2_table_workgroups(uint64_t n)
 {
