@@ -138,6 +138,38 @@ uint64_t dc_bytes(const HostChunk& hc)
     return b;
 }
 
+// Byte spans of the units that planes k (per level) need, in the rows region
+// (direct-copy units) and the payload blob (coded units), each list ascending
+// and merged: the retrieval uploads only these (Sec. 5.1's retrieval moves just
+// the precision segments the bound needs).
+void fetch_spans(const mdr_pipeline* p, const HostChunk& hc, const std::vector<uint32_t>& k,
+                 std::vector<std::pair<uint64_t, uint64_t>>& rows, std::vector<std::pair<uint64_t, uint64_t>>& pay)
+{
+    rows.clear();
+    pay.clear();
+    for (uint32_t l = 0; l < p->nlevels; ++l) {
+        if (k[l] == 0) continue;
+        for (uint32_t s = 0; s <= p->B; ++s) {
+            const UnitRec& u = hc.levels[l].units[s];
+            if (u.method == MDR_PLACEHOLDER || u.bytes == 0) continue;
+            if (s > 0 && s - 1 >= k[l]) break;  // the group's first plane is past k: so are the rest
+            auto& v = u.method == MDR_DC ? rows : pay;
+            v.emplace_back(hc.unit_off[(uint64_t)l * kMaxRows + s], u.bytes);
+        }
+    }
+    for (auto* v : {&rows, &pay}) {
+        std::sort(v->begin(), v->end());
+        size_t n = 0;
+        for (size_t i = 0; i < v->size(); ++i) {
+            if (n && (*v)[n - 1].first + (*v)[n - 1].second == (*v)[i].first)
+                (*v)[n - 1].second += (*v)[i].second;
+            else
+                (*v)[n++] = (*v)[i];
+        }
+        v->resize(n);
+    }
+}
+
 double elapsed(hipEvent_t a, hipEvent_t b)
 {
     float ms = 0.f;
@@ -387,19 +419,36 @@ mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, vo
         }
     } cleanup{rts};
     uint64_t h2d_bytes = 0, d2h_bytes = 0, fetched = 0;
+    // every chunk's plan first, on the host from its error tables: the uploads
+    // carry only the units the plan reads
+    std::vector<std::vector<uint32_t>> plans(N);
+    for (uint32_t c = 0; c < N; ++c) {
+        const int s = c & 1;
+        views[c] = device_view(p, *p->chunks[c], static_cast<uint8_t*>(p->dev_rows[s].p),
+                               static_cast<uint8_t*>(p->dev_pay[s].p));
+        plans[c].assign(p->nlevels, 0);
+        plan_to(views[c].get(), tol_abs, plans[c]);
+    }
+    std::vector<std::pair<uint64_t, uint64_t>> span_rows, span_pay;
     auto h2d = [&](uint32_t c) -> mdr_status {
         const HostChunk& hc = *p->chunks[c];
         const int s = c & 1;
         if (c >= 2) MDR_HIP(hipStreamWaitEvent(A, cmp_b[c - 2], 0));  // slot free once chunk c-2 is rebuilt
         MDR_HIP(hipEventRecord(h2d_a[c], A));
-        for (const auto& d : hc.dc)
+        fetch_spans(p, hc, plans[c], span_rows, span_pay);
+        for (const auto& d : span_rows) {
             MDR_HIP(hipMemcpyAsync(static_cast<uint8_t*>(p->dev_rows[s].p) + d.first,
                                    static_cast<const uint8_t*>(hc.rows) + d.first, d.second,
                                    hipMemcpyHostToDevice, A));
-        if (hc.pay_bytes)
-            MDR_HIP(hipMemcpyAsync(p->dev_pay[s].p, hc.pay, hc.pay_bytes, hipMemcpyHostToDevice, A));
+            h2d_bytes += d.second;
+        }
+        for (const auto& d : span_pay) {
+            MDR_HIP(hipMemcpyAsync(static_cast<uint8_t*>(p->dev_pay[s].p) + d.first,
+                                   static_cast<const uint8_t*>(hc.pay) + d.first, d.second,
+                                   hipMemcpyHostToDevice, A));
+            h2d_bytes += d.second;
+        }
         MDR_HIP(hipEventRecord(h2d_b[c], A));
-        h2d_bytes += dc_bytes(hc) + hc.pay_bytes;
         return MDR_OK;
     };
     mdr_status st = h2d(0);
@@ -410,8 +459,6 @@ mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, vo
             if (st) return st;
         }
         const int s = c & 1;
-        const HostChunk& hc = *p->chunks[c];
-        views[c] = device_view(p, hc, static_cast<uint8_t*>(p->dev_rows[s].p), static_cast<uint8_t*>(p->dev_pay[s].p));
         rts[c] = new mdr_retriever();
         rts[c]->ctx = p->ctx;
         rts[c]->r = views[c].get();
@@ -420,9 +467,8 @@ mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, vo
         for (auto& d : rts[c]->dec) d.resize(kMaxRows);
         RetrieveTask t;
         t.rt = rts[c];
-        t.knew = rts[c]->k;
+        t.knew = plans[c];
         t.tol_abs = tol_abs;
-        plan_to(views[c].get(), tol_abs, t.knew);
         std::vector<void*> lo(p->nlevels);
         uint64_t o = 0;
         for (uint32_t l = 0; l < p->nlevels; ++l) {

@@ -1,7 +1,9 @@
 """GPU parity of the chunked H2D / refactor / D2H pipeline: every chunk's
 refactored container equals the oracle's for that chunk alone, and retrieval
 through the pipeline (all planes, and a tolerance planned per chunk) writes to
-host memory exactly the oracle's reconstructions; with and without overlap."""
+host memory exactly the oracle's reconstructions; with and without overlap.
+The retrieval uploads only the units each chunk's plan needs (its sign unit
+and the groups below its planes), byte for byte what the oracle's plan reads."""
 import numpy as np
 import pytest
 
@@ -23,6 +25,19 @@ def ctx(mdr):
     c = mdr.Context(0)
     yield c
     c.close()
+
+
+def _planned_unit_bytes(levels, k):
+    """Bytes of the units that planes k need: each level's sign unit and every
+    group whose first plane is below k (placeholders hold 0 bytes)."""
+    total = 0
+    for lv, kl in zip(levels, k):
+        if kl == 0:
+            continue
+        total += len(lv.streams[0][1])
+        for first in range(0, kl, lv.m):
+            total += len(lv.streams[1 + first][1])
+    return total
 
 
 @pytest.mark.parametrize("dtype,B", [(np.float64, 64), (np.float64, 40), (np.float32, 32)])
@@ -52,13 +67,17 @@ def test_pipeline_matches_oracle_per_chunk(mdr, ctx, dtype, B):
         # pageable output (copies); both start poisoned
         for pinned in (True, False):
             dst = out if pinned else torch.empty(flat.size, dtype=tdt)
-            for rel in (0.0, 1e-4):
+            for rel in (0.0, 1e-4, 1e-2):
                 dst.fill_(float("nan"))
-                pipe.retrieve(rel, dst, relative=True, overlap=overlap)
+                info = pipe.retrieve(rel, dst, relative=True, overlap=overlap)
                 got = dst.numpy()
                 o = 0
+                want_h2d = 0
                 for c in range(nchunks):
                     vals, k, bound, met = oracle.retrieve_to(orc[c], rel * (hi - lo), relative=False)
                     ref = np.concatenate(vals)
                     assert_same_bits(got[o:o + ref.size], ref, ("chunk", c, "rel", rel, "pinned", pinned))
                     o += ref.size
+                    want_h2d += _planned_unit_bytes(orc[c], k)
+                # progressive fetch: exactly the sign unit and the planned groups crossed PCIe
+                assert info["h2d_bytes"] == want_h2d, (rel, info["h2d_bytes"], want_h2d)
