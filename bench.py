@@ -1,13 +1,17 @@
 """Benchmark of the refactor / progressive-retrieve hot path on one MI355X.
 
-Default workload: a 512^3 float32 field as 9 coefficient levels (2^27 values,
-512 MiB), 32 planes, groups of 4 planes.  One step = refactor of every level +
-progressive (incremental) retrieval to relative L-inf bounds 1e-1 ... 1e-6,
-each writing the full reconstruction.  Inputs are resident in HBM before the
-timed region.  Prints one JSON line.
+Default workload: the 1024^3 float64 field (8 GiB) as 32 slabs of
+32x1024x1024 values, each its own 9-level sub-domain, 64 planes, groups of 4
+planes, resident in HBM before the timed region.  One step = one batched
+refactor pass over the 32 slabs + one batched retrieval of every plane of the
+32 slabs, each writing the full reconstruction.  Prints one JSON line; the
+host-to-host chunked pipeline, per-slab retrieval latencies (cold), and short
+runs of the 512^3 float32 field, the 256-variable batch and the serving loop
+ride along as extra keys.
 
 value = original bytes moved through the path per second: the field once for
-refactor plus once per retrieval (the paper's GB/s-of-original-data convention).
+refactor plus once for the retrieval (the paper's GB/s-of-original-data
+convention).
 """
 from __future__ import annotations
 
@@ -23,29 +27,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-ENCODER_SRC = os.path.join(ROOT, "paper_2505_00227_amd", "csrc", "k_refactor.hip")
-TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_encode_field512_traffic.md")
+CSRC = os.path.join(ROOT, "paper_2505_00227_amd", "csrc")
+# kernel -> the source file it is built from (a traffic figure is valid only
+# for the source it was measured on)
+KERNEL_SRC = {"k_encode": "k_refactor.hip", "k_stats": "k_refactor.hip", "k_select": "k_refactor.hip",
+              "k_reconstruct": "k_retrieve.hip", "k_huf_decode": "k_lossless.hip",
+              "lossless": "k_lossless.hip"}
+# stage timed by the library -> kernel it launches
+STAGE_KERNEL = {"encode": "k_encode", "stats": "k_stats", "select": "k_select",
+                "reconstruct": "k_reconstruct", "huf_decode": "k_huf_decode", "lossless": "lossless"}
 
 
-def encoder_hash() -> str:
+def source_hash(kernel: str) -> str:
     import hashlib
-    return hashlib.sha256(open(ENCODER_SRC, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(open(os.path.join(CSRC, KERNEL_SRC[kernel]), "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per step of the encoder from the committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter on a plain copy of
-    known size), or None when the encoder source changed since they were taken."""
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter runs (profiles/<kernel>_<workload>_traffic.md: FETCH_SIZE
+    and WRITE_SIZE, each scaled by the same counter on a plain copy of known
+    size), or None when the kernel's source changed since they were taken."""
+    note = os.path.join(ROOT, "profiles", "%s_%s_traffic.md" % (kernel, workload))
     try:
         vals = {}
-        for line in open(TRAFFIC_NOTE):
+        for line in open(note):
             if line.startswith("machine: "):
                 for kv in line[len("machine: "):].split():
                     k, v = kv.split("=")
                     vals[k] = v
-        if vals.get("source_sha") != encoder_hash():
+        if vals.get("source_sha") != source_hash(kernel):
             return None
-        return float(vals["traffic_bytes_per_step"])
+        return float(vals["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -55,7 +68,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3, 4, 5],
+                    help="3 (default): the 1024^3 float64 field resident in HBM; --pipeline: host to host")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="the 1024^3 float64 field through the chunked host-to-host pipeline only")
     ap.add_argument("--chunks", type=int, default=32, help="chunked workload: 32x1024x1024 f64 slabs")
     ap.add_argument("--serve-requests", type=int, default=10000, help="serving workload: requests per load")
     ap.add_argument("--serve-edge", type=int, default=512, help="serving workload: field edge")
@@ -68,6 +84,10 @@ def parse():
                     help="multilevel decomposition of the 512^3 field, and the field through the whole path")
     ap.add_argument("--ablation", action="store_true",
                     help="encoder-design ablation: 32-bit words <-> 32 planes by each design, 2^20..2^28 words")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: leave out the short runs of the other workloads")
+    ap.add_argument("--no-qoi-estimators", dest="qoi_estimators", action="store_false",
+                    help="serving workload: skip the estimator comparison")
     ap.add_argument("--cpu-sample", type=int, default=1 << 25,
                     help="values of the finest level the oracle baseline refactors")
     return ap.parse_args()
@@ -247,7 +267,7 @@ def bench_batched(args):
         "speedup_batched_vs_per_variable": ss["step_ms"] / sb["step_ms"],
         "tune": tune,
     }
-    print(json.dumps(res))
+    return res
 
 
 def bench_chunked(args):
@@ -343,10 +363,11 @@ def bench_serving(args):
     # value fetched, rounds and time per V_total tolerance (relative to the
     # largest V_total the ranges allow), each from fresh retrievers
     qoi_estimators = {}
-    outs3 = [[torch.empty(n, dtype=torch.float32, device="cuda") for n in level_sizes] for _ in range(3)]
+    outs3 = [] if not args.qoi_estimators else [[torch.empty(n, dtype=torch.float32, device="cuda") for n in level_sizes] for _ in range(3)]
     nvals_field = sum(level_sizes)
-    for name, est, c in (("CP", "cp", 10.0), ("MA", "ma", 10.0), ("MAPE(c=2)", "mape", 2.0),
-                         ("MAPE(c=10)", "mape", 10.0)):
+    estimators = (("CP", "cp", 10.0), ("MA", "ma", 10.0), ("MAPE(c=2)", "mape", 2.0),
+                  ("MAPE(c=10)", "mape", 10.0)) if args.qoi_estimators else ()
+    for name, est, c in estimators:
         rows = {}
         for tol in (1e-1, 5e-1, 1e-2, 5e-2, 1e-3, 5e-3, 1e-4, 5e-4, 1e-5, 5e-5):
             rts = [mdr.Retriever(ctx, fields[i]) for i in range(3)]
@@ -447,7 +468,7 @@ def bench_serving(args):
         "latency_ms": {"p50": main_load["batched"]["p50_ms"], "p99": main_load["batched"]["p99_ms"]},
         "loads": loads,
     }
-    print(json.dumps(res))
+    return res
 
 
 def bench_ablation(args):
@@ -606,33 +627,306 @@ def bench_multilevel(args):
     print(json.dumps(res))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: the path has no multi-GPU component "
-              "(variables and chunks shard independently); use --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.ablation:
-        bench_ablation(args)
-        return
-    if args.multilevel:
-        bench_multilevel(args)
-        return
-    if args.config == 4:
-        bench_batched(args)
-        return
-    if args.config == 5:
-        bench_serving(args)
-        return
-    if args.config == 3:
-        bench_chunked(args)
-        return
+def unit_table(r, B, m):
+    """Per level of a refactored variable: (n, words per plane row, [(method,
+    payload bytes, plane rows)] per unit in stream order, sign unit first)."""
+    out = []
+    for l in range(r.nlevels):
+        n = r.info(l)["n"]
+        nbd = -(-n // 32) if r.dtype == 0 else 2 * -(-n // 64)
+        units = []
+        for s in [-1] + list(range(0, B, m)):
+            _, nb, meth = r.stream(l, s)
+            rows = 1 if s < 0 else min(m, B - s)
+            units.append((meth, nb, rows))
+        out.append((n, nbd, units))
+    return out
+
+
+def kernel_bytes(tables, s, B, m, k_retrieved):
+    """Algorithmic bytes per pass of each kernel: what its job must move.
+
+    k_encode: read every value, write every plane row (sign + B);
+    k_stats: read every value; lossless: read the rows of each coded unit,
+    write its payload; k_huf_decode: read the Huffman payloads of the fetched
+    units, write their rows; k_reconstruct: read the sign row and the k plane
+    rows of each level, write every value."""
+    enc = stats = lossless = huf = rec = 0
+    for t, k in zip(tables, k_retrieved):
+        for (n, nbd, units), kl in zip(t, k):
+            enc += n * s + 4 * (B + 1) * nbd
+            stats += n * s
+            fetched = 1 + -(-kl // m) if kl else 0
+            for i, (meth, nb, rows) in enumerate(units):
+                if meth in (1, 2):
+                    lossless += 4 * rows * nbd + nb
+                if meth == 2 and i < fetched:
+                    huf += nb + 4 * rows * nbd
+            if kl:
+                rec += 4 * (1 + kl) * nbd + n * s
+    return {"k_encode": enc, "k_stats": stats, "lossless": lossless, "k_huf_decode": huf,
+            "k_reconstruct": rec}
+
+
+def path_bytes(tables, s, B, m, k_retrieved):
+    """Algorithmic bytes of the whole path (refactor: values in, every stream
+    out, the error tables; retrieval: the fetched streams in, every value out)."""
+    ref = ret = 0
+    for t, k in zip(tables, k_retrieved):
+        for (n, nbd, units), kl in zip(t, k):
+            coded = sum(nb for _, nb, _ in units)
+            ref += n * s + coded + (B + 1) * s
+            fetched = 1 + -(-kl // m) if kl else 0
+            ret += sum(nb for _, nb, _ in units[:fetched]) + n * s
+    return ref, ret
+
+
+def roofline_from(stages, steps, kbytes, workload):
+    """The step's dominant kernel (most time in the timed region, from HIP
+    events on the library's stream) against the HBM peak."""
+    times = {STAGE_KERNEL[st]: v[0] for st, v in stages.items() if st in STAGE_KERNEL and v[1]}
+    kern = max((k for k in times if k in kbytes), key=times.get)
+    launches = {STAGE_KERNEL[st]: v[1] for st, v in stages.items() if st in STAGE_KERNEL}
+    ms_per_launch = times[kern] / max(1, launches[kern])
+    bytes_per_launch = kbytes[kern] * steps / max(1, launches[kern])
+    achieved = bytes_per_launch / (ms_per_launch / 1e3) / 1e9
+    traffic = measured_traffic(kern, workload)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "kernel": kern, "source_sha": source_hash(kern), "launches_per_step": launches[kern] / steps,
+            "ms_per_launch": ms_per_launch, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "kernel_ms_per_step": {k: v / steps for k, v in times.items()},
+            "kernel_frac": {k: (kbytes[k] * steps / (v / 1e3) / 1e9 / HBM_PEAK_GBS if v else None)
+                            for k, v in times.items() if k in kbytes}}
+
+
+def copy_rate():
+    """Measured device-to-device copy bandwidth (read + write) of 256 MiB: the
+    practical ceiling; the same copy scales the FETCH_SIZE / WRITE_SIZE
+    counters when this run is profiled."""
+    import torch
+    ref = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    ref_copy = ref.clone()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        ref_copy.copy_(ref)
+    ev1.record()
+    torch.cuda.synchronize()
+    return 2 * ref.numel() * 10 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+
+
+def cpu_baseline_slab(levels, B, m):
+    """The oracle as it stands, on the host cores, over one 32x1024x1024 slab of
+    the workload (2^25 float64 values, 9 levels): refactor + retrieval of every
+    plane.  GB/s of original data on the same convention as `value`."""
+    import oracle
+    p = oracle.Params(group_planes=m)
+    t0 = time.perf_counter()
+    lv = oracle.refactor(levels, B, p)
+    vals, k, bound, met = oracle.retrieve_to(lv, 0.0)
+    t = time.perf_counter() - t0
+    nbytes = sum(a.nbytes for a in levels)
+    return {"value": 2 * nbytes / t / 1e9, "unit": "GB/s", "cores": oracle.get_threads(),
+            "kind": "oracle", "seconds": t,
+            "sample": "one 32x1024x1024 slab (2^25 float64 values, 9 levels, 256 MiB): "
+                      "refactor + retrieval of every plane"}
+
+
+def bench_field1024(args):
+    """The 1024^3 float64 field (8 GiB) as 32 slabs of 32x1024x1024, each its
+    own 9-level sub-domain (B = 64, m = 4), resident in HBM: one step = batched
+    refactor of the slabs + batched retrieval of every plane."""
+    import numpy as np
+    import torch
+
+    import paper_2505_00227_amd as mdr
+    import workloads
+
+    B, m, s = 64, 4, 8
+    nch = args.chunks
+    sizes = workloads.chunk_level_sizes()
+    per = sum(sizes)
+    host = torch.empty(per * nch, dtype=torch.float64).pin_memory()
+    hv = host.numpy()
+    for c in range(nch):
+        hv[c * per:(c + 1) * per] = np.concatenate(workloads.chunk_levels(seed=3, chunk=c))
+    progress("generated", nch, "slabs")
+    dev_all = host.cuda()
+    out_all = torch.empty_like(dev_all)
+    dev = [list(torch.split(dev_all[c * per:(c + 1) * per], sizes)) for c in range(nch)]
+    outs = [list(torch.split(out_all[c * per:(c + 1) * per], sizes)) for c in range(nch)]
+    nbytes = dev_all.numel() * s
+    ctx = mdr.Context(0)
+    ctx.set_launch(graphs=0)
+    params = mdr.default_params(group_planes=m)
+    torch.cuda.synchronize()
+
+    state = {}
+
+    def step(tr):
+        t0 = time.perf_counter()
+        rs = mdr.refactor_batch(ctx, dev, B, params)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rts = [mdr.Retriever(ctx, r) for r in rs]
+        infos = mdr.retrieve_batch(rts, [0.0] * nch, outs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tr.append((t1 - t0, t2 - t1))
+        state["k"] = [rt.planes() for rt in rts]
+        state["bounds"] = [i["bound"] for i in infos]
+        for rt in rts:
+            rt.close()
+        if "tables" not in state:
+            state["tables"] = [unit_table(r, B, m) for r in rs]
+        for r in rs:
+            r.close()
+
+    for _ in range(args.warmup):
+        step([])
+    # every plane held: each slab's error is within its table bound (the tails
+    # below plane 64 of values far under the level maximum are all that is lost)
+    for c in range(nch):
+        err = float((out_all[c * per:(c + 1) * per] - dev_all[c * per:(c + 1) * per]).abs().max())
+        if not err <= state["bounds"][c]:
+            raise RuntimeError("slab %d: error %g above its bound %g" % (c, err, state["bounds"][c]))
+    ctx.set_timing(True)
+    ctx.timing(reset=True)
+    tr = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(tr)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = ctx.timing(reset=True)
+    ctx.set_timing(False)
+    progress("timed", args.steps, "steps: %.1f ms/step" % (elapsed / args.steps * 1e3))
+
+    tables, k = state["tables"], state["k"]
+    kb = kernel_bytes(tables, s, B, m, k)
+    ref_b, ret_b = path_bytes(tables, s, B, m, k)
+    t_ref = statistics.median(x[0] for x in tr)
+    t_ret = statistics.median(x[1] for x in tr)
+    stream_bytes = sum(nb for t in tables for (_, _, units) in t for _, nb, _ in units)
+
+    # per-slab retrieval latency, cold: a fresh retriever per (slab, bound), with
+    # 1 GiB of unrelated writes before each so that no stream is still in cache
+    rs = mdr.refactor_batch(ctx, dev, B, params)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    lat = {}
+    bounds = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 0.0]
+    for c in range(nch):
+        for tol in bounds:
+            rt = mdr.Retriever(ctx, rs[c])
+            flush.fill_(c & 0xFF)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            rt.retrieve(tol, outs[c])
+            torch.cuda.synchronize()
+            lat.setdefault(tol, []).append((time.perf_counter() - ta) * 1e3)
+            rt.close()
+    del flush
+    for r in rs:
+        r.close()
+    all_lat = sorted(x for v in lat.values() for x in v)
+
+    def pct(v, p):
+        v = sorted(v)
+        return v[min(len(v) - 1, int(round(p / 100.0 * (len(v) - 1))))]
+
+    latency = {"p50": pct(all_lat, 50), "p99": pct(all_lat, 99), "count": len(all_lat),
+               "per_bound": {("all" if t == 0 else "%.0e" % t): {"p50": pct(v, 50), "p99": pct(v, 99)}
+                             for t, v in lat.items()},
+               "note": "one 256 MiB slab per retrieval, fresh retriever, after 1 GiB of other writes"}
+    progress("latency", latency)
+    copy_gbps = copy_rate()
+    out_keep = out_all[:per * 2].cpu()  # the first two slabs, all planes (the resident path's result)
+    del dev, outs, dev_all, out_all
+
+    # host to host through the chunked pipeline (pinned H2D / refactor / D2H on
+    # three streams): PCIe-bound, reported beside the resident figures
+    pipe = mdr.Pipeline(ctx, nch, sizes, torch.float64, B, params)
+    hout = torch.empty_like(host).pin_memory()
+    runs = {}
+    for name, fn in (("refactor", lambda: pipe.refactor(host)), ("retrieve_all", lambda: pipe.retrieve(0.0, hout))):
+        fn()
+        best = min((fn() for _ in range(2)), key=lambda i: i["wall_ms"])
+        best["gbps"] = nbytes / (best["wall_ms"] / 1e3) / 1e9
+        runs[name] = best
+    if not torch.equal(hout[:per * 2], out_keep):
+        raise RuntimeError("pipelined retrieval differs from the resident one")
+    pipe.close()
+    del hout
+    progress("pipeline", runs)
+
+    res = {
+        "metric": "refactor & retrieve GB/s (frac of HBM peak); p50/p99 retrieval latency",
+        "value": 2 * nbytes / (elapsed / args.steps) / 1e9,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "chunked-1024^3-f64-%d-slabs-9-levels-resident" % nch, "values": nbytes // s,
+                   "nplanes": B, "group_planes": m, "bounds_rel": ["all planes"],
+                   "parallelism": "single-gpu"},
+        "refactor_ms": t_ref * 1e3,
+        "refactor_gbps": nbytes / t_ref / 1e9,
+        "refactor_hbm_frac": ref_b / t_ref / 1e9 / HBM_PEAK_GBS,
+        "retrieve_ms": t_ret * 1e3,
+        "retrieve_gbps": nbytes / t_ret / 1e9,
+        "retrieve_hbm_frac": ret_b / t_ret / 1e9 / HBM_PEAK_GBS,
+        "algorithmic_bytes": {"refactor": ref_b, "retrieve": ret_b, "streams": stream_bytes},
+        "latency_ms": latency,
+        "roofline": roofline_from(stages, args.steps, kb, "field1024_f64"),
+        "copy_gbps": copy_gbps,
+        "host_to_host": {"gbps": 2 * nbytes / ((runs["refactor"]["wall_ms"] + runs["retrieve_all"]["wall_ms"]) / 1e3) / 1e9,
+                         "runs": runs,
+                         "note": "pinned host memory in and out, PCIe included (not `value`)"},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_slab(workloads.chunk_levels(seed=3, chunk=0), B, m)
+    return res
+
+
+def extras(args):
+    """Short runs of the other workloads, as extra keys of the default line."""
+    import argparse as _ap
+    out = {}
+    progress("extra: 512^3 float32 field")
+    out["field512_f32"] = bench_field512(args, 2, 3, 1, cpu=False)
+    progress("extra: 256-variable batch")
+    a4 = _ap.Namespace(**vars(args))
+    a4.no_tune, a4.steps, a4.warmup = True, 2, 1
+    out["batched_256_vars"] = bench_batched(a4)
+    progress("extra: serving")
+    a5 = _ap.Namespace(**vars(args))
+    a5.serve_requests, a5.serve_loads, a5.qoi_estimators = 1000, "0.9", False
+    out["serving"] = bench_serving(a5)
+    for v in out.values():
+        for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+            v.pop(key, None)
+    return out
+
+
+def bench_field512(args, cfg, steps, warmup, cpu=True):
+    """The 512^3 float32 field (9 levels; `cfg` 1: the plain 2^20 level): one
+    step = refactor + incremental retrievals to relative bounds 1e-1 .. 1e-6."""
     import numpy as np
     import torch
 
     import paper_2505_00227_amd as mdr
 
-    w = workload(args.config)
+    w = workload(cfg)
     levels = w["levels"]
     B, m = w["B"], w["m"]
     nvals = sum(a.size for a in levels)
@@ -657,14 +951,14 @@ def main():
         rt.close()
         r.close()
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step([], [])
     ctx.set_timing(True)
     ctx.timing(reset=True)
     lat, tref = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(lat, tref)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -685,9 +979,9 @@ def main():
     copy_gbps = 2 * ref.numel() * 10 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
     del ref, ref_copy
 
-    ms_step = elapsed / args.steps * 1e3
+    ms_step = elapsed / steps * 1e3
     moved = nbytes * (1 + len(w["tols"]))
-    value = moved / (elapsed / args.steps) / 1e9
+    value = moved / (elapsed / steps) / 1e9
     lat_ms = sorted(t * 1e3 for _, t, _ in lat)
 
     def pct(p):
@@ -710,16 +1004,16 @@ def main():
         nbd = (a.size + 31) // 32
         plane_bytes += 4 * (B + 1) * nbd
     enc_bytes_per_step = nbytes + plane_bytes
-    enc_launches_per_step = enc_n / args.steps
-    achieved = (enc_bytes_per_step * args.steps) / (enc_ms / 1e3) / 1e9 if enc_ms else 0.0
+    enc_launches_per_step = enc_n / steps
+    achieved = (enc_bytes_per_step * steps) / (enc_ms / 1e3) / 1e9 if enc_ms else 0.0
     rec_ms, rec_n = stages["reconstruct"]
     res = {
         "metric": "refactor & retrieve GB/s (frac of HBM peak); p50/p99 retrieval latency",
         "value": value,
         "unit": "GB/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -732,20 +1026,51 @@ def main():
         "refactor_ms": statistics.median(tref) * 1e3,
         "retrieve": retrieve,
         "latency_ms": {"p50": pct(50), "p99": pct(99), "count": len(lat_ms)},
-        "stage_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "stage_ms_per_step": {k: v[0] / steps for k, v in stages.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic() if args.config == 2 else None),
+                     "traffic": (measured_traffic("k_encode", "field512_f32") if cfg == 2 else None),
                      "traffic_unit": "HBM bytes per step (all encoder launches)",
-                     "encoder_sha": encoder_hash(),
+                     "source_sha": source_hash("k_encode"),
                      "kernel": "k_encode", "launches_per_step": enc_launches_per_step,
                      "algorithmic_bytes_per_step": enc_bytes_per_step},
         "copy_gbps": copy_gbps,
-        "reconstruct_kernel_gbps": ((nbytes * len(w["tols"]) * args.steps) / (rec_ms / 1e3) / 1e9
+        "reconstruct_kernel_gbps": ((nbytes * len(w["tols"]) * steps) / (rec_ms / 1e3) / 1e9
                                     if rec_ms else None),
     }
-    if not args.no_cpu_baseline:
+    if cpu:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the path has no multi-GPU component "
+              "(variables and chunks shard independently); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.ablation:
+        bench_ablation(args)
+        return
+    if args.multilevel:
+        bench_multilevel(args)
+        return
+    if args.config == 4:
+        print(json.dumps(bench_batched(args)))
+        return
+    if args.config == 5:
+        print(json.dumps(bench_serving(args)))
+        return
+    if args.pipeline:
+        bench_chunked(args)
+        return
+    if args.config in (1, 2):
+        print(json.dumps(bench_field512(args, args.config, args.steps, args.warmup,
+                                        cpu=not args.no_cpu_baseline)))
+        return
+    res = bench_field1024(args)
+    if not args.no_extras:
+        res["extras"] = extras(args)
     print(json.dumps(res))
 
 
