@@ -105,6 +105,10 @@ def lib():
         L.orc_qoi_vtotal_argmax.argtypes = [u64, vp, vp, vp, vp]
         L.orc_qoi_vtotal_argmax.restype = u64
         L.orc_serialize.argtypes = [vp, u32, C.POINTER(_Params), vp, u64, C.POINTER(u64)]
+        L.orc_qoi_score_max.argtypes = [C.c_int, u32, u64, vp, vp, vp, vp, C.POINTER(u64)]
+        L.orc_qoi_score_max.restype = C.c_double
+        L.orc_qoi_estimate.argtypes = [C.c_int, u32, C.c_double, vp]
+        L.orc_qoi_estimate.restype = C.c_double
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = None
         L.orc_get_threads.restype = C.c_int
@@ -554,4 +558,126 @@ def retrieve_qoi_vtotal(vars3, tau: float, c: float = 10.0, k_in=None, max_iter:
                 ks[i] = knew
         if not moved:
             for i, levels in enumerate(vars3):
+                ks[i], _ = plan_one_step(levels, ks[i])
+
+
+# ---------------------------------------------------------------- QoI families (Sec. 5.2)
+QOI_KINDS = {"sumsq": 0, "magnitude": 1, "product": 2}
+
+
+def _qoi_nvars_ok(kind: str, nvars: int) -> bool:
+    return (kind == "product" and nvars == 2) or (kind in ("sumsq", "magnitude") and 1 <= nvars <= 3)
+
+
+def qoi_score_max(kind: str, vals, eps):
+    """(max_p r(p), first point attaining it) for the family's score r (see
+    orc_qoi_score_max in mdr_oracle.c); vals: one float64 array per variable."""
+    a = [np.ascontiguousarray(v, np.float64) for v in vals]
+    while len(a) < 3:
+        a.append(a[0])
+    e = np.zeros(3, np.float64)
+    e[:len(eps)] = eps
+    at = C.c_uint64()
+    m = lib().orc_qoi_score_max(QOI_KINDS[kind], len(vals), a[0].size, _ptr(a[0]), _ptr(a[1]), _ptr(a[2]),
+                                _ptr(e), C.byref(at))
+    return float(m), int(at.value)
+
+
+def qoi_estimate(kind: str, nvars: int, score_max: float, eps) -> float:
+    e = np.zeros(3, np.float64)
+    e[:len(eps)] = eps
+    return float(lib().orc_qoi_estimate(QOI_KINDS[kind], nvars, float(score_max), _ptr(e)))
+
+
+def _abs_max(levels) -> float:
+    nonempty = [lv for lv in levels if lv.n]
+    lo = min((lv.vmin for lv in nonempty), default=0.0)
+    hi = max((lv.vmax for lv in nonempty), default=0.0)
+    return max(abs(lo), abs(hi))
+
+
+def qoi_scale(kind: str, vars_) -> float:
+    """The family's value scale (relative tolerances multiply it): sum of squares:
+    Q_max = sum_c A_c^2 with A_c = max(|min_c|, |max_c|); magnitude: sqrt(Q_max);
+    product: A_0 A_1 (the largest values the ranges allow)."""
+    A = [_abs_max(levels) for levels in vars_]
+    if kind == "product":
+        return A[0] * A[1]
+    q = 0.0
+    for a in A:
+        q = q + a * a
+    return q if kind == "sumsq" else math.sqrt(q)
+
+
+def qoi_initial_bounds(kind: str, vars_, tau: float):
+    """Reading of Alg. 3's initial bounds per family.  Sum of squares: the
+    V_total reading, eps_c = (tau / Q_max) range_c.  Magnitude: tau / sqrt(n),
+    the largest equal bounds its value-free estimate sqrt(sum eps^2) accepts.
+    Product: eps_0 = tau / (2 A_1), eps_1 = tau / (2 A_0), the first-order terms
+    of its bound splitting tau evenly (infinite when the other factor is 0)."""
+    if kind == "sumsq":
+        q = qoi_scale("sumsq", vars_)
+        if q == 0.0:
+            return [0.0] * len(vars_)
+        return [(tau / q) * variable_range(levels) for levels in vars_]
+    if kind == "magnitude":
+        return [tau / math.sqrt(len(vars_))] * len(vars_)
+    A = [_abs_max(levels) for levels in vars_]
+    return [tau / (2.0 * A[1]) if A[1] > 0 else math.inf, tau / (2.0 * A[0]) if A[0] > 0 else math.inf]
+
+
+def qoi_point_estimate(kind: str, point_vals, eps) -> float:
+    """The estimate at one point (values as given), evaluated as tau' is."""
+    m, _ = qoi_score_max(kind, [np.array([v], np.float64) for v in point_vals], eps)
+    return qoi_estimate(kind, len(point_vals), m, eps)
+
+
+def retrieve_qoi(kind: str, vars_, tau: float, c: float = 10.0, k_in=None, max_iter: int = 10000,
+                 estimator: str = "mape", decay: float = 0.5):
+    """Alg. 3 (Sec. 5.2) for a QoI family: returns (values per var, k per var,
+    tau', met, iterations).  The same loop as retrieve_qoi_vtotal: plan each
+    variable to its initial bound; then reconstruct, take eps_c = the bound of
+    the planes held, tau' = the family's estimate; stop when tau' <= tau or
+    every plane is held; else next bounds from the estimator (MAPE: eps_c / p
+    when p = tau'/tau > c; CP: at the point with the largest score, every bound
+    times `decay` until that point's estimate is within tau; MA: none) with
+    one more merged group per variable when they add nothing."""
+    assert estimator in ("mape", "ma", "cp") and _qoi_nvars_ok(kind, len(vars_))
+    nv = len(vars_)
+    ks = [list(k_in[i]) if k_in is not None else [0] * len(v) for i, v in enumerate(vars_)]
+    eps0 = qoi_initial_bounds(kind, vars_, tau)
+    for i, levels in enumerate(vars_):
+        ks[i], _ = plan(levels, eps0[i], ks[i])
+    it = 0
+    while True:
+        it += 1
+        vals = [np.concatenate([a.astype(np.float64) for a in retrieve(levels, ks[i])])
+                for i, levels in enumerate(vars_)]
+        eps = [bound_of(levels, ks[i]) for i, levels in enumerate(vars_)]
+        score, at = qoi_score_max(kind, vals, eps)
+        tprime = qoi_estimate(kind, nv, score, eps)
+        full = all(all(k == levels[0].B for k in ks[i]) for i, levels in enumerate(vars_))
+        if tprime <= tau or full or it >= max_iter:
+            return vals, ks, tprime, tprime <= tau, it
+        target = None
+        if estimator == "mape":
+            p = tprime / tau if tau > 0 else math.inf
+            if p > c:
+                target = [e / p for e in eps]
+        elif estimator == "cp":
+            pv = [float(vals[i][at]) for i in range(nv)]
+            e = [float(x) for x in eps]
+            steps = 0
+            while qoi_point_estimate(kind, pv, e) > tau and steps < 2200:
+                e = [x * decay for x in e]
+                steps += 1
+            target = e
+        moved = False
+        if target is not None:
+            for i, levels in enumerate(vars_):
+                knew, _ = plan(levels, target[i], ks[i])
+                moved = moved or knew != ks[i]
+                ks[i] = knew
+        if not moved:
+            for i, levels in enumerate(vars_):
                 ks[i], _ = plan_one_step(levels, ks[i])

@@ -999,6 +999,84 @@ uint64_t orc_qoi_vtotal_argmax(uint64_t n, const double* vx, const double* vy, c
 }
 
 /* ------------------------------------------------------------------------ */
+/* Sec. 5.2: further QoI families (error estimation for derived quantities)    */
+/* ------------------------------------------------------------------------ */
+/*
+ * Per point, with the reconstruction's values vhat_c and L-inf bounds eps_c of
+ * the variables (|v_c - vhat_c| <= eps_c), each family's raw score r(p):
+ *
+ *   ORC_QOI_SUMSQ      S = sum_c v_c^2 over nvars = 1..3 variables:
+ *                      |S - Shat| <= D(p) = sum_c eps_c (2|vhat_c| + eps_c)
+ *                      (the V_total bound; with three variables it is V_total),
+ *                      r(p) = D(p).
+ *   ORC_QOI_MAGNITUDE  M = sqrt(S): |M - Mhat| = |S - Shat| / (M + Mhat) <= D / Mhat
+ *                      (M >= 0), and |M - Mhat| <= ||v - vhat||_2 <= sqrt(A),
+ *                      A = sum_c eps_c^2 (reverse triangle inequality).  So
+ *                      |M - Mhat| <= sqrt(min(A, D^2 / Shat)); the score is
+ *                      r(p) = D(p)^2 / Shat(p) (+inf when Shat = 0), and the
+ *                      estimate is sqrt(min(A, max_p r(p))).
+ *   ORC_QOI_PRODUCT    P = v_0 v_1 (nvars = 2): P - Phat = vhat_0 e_1 +
+ *                      vhat_1 e_0 + e_0 e_1 with |e_c| <= eps_c, so
+ *                      |P - Phat| <= r(p) = (|vhat_0| eps_1 + |vhat_1| eps_0) + eps_0 eps_1.
+ *
+ * Each is evaluated in double in the order written (Shat = (vx^2 + vy^2) + vz^2),
+ * and the estimate tau' (max_p r(p), or the magnitude's square root of the
+ * minimum) is inflated by (1 + 2^-40) to cover the rounding of these few
+ * operations.  Pins: the paper's invariant real error <= estimate <= tolerance
+ * (real computed from the originals), hand-derived points, and sampled
+ * perturbations inside the bounds.
+ */
+static double qoi_score(int kind, uint32_t nvars, const double* const* v, uint64_t i, const double eps[3])
+{
+    if (kind == ORC_QOI_PRODUCT) {
+        double a0 = fabs(v[0][i]), a1 = fabs(v[1][i]);
+        double r = (a0 * eps[1]) + (a1 * eps[0]);
+        return r + (eps[0] * eps[1]);
+    }
+    double d = 0.0;
+    for (uint32_t c = 0; c < nvars; ++c) {
+        double a = fabs(v[c][i]);
+        double t = eps[c] * ((2.0 * a) + eps[c]);
+        d = d + t;
+    }
+    if (kind == ORC_QOI_SUMSQ) return d;
+    double sh = 0.0;
+    for (uint32_t c = 0; c < nvars; ++c) sh = sh + (v[c][i] * v[c][i]);
+    if (sh == 0.0) return INFINITY;
+    return (d * d) / sh;
+}
+
+/* max_p r(p) (0 for n = 0); argmax: the first point attaining it (n for n = 0) */
+double orc_qoi_score_max(int kind, uint32_t nvars, uint64_t n, const double* v0, const double* v1,
+                         const double* v2, const double eps[3], uint64_t* argmax)
+{
+    const double* v[3] = {v0, v1, v2};
+    double worst = -1.0;
+    uint64_t at = n;
+    for (uint64_t i = 0; i < n; ++i) {
+        double r = qoi_score(kind, nvars, v, i, eps);
+        if (r > worst) {
+            worst = r;
+            at = i;
+        }
+    }
+    if (argmax) *argmax = at;
+    return n ? worst : 0.0;
+}
+
+/* the estimate tau' from the largest score */
+double orc_qoi_estimate(int kind, uint32_t nvars, double score_max, const double eps[3])
+{
+    double t = score_max;
+    if (kind == ORC_QOI_MAGNITUDE) {
+        double a = 0.0;
+        for (uint32_t c = 0; c < nvars; ++c) a = a + (eps[c] * eps[c]);
+        t = sqrt(score_max < a ? score_max : a);
+    }
+    return t * (1.0 + ldexp(1.0, -40));
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sec. 5.1 serialization (container format of this project)                 */
 /* ------------------------------------------------------------------------ */
 /*

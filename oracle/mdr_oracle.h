@@ -94,6 +94,11 @@ int orc_plan(uint32_t nlevels, uint32_t B, uint32_t m, const double* E /* nlevel
 int orc_plan_one_step(uint32_t nlevels, uint32_t B, uint32_t m, const double* E,
                       const uint64_t* unit_bytes, uint32_t* k /* in/out */);
 void orc_abl_planes(int interleaved, const uint32_t* in, uint64_t n, uint32_t* planes, uint64_t words);
+/* QoI families of Sec. 5.2 beyond V_total (see the definitions in mdr_oracle.c) */
+enum { ORC_QOI_SUMSQ = 0, ORC_QOI_MAGNITUDE = 1, ORC_QOI_PRODUCT = 2 };
+double orc_qoi_score_max(int kind, uint32_t nvars, uint64_t n, const double* v0, const double* v1,
+                         const double* v2, const double eps[3], uint64_t* argmax);
+double orc_qoi_estimate(int kind, uint32_t nvars, double score_max, const double eps[3]);
 uint64_t orc_qoi_vtotal_argmax(uint64_t n, const double* vx, const double* vy, const double* vz,
                                const double eps[3]);
 double orc_qoi_vtotal_tau(uint64_t n, const double* vx, const double* vy, const double* vz,
