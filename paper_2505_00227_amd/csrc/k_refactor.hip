@@ -209,9 +209,10 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats(const StatsJob* __restr
 // and folded in with an LDS max; the others cannot change the result.  Cuts
 // with K_k < 1/2 take the direct per-block maximum; k = 0 is max |x|, known from
 // the statistics.  Stale maxima only add candidates, so the result is exact.
-// FAST: f32 with 32 planes in groups of 4 (every row, its unit and its
-// histogram offset known at compile time): rows go from registers straight to
-// memory, neighbours come by lane shuffle, runs are counted per thread and unit.
+// FAST: 32 planes of f32 or 64 planes of f64, in groups of 4 (every row, its
+// unit and its histogram offset known at compile time): rows go from registers
+// straight to memory, neighbours come by lane shuffle, runs are counted per
+// thread (f32) or per wavefront (f64) and unit.
 template <bool F64, bool VEC, bool FAST>
 __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t wg)
 {
@@ -228,13 +229,20 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     __shared__ uint32_t s_zero[FAST ? 1 : kThreads];  // sink for zero bytes (one slot per thread)
     // FAST: the byte histograms at fixed LDS addresses, so each unit's offset is
     // an instruction immediate
-    __shared__ uint32_t s_hist_fast[FAST ? 9 * 256 : 1];
+    constexpr int FUNITS = F64 ? 17 : 9;  // FAST: units (sign + 16 or 8 groups)
+    __shared__ uint32_t s_hist_fast[FAST ? FUNITS * 256 : 1];
 
     __shared__ uint32_t s_hoff[kMaxRows];  // row -> its unit's histogram offset
-    __shared__ uint32_t s_edge[FAST ? 4 : 1][kThreads / 64][FAST ? 33 : 1];  // last lane's words per wave
-    uint32_t trc[FAST ? 9 : 1];  // FAST: this thread's word transitions per unit
+    // FAST: each wave's last words of every row for the next wave's first lanes
+    // (f32: lane 63's; f64: lanes 62 and 63, the two halves of its last W-bit word)
+    __shared__ uint32_t s_edge[FAST && !F64 ? 4 : 1][kThreads / 64][FAST && !F64 ? 33 : 1];
+    // f64: every wave's first (lanes 0, 1) and last (lanes 62, 63) words per row
+    __shared__ uint32_t s_first64[FAST && F64 ? 4 : 1][kThreads / 64][2][FAST && F64 ? 65 : 1];
+    __shared__ uint32_t s_last64[FAST && F64 ? 4 : 1][kThreads / 64][2][FAST && F64 ? 65 : 1];
+    uint32_t edge_trc[2] = {0, 0};  // f64 FAST: transitions at the wave's left edge, rows lane and lane + 64
+    uint32_t trc[FAST ? FUNITS : 1];  // FAST: word transitions per unit (f32: this thread's; f64: the wave's)
 #pragma unroll
-    for (int i = 0; i < (FAST ? 9 : 1); ++i) trc[i] = 0;
+    for (int i = 0; i < (FAST ? FUNITS : 1); ++i) trc[i] = 0;
     const uint32_t tid = threadIdx.x, lane = tid & 63;
     // every field the tile loop needs, in registers: stores through the row
     // pointer could otherwise alias the job table and force reloads
@@ -380,35 +388,52 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                            S12l = (uint32_t)S12;
             const uint32_t S1h = (uint32_t)(S1 >> 32), S2h = (uint32_t)(S2 >> 32), S4h = (uint32_t)(S4 >> 32),
                            S8h = (uint32_t)(S8 >> 32), S12h = (uint32_t)(S12 >> 32);
+            // ALL12: every cut's maximum already starts with 12 ones (the usual
+            // case past a workgroup's first tile), so the 12-bit runs alone flag
+            // the candidates and the shorter runs' masks drop out
+            auto key_pass = [&](auto all12_t) {
+                constexpr bool ALL12 = decltype(all12_t)::value;
 #pragma unroll
-            for (int j = 0; j < 32; ++j) {
-                const double y = v[j];
-                const double f = __builtin_amdgcn_fract(y);
-                frac_max64 = max(frac_max64, (uint64_t)__double_as_longlong(f));
-                const double yh = __builtin_trunc(y * 0x1p-32);
-                const uint32_t X3 = (uint32_t)yh, X2 = (uint32_t)(y - yh * 0x1p32), X1 = (uint32_t)(f * 0x1p32);
-                // (word << k) = alignbit(word, word below, 32 - k)
-                const uint32_t r2_3 = X3 & __builtin_amdgcn_alignbit(X3, X2, 31);
-                const uint32_t r2_2 = X2 & __builtin_amdgcn_alignbit(X2, X1, 31);
-                const uint32_t r2_1 = X1 & (X1 << 1);
-                const uint32_t r4_3 = r2_3 & __builtin_amdgcn_alignbit(r2_3, r2_2, 30);
-                const uint32_t r4_2 = r2_2 & __builtin_amdgcn_alignbit(r2_2, r2_1, 30);
-                const uint32_t r4_1 = r2_1 & (r2_1 << 2);
-                const uint32_t r8_3 = r4_3 & __builtin_amdgcn_alignbit(r4_3, r4_2, 28);
-                const uint32_t r8_2 = r4_2 & __builtin_amdgcn_alignbit(r4_2, r4_1, 28);
-                const uint32_t r8_1 = r4_1 & (r4_1 << 4);
-                const uint32_t r12_3 = r8_3 & __builtin_amdgcn_alignbit(r8_3, r8_2, 28);
-                const uint32_t r12_2 = r8_2 & __builtin_amdgcn_alignbit(r8_2, r8_1, 28);
-                const uint32_t ca = (X2 & S1l) | (r2_2 & S2l) | (r4_2 & S4l) | (r8_2 & S8l) | (r12_2 & S12l);
-                const uint32_t cb = (X3 & S1h) | (r2_3 & S2h) | (r4_3 & S4h) | (r8_3 & S8h) | (r12_3 & S12h);
-                uint64_t cand = ((uint64_t)cb << 32) | ca;  // bit c-1: cut c
-                while (cand) {
-                    const int c = __ffsll((unsigned long long)cand);
-                    cand &= cand - 1;
-                    const double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(y, -c));
-                    atomicMax(&s_key64[B - c], (unsigned long long)__double_as_longlong(key));
+                for (int j = 0; j < 32; ++j) {
+                    const double y = v[j];
+                    const double f = __builtin_amdgcn_fract(y);
+                    frac_max64 = max(frac_max64, (uint64_t)__double_as_longlong(f));
+                    asm volatile("" : "+v"(frac_max64));  // fold in now, not at the end
+                    const double yh = __builtin_trunc(y * 0x1p-32);
+                    const uint32_t X3 = (uint32_t)yh, X2 = (uint32_t)(y - yh * 0x1p32), X1 = (uint32_t)(f * 0x1p32);
+                    // (word << k) = alignbit(word, word below, 32 - k)
+                    const uint32_t r2_3 = X3 & __builtin_amdgcn_alignbit(X3, X2, 31);
+                    const uint32_t r2_2 = X2 & __builtin_amdgcn_alignbit(X2, X1, 31);
+                    const uint32_t r2_1 = X1 & (X1 << 1);
+                    const uint32_t r4_3 = r2_3 & __builtin_amdgcn_alignbit(r2_3, r2_2, 30);
+                    const uint32_t r4_2 = r2_2 & __builtin_amdgcn_alignbit(r2_2, r2_1, 30);
+                    const uint32_t r4_1 = r2_1 & (r2_1 << 2);
+                    const uint32_t r8_3 = r4_3 & __builtin_amdgcn_alignbit(r4_3, r4_2, 28);
+                    const uint32_t r8_2 = r4_2 & __builtin_amdgcn_alignbit(r4_2, r4_1, 28);
+                    const uint32_t r8_1 = r4_1 & (r4_1 << 4);
+                    const uint32_t r12_3 = r8_3 & __builtin_amdgcn_alignbit(r8_3, r8_2, 28);
+                    const uint32_t r12_2 = r8_2 & __builtin_amdgcn_alignbit(r8_2, r8_1, 28);
+                    uint32_t ca, cb;
+                    if constexpr (ALL12) {
+                        ca = r12_2 & S12l;
+                        cb = r12_3 & S12h;
+                    } else {
+                        ca = (X2 & S1l) | (r2_2 & S2l) | (r4_2 & S4l) | (r8_2 & S8l) | (r12_2 & S12l);
+                        cb = (X3 & S1h) | (r2_3 & S2h) | (r4_3 & S4h) | (r8_3 & S8h) | (r12_3 & S12h);
+                    }
+                    uint64_t cand = ((uint64_t)cb << 32) | ca;  // bit c-1: cut c
+                    while (cand) {
+                        const int c = __ffsll((unsigned long long)cand);
+                        cand &= cand - 1;
+                        const double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(y, -c));
+                        atomicMax(&s_key64[B - c], (unsigned long long)__double_as_longlong(key));
+                    }
                 }
-            }
+            };
+            if (S12 == (B > 1 ? (1ull << (B - 1)) - 1ull : 0ull))
+                key_pass(std::true_type{});
+            else
+                key_pass(std::false_type{});
             const uint64_t all = B > 1 ? (1ull << (B - 1)) - 1ull : 0ull;  // cuts 1 .. B-1
             uint64_t weak = all & ~strong;
             while (weak) {
@@ -518,7 +543,86 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         // row 0 = sign, row r >= 1 = plane r-1 = bit B-r
         transpose32(lo);
         if constexpr (F64) transpose32(hi);
-        if constexpr (FAST) {
+        if constexpr (FAST && F64) {
+            // row r (0..64) is sgn, hi[32 - r] (r <= 32) or lo[64 - r]; unit
+            // of row r is (r + 3) / 4.  A W-bit word is the u32 pair of lanes
+            // 2j, 2j+1 (low half first).  Transitions inside a wave: against
+            // the pair two lanes down (two wave shifts).  At the wave's left
+            // edge: lanes 0, 1 and 62, 63 of every wave leave their words in
+            // LDS, and after the tile's barrier lane r of each wave compares
+            // row r of its first word with the left wave's last word (wave 0:
+            // wave 3 of the previous tile), so the row loop reads no LDS.
+            const uint32_t wave = tid >> 6;
+            const uint32_t par = (t - t0) & 3;  // edge buffers in use, as for f32
+#define MDR_ROW64(r) ((r) == 0 ? sgn : ((r) <= 32 ? hi[32 - (r)] : lo[64 - (r)]))
+            if (lane < 2 || lane >= 62) {
+                uint32_t* dst = lane < 2 ? &s_first64[par][wave][lane][0] : &s_last64[par][wave][lane - 62][0];
+#pragma unroll
+                for (int r = 0; r <= 64; ++r) dst[r] = MDR_ROW64(r);
+            }
+            if (t == t0 && tid < 2) {
+#pragma unroll
+                for (int r = 0; r <= 64; ++r) recs[((uint64_t)wg * kMaxRows + r) * 4 + tid] = MDR_ROW64(r);
+            }
+            if (valid && blk + 2 > last_blk) {
+#pragma unroll
+                for (int r = 0; r <= 64; ++r)
+                    recs[((uint64_t)wg * kMaxRows + r) * 4 + 2 + (blk + 1 - last_blk)] = MDR_ROW64(r);
+            }
+            __syncthreads();  // edges written; every thread is done with its y values
+            {
+                // the wave's first word against its left neighbour; the range's
+                // first word (wave 0 of its first tile) has none
+                const uint32_t first_blk = t * kTileBlocks + wave * 64;
+                if (first_blk < nbd && (wave > 0 || t > t0)) {
+                    const uint32_t lp = wave ? par : ((par + 3) & 3), lw = wave ? wave - 1 : 3;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t r = lane + 64u * h;
+                        if (r <= 64) {
+                            const bool ne = s_first64[par][wave][0][r] != s_last64[lp][lw][0][r] ||
+                                            s_first64[par][wave][1][r] != s_last64[lp][lw][1][r];
+                            edge_trc[h] += ne ? 1u : 0u;
+                        }
+                    }
+                }
+            }
+            const bool even = (lane & 1) == 0;
+            auto rows_out = [&](auto full_tile) {
+                constexpr bool FULL = decltype(full_tile)::value;
+                uint64_t rb = reinterpret_cast<uint64_t>(job.rows);
+                asm volatile("" : "+s"(rb));
+                const uint32_t boff = blk * 4u;
+#pragma unroll
+                for (int r = 0; r <= 64; ++r) {
+                    const uint32_t w = MDR_ROW64(r);
+                    const int unit = (r + 3) / 4;
+                    if (FULL || valid) {
+                        *gmem(reinterpret_cast<uint32_t*>(rb + boff)) = w;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t byte = (w >> (8 * q)) & 0xFFu;
+                            if (byte) atomicAdd(&s_hist_fast[unit * 256 + byte], 1u);
+                        }
+                    }
+                    // the same half of the previous word: two wave_shr:1 (lane l <- lane
+                    // l-2); lanes 0 and 1 see their own word (counted at the edge above)
+                    const int p1 = __builtin_amdgcn_update_dpp((int)w, (int)w, 0x138, 0xF, 0xF, false);
+                    const int p2 = __builtin_amdgcn_update_dpp((int)w, p1, 0x138, 0xF, 0xF, false);
+                    const int ne = (lane >= 2 && (int)w != p2) ? 1 : 0;
+                    // the partner half's verdict: quad_perm [1, 0, 3, 2]
+                    const int ne_pair = ne | __builtin_amdgcn_update_dpp(0, ne, 0xB1, 0xF, 0xF, false);
+                    trc[unit] += (uint32_t)__popcll(__ballot((FULL || valid) && even && ne_pair));
+                    rb += 4ull * nbd;
+                }
+            };
+            if ((t + 1) * kTileBlocks <= nbd)
+                rows_out(std::true_type{});
+            else
+                rows_out(std::false_type{});
+#undef MDR_ROW64
+            continue;
+        } else if constexpr (FAST) {
             // row r (0..32) is sgn or lo[32 - r]; unit of row r is (r + 3) / 4
             const uint32_t wave = tid >> 6;
             // four buffers: without a barrier at the top of the tile, a wave can
@@ -660,7 +764,15 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     }
 
     // ---- flush: per-workgroup partials (reduced by the selection kernel)
-    if constexpr (FAST) {
+    if constexpr (FAST && F64) {
+        // wave-wide counts already; a unit's transitions go to its first row's
+        // slot (the selection sums a unit's rows), the edge counts to their row's
+#pragma unroll
+        for (int i = 0; i < FUNITS; ++i)
+            if (lane == 0 && trc[i]) atomicAdd(&s_trans[i == 0 ? 0 : 1 + (i - 1) * 4], trc[i]);
+        if (edge_trc[0]) atomicAdd(&s_trans[lane], edge_trc[0]);
+        if (lane == 0 && edge_trc[1]) atomicAdd(&s_trans[64], edge_trc[1]);
+    } else if constexpr (FAST) {
         // a unit's transitions go to its first row's slot (the selection sums a unit's rows)
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -709,25 +821,35 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5, 8))
     encode_body<false, VEC, FAST>(job, blockIdx.x - job.wg_base);
 }
 
-template <bool VEC>
+template <bool VEC, bool FAST>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_encode_f64(
     const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
 {
     const EncodeJob& job = jobs[wg_job[blockIdx.x]];
-    encode_body<true, VEC, false>(job, blockIdx.x - job.wg_base);
+    encode_body<true, VEC, FAST>(job, blockIdx.x - job.wg_base);
+}
+
+// the f64 fast path holds no staged rows: four waves per SIMD (128 registers)
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_encode_f64_fast(
+    const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
+{
+    const EncodeJob& job = jobs[wg_job[blockIdx.x]];
+    encode_body<true, VEC, true>(job, blockIdx.x - job.wg_base);
 }
 
 // ------------------------------------------------------------------ hybrid selection
-// One workgroup of kSelThreads threads per (unit, level) (Alg. 2): gather the byte
+// One workgroup of NT threads per (unit, level) (Alg. 2): gather the byte
 // histogram and the run count, build length-limited Huffman code lengths with
 // the two-queue construction, canonical codes, both size estimates, and the
 // method decision.  Units that Alg. 2 can only copy (S <= T_s) skip the codebook.
-// 512 threads: the tree is built on one lane, so smaller workgroups let more
-// units build theirs at once (a batch of many variables has thousands; 1024
-// threads made such a batch's selection 3x slower, 256 a single field's 20 %)
-constexpr int kSelThreads = 512;
-
-__global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
+// NT = 256, 512 or 1024 threads (a launch knob): the tree is built on one
+// lane, so smaller workgroups let more units build theirs at once (a batch of
+// many variables has thousands; 1024 threads made such a batch's selection 3x
+// slower than 512), while the histogram and rank steps of a few large units
+// go faster with more threads (256 made a single field's 20 % slower).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_select(const SelectParams job,
                                                          const SelectLevel* __restrict__ levels)
 {
     __shared__ unsigned long long s_f[256];     // working counts (halved when limiting)
@@ -737,13 +859,13 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
     __shared__ int s_sorted[256];
     __shared__ int s_dp[1024];  // depths and parents while measuring the tree
     __shared__ uint8_t s_len[256];
-    __shared__ unsigned long long s_red[kSelThreads / 64];
+    __shared__ unsigned long long s_red[NT / 64];
     __shared__ int s_nl, s_maxlen;
     __shared__ uint32_t s_count[33], s_first[33];
 
     const SelectLevel& lv = levels[blockIdx.y];
     const uint32_t u = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t B = job.B, m = job.m, G = job.G, grid = lv.grid, nunits = job.nunits;
+    const uint32_t B = job.B, m = job.m, G = job.G, grid = lv.grid;
     const uint32_t r0 = u == 0 ? 0 : 1 + (u - 1) * m;
     const uint32_t r1 = u == 0 ? 1 : min(B + 1, r0 + m);
     const uint64_t S = (uint64_t)(r1 - r0) * lv.nbd * 4;
@@ -775,7 +897,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         if (lane == 0) s_red[wave] = v;
         __syncthreads();
         unsigned long long t = 0;
-        for (int w = 0; w < kSelThreads / 64; ++w) t += s_red[w];
+        for (int w = 0; w < NT / 64; ++w) t += s_red[w];
         __syncthreads();
         return t;
     };
@@ -799,11 +921,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         // of range w - 1, row r0 + i % nrow; four boundaries per thread in flight
         const auto recs = gmem(lv.recs);
         const uint32_t nbnd = (grid - 1) * nrow;
-        for (uint32_t i0 = tid; i0 < nbnd; i0 += 4 * kSelThreads) {
+        for (uint32_t i0 = tid; i0 < nbnd; i0 += 4 * NT) {
             uint32_t cw[4][2], pw[4][2];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint32_t i = min(i0 + k * kSelThreads, nbnd - 1);
+                const uint32_t i = min(i0 + k * NT, nbnd - 1);
                 const uint32_t w = 1 + i / nrow, r = r0 + i % nrow;
                 const uint64_t cur = ((uint64_t)w * kMaxRows + r) * 2 * G;
                 const uint64_t prv = ((uint64_t)(w - 1) * kMaxRows + r) * 2 * G;
@@ -815,10 +937,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                if (i0 + k * kSelThreads < nbnd) tr += (cw[k][0] != pw[k][0] || cw[k][1] != pw[k][1]) ? 1 : 0;
+                if (i0 + k * NT < nbnd) tr += (cw[k][0] != pw[k][0] || cw[k][1] != pw[k][1]) ? 1 : 0;
         }
     }
-    for (uint32_t r = r0 + 1 + tid; r < r1; r += kSelThreads) {
+    for (uint32_t r = r0 + 1 + tid; r < r1; r += NT) {
         const uint32_t* cur = lv.recs + ((uint64_t)0 * kMaxRows + r) * 2 * G;
         const uint32_t* prv = lv.recs + ((uint64_t)(grid - 1) * kMaxRows + (r - 1)) * 2 * G;
         bool ne = false;
@@ -839,7 +961,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         // rank of each present symbol in (count, symbol) order: kRankParts
         // threads per symbol, 256 / kRankParts comparisons each
         {
-            constexpr uint32_t kRankParts = kSelThreads / 256;
+            constexpr uint32_t kRankParts = NT / 256;
             constexpr int kSpan = 256 / kRankParts;
             const uint32_t sym = tid & 255, part = tid >> 8;
             const unsigned long long fsym = s_f[sym];
@@ -912,10 +1034,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
         const int nnodes = nl > 1 ? 2 * nl - 1 : 0;
         int* s_d = s_dp;
         int* s_p = s_dp + 512;
-        constexpr int kNodesPer = (512 + kSelThreads - 1) / kSelThreads;  // nodes per thread
+        constexpr int kNodesPer = (512 + NT - 1) / NT;  // nodes per thread
 #pragma unroll
         for (int h = 0; h < kNodesPer; ++h) {
-            const int v = (int)tid + h * kSelThreads;
+            const int v = (int)tid + h * NT;
             if (v < nnodes) {
                 s_p[v] = s_parent[v];
                 s_d[v] = (v == nnodes - 1) ? 0 : 1;
@@ -926,7 +1048,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             int nd[kNodesPer], np[kNodesPer];
 #pragma unroll
             for (int h = 0; h < kNodesPer; ++h) {
-                const int v = (int)tid + h * kSelThreads;
+                const int v = (int)tid + h * NT;
                 nd[h] = 0, np[h] = 0;
                 if (v < nnodes) {
                     const int p = s_p[v];
@@ -937,7 +1059,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             __syncthreads();
 #pragma unroll
             for (int h = 0; h < kNodesPer; ++h) {
-                const int v = (int)tid + h * kSelThreads;
+                const int v = (int)tid + h * NT;
                 if (v < nnodes) {
                     s_d[v] = nd[h];
                     s_p[v] = np[h];
@@ -959,7 +1081,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select(const SelectParams job,
             // ITU-T T.81 Annex K count adjustment on one lane, then hand the
             // lengths out again: heaviest leaf (last in sorted order) shortest
             uint32_t* s_bits = reinterpret_cast<uint32_t*>(s_parent);  // 256+1 entries
-            for (uint32_t i = tid; i <= 256; i += kSelThreads) s_bits[i] = 0;
+            for (uint32_t i = tid; i <= 256; i += NT) s_bits[i] = 0;
             __syncthreads();
             if (tid < nl) atomicAdd(&s_bits[s_d[tid]], 1u);
             __syncthreads();
@@ -1127,7 +1249,7 @@ hipError_t launch_stats_batch(const StatsJob* jobs, const uint32_t* wg_job, uint
 
 size_t encode_lds_bytes(uint32_t nunits, uint32_t B, uint32_t m, bool f64)
 {
-    if (!f64 && B == 32 && m == 4) return 0;  // the fast path: static LDS only
+    if ((!f64 && B == 32 && m == 4) || (f64 && B == 64 && m == 4)) return 0;  // the fast paths: static LDS only
     const uint32_t npass = B + 1 > kPassRows ? 2u : 1u;  // as the kernel stages its rows
     const size_t planes = (size_t)((B + 1 + npass - 1) / npass) * kTileBlocks * sizeof(uint32_t);
     return (size_t)nunits * 256 * sizeof(uint32_t) + planes;
@@ -1137,8 +1259,8 @@ hipError_t encode_set_lds(uint32_t nunits, uint32_t B, uint32_t m, bool f64)
 {
     const size_t shmem = encode_lds_bytes(nunits, B, m, f64);
     if (shmem <= 64 * 1024) return hipSuccess;  // the fast path always fits
-    const void* fns[2] = {f64 ? (const void*)k_encode_f64<true> : (const void*)k_encode_f32<true, false>,
-                          f64 ? (const void*)k_encode_f64<false> : (const void*)k_encode_f32<false, false>};
+    const void* fns[2] = {f64 ? (const void*)k_encode_f64<true, false> : (const void*)k_encode_f32<true, false>,
+                          f64 ? (const void*)k_encode_f64<false, false> : (const void*)k_encode_f32<false, false>};
     for (const void* fn : fns) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
         if (e != hipSuccess) return e;
@@ -1149,15 +1271,22 @@ hipError_t encode_set_lds(uint32_t nunits, uint32_t B, uint32_t m, bool f64)
 hipError_t launch_encode_batch(const EncodeJob* jobs, const uint32_t* wg_job, uint32_t grid,
                                uint32_t nunits, uint32_t B, uint32_t m, bool f64, bool vec, hipStream_t s)
 {
-    const bool fast = !f64 && B == 32 && m == 4;
+    const bool fast = (!f64 && B == 32 && m == 4) || (f64 && B == 64 && m == 4);
     if (grid == 0) return hipSuccess;
     const size_t shmem = encode_lds_bytes(nunits, B, m, f64);
     dim3 g(grid), b(kThreads);
     if (f64) {
-        if (vec)
-            hipLaunchKernelGGL((k_encode_f64<true>), g, b, shmem, s, jobs, wg_job);
-        else
-            hipLaunchKernelGGL((k_encode_f64<false>), g, b, shmem, s, jobs, wg_job);
+        if (fast) {
+            if (vec)
+                hipLaunchKernelGGL((k_encode_f64_fast<true>), g, b, shmem, s, jobs, wg_job);
+            else
+                hipLaunchKernelGGL((k_encode_f64_fast<false>), g, b, shmem, s, jobs, wg_job);
+        } else {
+            if (vec)
+                hipLaunchKernelGGL((k_encode_f64<true, false>), g, b, shmem, s, jobs, wg_job);
+            else
+                hipLaunchKernelGGL((k_encode_f64<false, false>), g, b, shmem, s, jobs, wg_job);
+        }
     } else {
         if (fast) {
             if (vec)
@@ -1178,7 +1307,13 @@ hipError_t launch_select_batch(const SelectParams& p, const SelectLevel* lv, uin
                                hipStream_t s)
 {
     if (nlev == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select, dim3(p.nunits, nlev), dim3(kSelThreads), 0, s, p, lv);
+    const dim3 g(p.nunits, nlev);
+    if (p.threads == 256)
+        hipLaunchKernelGGL(k_select<256>, g, dim3(256), 0, s, p, lv);
+    else if (p.threads == 1024)
+        hipLaunchKernelGGL(k_select<1024>, g, dim3(1024), 0, s, p, lv);
+    else
+        hipLaunchKernelGGL(k_select<512>, g, dim3(512), 0, s, p, lv);
     return hipGetLastError();
 }
 

@@ -92,6 +92,7 @@ struct SelectParams {
     uint32_t B, m, nunits, G;  // G: u32 words per W-bit word (1 f32, 2 f64)
     uint32_t t_cr_milli, huf_chunk, huf_lmax;
     int32_t force_method;
+    uint32_t threads;  // workgroup size of the selection kernel: 256, 512 or 1024
     uint64_t t_s;
 };
 
@@ -180,6 +181,8 @@ struct ReconJob {
 hipError_t launch_reconstruct_batch(const ReconJob* jobs, const uint32_t* wg_job, uint32_t grid,
                                    bool f64, hipStream_t s);
 // V_total estimate of many (request, level) jobs of one dtype; acc must hold 0 first
+// QoI families, as mdr_qoi_kind numbers them
+constexpr uint32_t kQoiSumsq = 0, kQoiMagnitude = 1, kQoiProduct = 2;
 struct QoiJob {
     const void* x;
     const void* y;
@@ -189,6 +192,7 @@ struct QoiJob {
     unsigned long long* acc;  // max of the estimate's bit patterns (non-negative doubles)
     unsigned long long* arg;  // first point attaining it (argmax launch only)
     uint64_t base;            // index of the job's first point in its variable
+    uint32_t kind, nvars;     // QoI family (kQoi*) and its variables (absent ones: zero bounds)
     uint32_t wg_base, grid;   // this job's workgroups in the launch
 };
 hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
