@@ -319,7 +319,7 @@ mdr_status mdr_deserialize(mdr_context* ctx, const void* host, uint64_t bytes, m
     R->payload_arena = std::make_shared<PoolBuf>();
     he = R->rows_arena->alloc(ctx->pool, rows_bytes);
     if (he != hipSuccess) return hip_fail(he, "hipMalloc(planes)");
-    he = R->payload_arena->alloc(ctx->pool, pay_bytes);
+    he = R->payload_arena->alloc(ctx->pool, pay_bytes + 256);  // padded for the Huffman decoder's block reads
     if (he != hipSuccess) return hip_fail(he, "hipMalloc(payloads)");
     uint8_t* rb = static_cast<uint8_t*>(R->rows_arena->p);
     for (uint32_t l = 0; l < nlevels; ++l) {

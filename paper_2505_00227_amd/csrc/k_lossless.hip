@@ -731,34 +731,48 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     const uint32_t c = (blockIdx.x - job.wg_base) * kThreads + tid;
     if (c >= nchunks) return;
     const auto off = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader));
-    const auto words = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1)));
     const uint32_t wb = off[c], we = off[c + 1];
     // words past the chunk's end are never decoded: read the last one instead
     const uint32_t wl = we > wb ? we - 1 : wb;
     const uint64_t lo = (uint64_t)c * chunk;
     const uint32_t cnt = (uint32_t)((lo + chunk <= S) ? chunk : S - lo);  // a multiple of 4
     const auto dst4 = gmem(reinterpret_cast<u32x4*>(job.out + lo));
-    // eight compressed words in flight: refill j takes q[j] and reloads it with
-    // the word eight refills ahead (registers are never moved, so a refill
-    // waits only for its own, oldest load)
-    uint32_t q[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) q[j] = words[min(wb + j, wl)];
-    uint32_t wp = wb + 8;
+    // Compressed words arrive as aligned 16-byte blocks, two in flight: a
+    // thread's stream is its own, and with one word per load every line came
+    // from memory several times over before the thread had used it up.  Block
+    // k holds words 4k - delta .. 4k - delta + 3 of the chunk data (delta puts
+    // the data's start on its 16-byte grid); the first block may begin before
+    // the chunk and the last may end past it (a stream's allocation is padded
+    // to 256 bytes), but no block past the one holding word wl is read.
+    const uintptr_t wbase = reinterpret_cast<uintptr_t>(payload + kHufHeader + 4ull * (nchunks + 1));
+    const uint32_t delta = (uint32_t)((wbase & 15u) >> 2);
+    const auto blk4 = gmem(reinterpret_cast<const u32x4*>(wbase & ~(uintptr_t)15));
+    const uint32_t b0 = (wb + delta) >> 2, j0 = (wb + delta) & 3u, bl = (wl + delta) >> 2;
+    u32x4 qa = blk4[b0], qb = blk4[min(b0 + 1, bl)];
+    uint32_t bnext = b0 + 2;
+    bool first = true;
     uint64_t buf = 0;
     int nb = 0;
     uint64_t pend = 0;  // decoded bytes not yet in a whole word (fewer than 4 between iterations)
-    uint32_t npend = 0, done = 0, wo = 0, nob = 0;
-    u32x4 ob = {0, 0, 0, 0};  // whole words waiting for a 16-byte store
+    uint32_t npend = 0, done = 0, wo = 0, nob = 0, nsl = 0;
+    // decoded words leave in whole 64-byte pieces: ob collects four words, the
+    // slots s0..s2 the three vectors before it (a line written at once is
+    // written once; 16-byte pieces of lines far apart were written back piecemeal)
+    u32x4 ob = {0, 0, 0, 0}, s0 = {0, 0, 0, 0}, s1 = {0, 0, 0, 0}, s2 = {0, 0, 0, 0};
     bool more = done < cnt;
     while (more) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             if (!more) break;
-            buf |= (uint64_t)q[j] << (32 - nb);
+            if (first && (uint32_t)j < j0) continue;  // words of the first block before the chunk
+            const uint32_t wj = j < 4 ? qa[j] : qb[j - 4];
+            buf |= (uint64_t)wj << (32 - nb);
             nb += 32;
-            q[j] = words[min(wp, wl)];
-            ++wp;
+            if (j == 3) qa = blk4[min(bnext++, bl)];
+            if (j == 7) {
+                qb = blk4[min(bnext++, bl)];
+                first = false;
+            }
             // more than 32 bits in the buffer: a whole window for every lookup.
             // The last lookup may decode up to two symbols past the chunk's
             // end; they never complete a word, so they are never stored.
@@ -775,16 +789,32 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
                     pend >>= 32;
                     npend -= 4;
                     if (++nob == 4) {
-                        dst4[wo++] = ob;
                         nob = 0;
+                        if (nsl == 0) {
+                            s0 = ob;
+                        } else if (nsl == 1) {
+                            s1 = ob;
+                        } else if (nsl == 2) {
+                            s2 = ob;
+                        } else {
+                            dst4[wo] = s0;
+                            dst4[wo + 1] = s1;
+                            dst4[wo + 2] = s2;
+                            dst4[wo + 3] = ob;
+                            wo += 4;
+                        }
+                        nsl = (nsl + 1) & 3u;
                     }
                 }
             }
             more = done < cnt;
         }
     }
-    // a chunk ends on a word; up to three whole words remain, the newest
-    // nob of ob (in order)
+    // a chunk ends on a word: the whole vectors held in the slots, then up to
+    // three words, the newest nob of ob (in order)
+    if (nsl > 0) dst4[wo++] = s0;
+    if (nsl > 1) dst4[wo++] = s1;
+    if (nsl > 2) dst4[wo++] = s2;
     const auto dst = gmem(reinterpret_cast<uint32_t*>(job.out + lo)) + 4 * wo;
     if (nob == 3) {
         dst[0] = ob.y;

@@ -376,8 +376,10 @@ mdr_status mdr_pipeline_retrieve(mdr_pipeline* p, mdr_bound kind, double tol, vo
             hipError_t e = p->dev_rows[s].alloc(p->ctx->pool, rows_max);
             if (e != hipSuccess) return hip_fail(e, "hipMalloc(pipeline rows)");
         }
-        if (p->dev_pay[s].bytes < std::max<uint64_t>(pay_max, 256)) {
-            hipError_t e = p->dev_pay[s].alloc(p->ctx->pool, std::max<uint64_t>(pay_max, 256));
+        // 256 bytes past the last payload: the Huffman decoder reads whole aligned
+        // 16-byte blocks, the last of which may end past its stream
+        if (p->dev_pay[s].bytes < pay_max + 256) {
+            hipError_t e = p->dev_pay[s].alloc(p->ctx->pool, pay_max + 256);
             if (e != hipSuccess) return hip_fail(e, "hipMalloc(pipeline payloads)");
         }
         if (!p->dev_out[s].p) {
@@ -553,7 +555,7 @@ mdr_status mdr_pipeline_chunk(const mdr_pipeline* p, uint32_t chunk, mdr_context
     auto pay = std::make_shared<PoolBuf>();
     hipError_t e = rows->alloc(ctx->pool, hc.rows_bytes);
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(chunk rows)");
-    e = pay->alloc(ctx->pool, std::max<uint64_t>(hc.pay_bytes, 256));
+    e = pay->alloc(ctx->pool, hc.pay_bytes + 256);  // padded for the decoder's block reads
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(chunk payloads)");
     for (const auto& d : hc.dc)
         MDR_HIP(hipMemcpy(static_cast<uint8_t*>(rows->p) + d.first, static_cast<const uint8_t*>(hc.rows) + d.first,

@@ -121,6 +121,7 @@ struct Layout {
     uint64_t d_sjobs = 0, d_ejobs = 0, d_slev = 0, d_largs = 0, d_map[4] = {}, desc_bytes = 0;
     std::vector<uint32_t> map[4];  // workgroup -> job: stats (unaligned, aligned), encode (same)
     std::string key;               // launch shape, for the graph cache
+    mdr_launch_shape shape{};      // the knobs this pass runs with
 };
 
 mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t nvars, mdr_dtype dtype,
@@ -131,7 +132,7 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
     L.B = B;
     L.m = prm.group_planes;
     L.nunits = 1 + (B + L.m - 1) / L.m;
-    uint64_t total_tiles = 0;
+    uint64_t total_tiles = 0, total_values = 0;
     for (uint32_t v = 0; v < nvars; ++v) {
         L.var_first.push_back((uint32_t)L.jobs.size());
         for (uint32_t l = 0; l < vars[v].nlevels; ++l) {
@@ -150,6 +151,7 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
             jp.ntiles = (uint32_t)ceil_div(jp.nbd, kTileBlocks);
             jp.vec = ((uintptr_t)lv.data % 16) == 0;
             total_tiles += jp.ntiles;
+            total_values += lv.n;
             L.jobs.push_back(jp);
         }
     }
@@ -157,16 +159,21 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
     L.J = (uint32_t)L.jobs.size();
     L.U = L.J * L.nunits;
     if (L.J == 0) return MDR_OK;
+    {
+        uint32_t tk[5];
+        tune_key(dtype, B, L.m, total_values, L.J, tk);
+        L.shape = effective_shape(ctx, tk);
+    }
 
     // every encoder workgroup walks about the same number of tiles, so that a
     // batch of mixed level sizes finishes together
-    const uint64_t tpw_all = std::max<uint64_t>(1, ceil_div(total_tiles, std::max<uint32_t>(1, ctx->enc_target_wg)));
+    const uint64_t tpw_all = std::max<uint64_t>(1, ceil_div(total_tiles, std::max<uint32_t>(1, L.shape.enc_target_wg)));
     uint64_t hist = 0, recs = 0, trans = 0;
     for (JobPlan& jp : L.jobs) {
         if (jp.ntiles) {
             jp.tpw = (uint32_t)std::min<uint64_t>(jp.ntiles, tpw_all);
             jp.grid_e = (uint32_t)ceil_div(jp.ntiles, jp.tpw);
-            jp.grid_s = (uint32_t)std::min<uint64_t>(kStatsMaxWg, ceil_div(jp.n, std::max<uint32_t>(1024, ctx->stats_wg_values)));
+            jp.grid_s = (uint32_t)std::min<uint64_t>(kStatsMaxWg, ceil_div(jp.n, std::max<uint32_t>(1024, L.shape.stats_wg_values)));
         }
         jp.rows_off = L.rows_bytes;
         L.rows_bytes += align256(4ull * (B + 1) * jp.nbd);
@@ -256,8 +263,9 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
     put(prm.huf_chunk);
     put(prm.huf_lmax);
     put((uint64_t)(int64_t)prm.force_method);
-    put(ctx->enc_target_wg);
-    put(ctx->stats_wg_values);
+    put(L.shape.enc_target_wg);
+    put(L.shape.stats_wg_values);
+    put(L.shape.select_threads);
     put(nvars);
     for (const JobPlan& jp : L.jobs) {
         put(jp.n);
@@ -379,6 +387,7 @@ mdr_status enqueue_pass(mdr_context* ctx, const Layout& L, const mdr_codec_param
         sp.huf_chunk = prm.huf_chunk;
         sp.huf_lmax = prm.huf_lmax;
         sp.force_method = prm.force_method;
+        sp.threads = L.shape.select_threads;
         sp.t_s = prm.t_s_bytes;
         for (uint32_t j0 = 0; j0 < L.J; j0 += 65535)
             MDR_HIP(launch_select_batch(sp, sl + j0, std::min<uint32_t>(65535, L.J - j0), s));
@@ -487,6 +496,10 @@ mdr_status refactor_batch(mdr_context* ctx, const VarLevels* vars, uint32_t nvar
                           mdr_refactored** outs)
 {
     MDR_HIP(hipSetDevice(ctx->device));
+    if (ctx->autotune && !ctx->tuning) {
+        mdr_status ts = tune_on_first_use(ctx, vars, nvars, dtype, B, prm, s);
+        if (ts) return ts;
+    }
     Layout L;
     mdr_status st = make_layout(ctx, vars, nvars, dtype, B, prm, L);
     if (st) return st;
@@ -496,7 +509,7 @@ mdr_status refactor_batch(mdr_context* ctx, const VarLevels* vars, uint32_t nvar
     {
         hipError_t e = rows->alloc(ctx->pool, L.rows_bytes);
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(planes)");
-        e = pay->alloc(ctx->pool, L.pay_cap);
+        e = pay->alloc(ctx->pool, L.pay_cap + 256);  // padded for the Huffman decoder's block reads
         if (e != hipSuccess) return hip_fail(e, "hipMalloc(payloads)");
     }
     if (L.J == 0) return assemble(ctx, L, dtype, prm, nullptr, rows, pay, nvars, outs);
