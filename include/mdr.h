@@ -129,6 +129,55 @@ mdr_status mdr_context_timing(mdr_context* ctx, double* ms, uint64_t* launches, 
 mdr_status mdr_context_set_launch(mdr_context* ctx, uint32_t enc_target_wg, uint32_t stats_wg_values,
                                   int graphs);
 
+/* ---- Launch-shape autotuner (the batched pass's block and tile shapes) ----
+ * A launch shape is the three knobs of the refactor pass: enc_target_wg and
+ * stats_wg_values (above) and select_threads, the workgroup size of the
+ * Alg. 2 selection kernel (256, 512 or 1024; default 512).  No knob changes a
+ * result, bit for bit; only time.
+ *
+ * The context keeps a tuning table keyed by (dtype, nplanes, group size,
+ * floor(log2(values in the pass)), floor(log2(levels in the pass))); a pass
+ * whose key has an entry runs at that entry's shape, any other pass at the
+ * context's default shape (mdr_context_set_launch / _set_select_threads).
+ *
+ * mdr_autotune_refactor: times refactor passes over the given variables (the
+ * arguments of mdr_refactor_batch; the results are discarded) at the default
+ * shape and at candidate shapes, by coordinate descent (encoder workgroups,
+ * then statistics workgroup values, then selection threads; `reps` passes per
+ * shape, the fastest counted; HIP events on `stream`), and records the fastest
+ * in the table.  With force = 0 and an entry already present for the key, it
+ * times nothing and reports that entry (candidates = 0).  Waits for `stream`.
+ * mdr_tune_save / mdr_tune_load: write / read the table as JSON (one entry per
+ * line); load merges into the table (a missing file is MDR_ERR_INVALID_ARG,
+ * a malformed one MDR_ERR_CORRUPT_STREAM).  mdr_context_create loads the file
+ * named by the environment variable MDR_TUNE_CACHE when it exists, and with
+ * MDR_AUTOTUNE=1 a pass whose key has no entry is tuned first (then the file,
+ * if named, is rewritten). */
+typedef struct {
+    uint32_t enc_target_wg;
+    uint32_t stats_wg_values;
+    uint32_t select_threads;
+} mdr_launch_shape;
+typedef struct {
+    mdr_launch_shape best;     /* the recorded shape */
+    mdr_launch_shape dflt;     /* the context's default shape */
+    double best_ms;            /* fastest pass at `best` (0 when taken from the table) */
+    double default_ms;         /* fastest pass at the default shape (0 likewise) */
+    uint32_t candidates;       /* shapes timed, 0 = taken from the table */
+    uint32_t value_bucket;     /* floor(log2(values in the pass)) */
+    uint32_t level_bucket;     /* floor(log2(levels in the pass)) */
+} mdr_tune_result;
+mdr_status mdr_context_set_select_threads(mdr_context* ctx, uint32_t threads);
+mdr_status mdr_autotune_refactor(mdr_context* ctx, const mdr_level_view* const* vars, const uint32_t* nlevels,
+                                 uint32_t nvars, mdr_dtype dtype, uint32_t nplanes,
+                                 const mdr_codec_params* params, void* stream, uint32_t reps, int force,
+                                 mdr_tune_result* out);
+mdr_status mdr_tune_save(const mdr_context* ctx, const char* path);
+mdr_status mdr_tune_load(mdr_context* ctx, const char* path);
+/* number of table entries, and entry i's key and shape (for inspection) */
+mdr_status mdr_tune_entries(const mdr_context* ctx, uint32_t* count);
+mdr_status mdr_tune_entry(const mdr_context* ctx, uint32_t i, uint32_t key[5], mdr_launch_shape* shape);
+
 /* ---------------------------------------------------------------- refactor */
 /*
  * Refactor one variable given as nlevels coefficient levels (coarsest first).
@@ -281,6 +330,33 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
                                         mdr_bound kind, double tau, const mdr_qoi_params* params,
                                         void* const* out_x, void* const* out_y, void* const* out_z,
                                         void* stream, mdr_qoi_info* info);
+
+/*
+ * Further QoI families (Sec. 5.2 controls errors of derived quantities; the
+ * families below are this library's reading of that error estimation).  The
+ * loop, the estimators and the retriever requirements are those of
+ * mdr_retrieve_qoi_vtotal_with, over nvars retrievers rts[] (distinct, same
+ * dtype and points per level) writing outs[c][l]; per family, at every point,
+ * from the reconstruction vhat_c and the planes' bounds eps_c:
+ *   MDR_QOI_SUMSQ      S = sum_c v_c^2, nvars 1..3 (3: V_total):
+ *                      score D = sum_c eps_c (2|vhat_c| + eps_c); tau' = max D;
+ *                      scale Q_max = sum_c A_c^2 (A_c = max(|min_c|, |max_c|));
+ *                      initial eps_c = (tau / Q_max) range_c.
+ *   MDR_QOI_MAGNITUDE  M = sqrt(S), nvars 1..3: |M - Mhat| <= D / Mhat and
+ *                      <= sqrt(sum_c eps_c^2); score D^2 / Shat (+inf at
+ *                      Shat = 0), tau' = sqrt(min(sum_c eps_c^2, max score));
+ *                      scale sqrt(Q_max); initial eps_c = tau / sqrt(nvars).
+ *   MDR_QOI_PRODUCT    P = v_0 v_1, nvars 2: score (|vhat_0| eps_1 +
+ *                      |vhat_1| eps_0) + eps_0 eps_1; tau' = max score; scale
+ *                      A_0 A_1; initial eps_0 = tau / (2 A_1), eps_1 = tau / (2 A_0).
+ * tau' is inflated by (1 + 2^-40) (rounding cover); MDR_REL multiplies tau by
+ * the scale.  info->eps holds the first nvars bounds.  Bad family, variable
+ * count or estimator: MDR_ERR_INVALID_ARG.
+ */
+typedef enum { MDR_QOI_SUMSQ = 0, MDR_QOI_MAGNITUDE = 1, MDR_QOI_PRODUCT = 2 } mdr_qoi_kind;
+mdr_status mdr_retrieve_qoi(mdr_qoi_kind family, mdr_retriever* const* rts, uint32_t nvars, mdr_bound kind,
+                            double tau, const mdr_qoi_params* params, void* const* const* outs, void* stream,
+                            mdr_qoi_info* info);
 
 /* ---------------------------------------------------------------- chunked pipeline */
 /*

@@ -58,6 +58,7 @@ class mdr_qoi_params(C.Structure):
 
 MDR_QOI_MAPE, MDR_QOI_MA, MDR_QOI_CP = 0, 1, 2
 QOI_ESTIMATORS = {"mape": MDR_QOI_MAPE, "ma": MDR_QOI_MA, "cp": MDR_QOI_CP}
+QOI_FAMILIES = {"sumsq": 0, "magnitude": 1, "product": 2}
 
 
 class mdr_qoi_info(C.Structure):
@@ -98,6 +99,25 @@ class mdr_server_info(C.Structure):
     _fields_ = [("pending", C.c_uint32), ("active", C.c_uint32), ("completed_unreleased", C.c_uint32),
                 ("pad", C.c_uint32), ("steps", C.c_uint64), ("step_requests", C.c_uint64),
                 ("hbm_in_use", C.c_uint64), ("hbm_budget", C.c_uint64), ("hbm_held", C.c_uint64)]
+
+
+class mdr_launch_shape(C.Structure):
+    _fields_ = [("enc_target_wg", C.c_uint32), ("stats_wg_values", C.c_uint32),
+                ("select_threads", C.c_uint32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class mdr_tune_result(C.Structure):
+    _fields_ = [("best", mdr_launch_shape), ("dflt", mdr_launch_shape), ("best_ms", C.c_double),
+                ("default_ms", C.c_double), ("candidates", C.c_uint32), ("value_bucket", C.c_uint32),
+                ("level_bucket", C.c_uint32)]
+
+    def as_dict(self):
+        return {"best": self.best.as_dict(), "default": self.dflt.as_dict(), "best_ms": self.best_ms,
+                "default_ms": self.default_ms, "candidates": self.candidates,
+                "value_bucket": self.value_bucket, "level_bucket": self.level_bucket}
 
 
 class mdr_pipeline_info(C.Structure):
@@ -167,6 +187,15 @@ _SIGS = {
     "mdr_server_release": ([_vp, _u64], C.c_int),
     "mdr_server_stats": ([_vp, _P(mdr_server_info)], C.c_int),
     "mdr_server_destroy": ([_vp], None),
+    "mdr_context_set_select_threads": ([_vp, _u32], C.c_int),
+    "mdr_retrieve_qoi": ([C.c_int, _P(_vp), _u32, C.c_int, C.c_double, _P(mdr_qoi_params), _P(_P(_vp)), _vp,
+                          _P(mdr_qoi_info)], C.c_int),
+    "mdr_autotune_refactor": ([_vp, _P(_P(mdr_level_view)), _P(_u32), _u32, C.c_int, _u32,
+                               _P(mdr_codec_params), _vp, _u32, C.c_int, _P(mdr_tune_result)], C.c_int),
+    "mdr_tune_save": ([_vp, C.c_char_p], C.c_int),
+    "mdr_tune_load": ([_vp, C.c_char_p], C.c_int),
+    "mdr_tune_entries": ([_vp, _P(_u32)], C.c_int),
+    "mdr_tune_entry": ([_vp, _u32, _P(_u32), _P(mdr_launch_shape)], C.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -263,6 +292,40 @@ class Context:
         """Refactor launch shape (0 / -1 leave a knob unchanged); see mdr_context_set_launch."""
         _check(_lib.mdr_context_set_launch(self.handle, int(enc_target_wg), int(stats_wg_values),
                                            int(graphs)))
+
+    def set_select_threads(self, threads: int) -> None:
+        """Workgroup size of the selection kernel (256, 512 or 1024)."""
+        _check(_lib.mdr_context_set_select_threads(self.handle, int(threads)))
+
+    def autotune(self, variables, nplanes: int, params: mdr_codec_params | None = None, reps: int = 2,
+                 force: bool = False, stream=None) -> dict:
+        """mdr_autotune_refactor over these variables (lists of device tensors)."""
+        dt = _dtype_code(variables[0][0])
+        keep = [_views(levels, dt)[0] for levels in variables]
+        vp = (_P(mdr_level_view) * len(keep))(*[C.cast(v, _P(mdr_level_view)) for v in keep])
+        nl = (_u32 * len(keep))(*[len(levels) for levels in variables])
+        res = mdr_tune_result()
+        _check(_lib.mdr_autotune_refactor(self.handle, vp, nl, len(keep), dt, nplanes,
+                                          C.byref(params) if params is not None else None,
+                                          _stream_ptr(stream), int(reps), 1 if force else 0, C.byref(res)))
+        return res.as_dict()
+
+    def tune_save(self, path: str) -> None:
+        _check(_lib.mdr_tune_save(self.handle, path.encode()))
+
+    def tune_load(self, path: str) -> None:
+        _check(_lib.mdr_tune_load(self.handle, path.encode()))
+
+    def tune_table(self) -> list:
+        n = _u32()
+        _check(_lib.mdr_tune_entries(self.handle, C.byref(n)))
+        out = []
+        for i in range(n.value):
+            key = (_u32 * 5)()
+            sh = mdr_launch_shape()
+            _check(_lib.mdr_tune_entry(self.handle, i, key, C.byref(sh)))
+            out.append({"key": list(key), "shape": sh.as_dict()})
+        return out
 
     def __del__(self):
         self.close()
@@ -463,6 +526,24 @@ def retrieve_qoi_vtotal(rx: Retriever, ry: Retriever, rz: Retriever, tau: float,
     _check(_lib.mdr_retrieve_qoi_vtotal_with(rx.handle, ry.handle, rz.handle,
                                              MDR_REL if relative else MDR_ABS, float(tau), C.byref(prm),
                                              o[0], o[1], o[2], _stream_ptr(stream), C.byref(info)))
+    return info.as_dict()
+
+
+def retrieve_qoi(family: str, rts, tau: float, outs, relative: bool = False, mape_c: float = 10.0,
+                 stream=None, estimator: str = "mape", cp_decay: float = 0.5) -> dict:
+    """mdr_retrieve_qoi: refine the retrievers until the family's bound
+    ("sumsq" of 1-3 variables, "magnitude" of 1-3, "product" of 2) meets tau."""
+    info = mdr_qoi_info()
+    prm = mdr_qoi_params()
+    prm.estimator = QOI_ESTIMATORS[estimator]
+    prm.mape_c = float(mape_c)
+    prm.cp_decay = float(cp_decay)
+    n = len(rts)
+    hs = (_vp * n)(*[r.handle.value for r in rts])
+    keep = [Retriever._outs(o) for o in outs]
+    op = (_P(_vp) * n)(*[C.cast(o, _P(_vp)) for o in keep])
+    _check(_lib.mdr_retrieve_qoi(QOI_FAMILIES[family], hs, n, MDR_REL if relative else MDR_ABS, float(tau),
+                                 C.byref(prm), op, _stream_ptr(stream), C.byref(info)))
     return info.as_dict()
 
 

@@ -277,6 +277,7 @@ mdr_status mdr_context_create(int hip_device, mdr_context** out)
     auto* c = new mdr_context();
     c->device = hip_device;
     c->pool = std::make_shared<DevicePool>(kPoolCacheBytes);
+    tune_from_env(c);
     *out = c;
     return MDR_OK;
 }
@@ -518,34 +519,85 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
                                         void* const* out_x, void* const* out_y, void* const* out_z,
                                         void* stream, mdr_qoi_info* info)
 {
+    mdr_retriever* const rts[3] = {vx, vy, vz};
+    void* const* const outs[3] = {out_x, out_y, out_z};
+    return mdr_retrieve_qoi(MDR_QOI_SUMSQ, rts, 3, kind, tau, params, outs, stream, info);
+}
+
+}  // extern "C"
+
+namespace {
+
+static_assert(MDR_QOI_SUMSQ == kQoiSumsq && MDR_QOI_MAGNITUDE == kQoiMagnitude && MDR_QOI_PRODUCT == kQoiProduct,
+              "QoI family numbers");
+
+// A family's score at one point from the absolute values a[c] and bounds e[c],
+// in the kernel's order of operations (see k_qoi_batch)
+double qoi_score_at(int kind, uint32_t nv, const double* a, const double* e)
+{
+    if (kind == MDR_QOI_PRODUCT) return ((a[0] * e[1]) + (a[1] * e[0])) + (e[0] * e[1]);
+    double d = 0.0;
+    for (uint32_t c = 0; c < nv; ++c) d = d + e[c] * ((2.0 * a[c]) + e[c]);
+    if (kind == MDR_QOI_SUMSQ) return d;
+    double sh = 0.0;
+    for (uint32_t c = 0; c < nv; ++c) sh = sh + (a[c] * a[c]);
+    return sh == 0.0 ? INFINITY : (d * d) / sh;
+}
+
+// tau' from the largest score: the score itself, or for the magnitude the root
+// of its minimum with sum eps^2; inflated by (1 + 2^-40) for rounding
+double qoi_estimate_of(int kind, uint32_t nv, double score, const double* e)
+{
+    double t = score;
+    if (kind == MDR_QOI_MAGNITUDE) {
+        double s2 = 0.0;
+        for (uint32_t c = 0; c < nv; ++c) s2 = s2 + (e[c] * e[c]);
+        t = std::sqrt(score < s2 ? score : s2);
+    }
+    return t * (1.0 + std::ldexp(1.0, -40));
+}
+
+}  // namespace
+
+extern "C" {
+
+mdr_status mdr_retrieve_qoi(mdr_qoi_kind qkind, mdr_retriever* const* rts, uint32_t nv, mdr_bound kind, double tau,
+                            const mdr_qoi_params* params, void* const* const* outs, void* stream,
+                            mdr_qoi_info* info)
+{
     g_err.clear();
     mdr_qoi_params prm{};
     prm.estimator = MDR_QOI_MAPE;
     if (params) prm = *params;
+    if (qkind != MDR_QOI_SUMSQ && qkind != MDR_QOI_MAGNITUDE && qkind != MDR_QOI_PRODUCT)
+        return fail(MDR_ERR_INVALID_ARG, "unknown QoI family");
+    if (!rts || !outs) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
+    if (qkind == MDR_QOI_PRODUCT ? nv != 2 : (nv < 1 || nv > 3))
+        return fail(MDR_ERR_INVALID_ARG, "a product takes 2 variables, a sum of squares or magnitude 1 to 3");
     if (prm.estimator != MDR_QOI_MAPE && prm.estimator != MDR_QOI_MA && prm.estimator != MDR_QOI_CP)
         return fail(MDR_ERR_INVALID_ARG, "unknown QoI estimator");
     if (!(prm.cp_decay < 1.0)) return fail(MDR_ERR_INVALID_ARG, "cp_decay must be below 1");
     const double mape_c = prm.mape_c;
     const double decay = prm.cp_decay > 0.0 ? prm.cp_decay : 0.5;
     const bool cp = prm.estimator == MDR_QOI_CP;
-    mdr_retriever* rts[3] = {vx, vy, vz};
-    void* const* outs[3] = {out_x, out_y, out_z};
-    for (int c = 0; c < 3; ++c)
+    for (uint32_t c = 0; c < nv; ++c)
         if (!rts[c] || !outs[c]) return fail(MDR_ERR_INVALID_ARG, "NULL argument");
     if (!(tau >= 0.0) || std::isinf(tau)) return fail(MDR_ERR_INVALID_ARG, "tolerance must be finite and >= 0");
     if (kind != MDR_ABS && kind != MDR_REL) return fail(MDR_ERR_INVALID_ARG, "bad bound kind");
-    const mdr_refactored* r0 = vx->r;
-    for (int c = 1; c < 3; ++c) {
+    const mdr_refactored* r0 = rts[0]->r;
+    for (uint32_t c = 1; c < nv; ++c) {
         const mdr_refactored* rc = rts[c]->r;
         if (rc->dtype != r0->dtype || rc->levels.size() != r0->levels.size())
-            return fail(MDR_ERR_INVALID_ARG, "vx, vy, vz must share dtype and level structure");
+            return fail(MDR_ERR_INVALID_ARG, "the variables must share dtype and level structure");
         for (size_t l = 0; l < r0->levels.size(); ++l)
             if (rc->levels[l].n != r0->levels[l].n)
-                return fail(MDR_ERR_INVALID_ARG, "vx, vy, vz must hold the same points per level");
-        if (rts[c]->ctx->device != vx->ctx->device) return fail(MDR_ERR_INVALID_ARG, "retrievers on different devices");
+                return fail(MDR_ERR_INVALID_ARG, "the variables must hold the same points per level");
+        if (rts[c]->ctx->device != rts[0]->ctx->device) return fail(MDR_ERR_INVALID_ARG, "retrievers on different devices");
+        for (uint32_t d = 0; d < c; ++d)
+            if (rts[d] == rts[c]) return fail(MDR_ERR_INVALID_ARG, "a retriever appears twice");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    mdr_context* ctx = vx->ctx;
+    mdr_context* ctx = rts[0]->ctx;
     MDR_HIP(hipSetDevice(ctx->device));
     mdr_status st = ensure_dev(ctx->qacc, 256);
     if (st) return st;
@@ -553,29 +605,40 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
     if (st) return st;
     unsigned long long* acc = static_cast<unsigned long long*>(ctx->qacc.p);
 
-    // initial bounds: eps_c = (tau / Q_max) * range_c
-    double qmax = 0.0, range[3];
-    for (int c = 0; c < 3; ++c) {
-        const mdr_refactored* rc = rts[c]->r;
+    // the family's scale (relative tolerances) and Alg. 3's initial bounds
+    double amax[3] = {0, 0, 0}, range[3] = {0, 0, 0};
+    for (uint32_t c = 0; c < nv; ++c) {
         double lo = 0.0, hi = 0.0;
         bool have = false;
-        for (const LevelRec& L : rc->levels) {
+        for (const LevelRec& L : rts[c]->r->levels) {
             if (L.n == 0) continue;
             if (!have || L.vmin < lo) lo = L.vmin;
             if (!have || L.vmax > hi) hi = L.vmax;
             have = true;
         }
-        double a = std::max(std::fabs(lo), std::fabs(hi));
-        qmax = qmax + a * a;
-        range[c] = value_range(rc);
+        amax[c] = std::max(std::fabs(lo), std::fabs(hi));
+        range[c] = value_range(rts[c]->r);
     }
-    const double tau_abs = kind == MDR_REL ? tau * qmax : tau;
+    double qmax = 0.0;
+    for (uint32_t c = 0; c < nv; ++c) qmax = qmax + amax[c] * amax[c];
+    double scale = qmax;
+    if (qkind == MDR_QOI_MAGNITUDE) scale = std::sqrt(qmax);
+    if (qkind == MDR_QOI_PRODUCT) scale = amax[0] * amax[1];
+    const double tau_abs = kind == MDR_REL ? tau * scale : tau;
+    double e0[3] = {0, 0, 0};
+    for (uint32_t c = 0; c < nv; ++c) {
+        if (qkind == MDR_QOI_SUMSQ)
+            e0[c] = qmax == 0.0 ? 0.0 : (tau_abs / qmax) * range[c];
+        else if (qkind == MDR_QOI_MAGNITUDE)
+            e0[c] = tau_abs / std::sqrt((double)nv);
+        else
+            e0[c] = amax[1 - c] > 0.0 ? tau_abs / (2.0 * amax[1 - c]) : INFINITY;
+    }
     const double cmape = mape_c > 0.0 ? mape_c : 10.0;
     std::vector<uint32_t> ks[3];
-    for (int c = 0; c < 3; ++c) {
+    for (uint32_t c = 0; c < nv; ++c) {
         ks[c] = rts[c]->k;
-        double e0 = qmax == 0.0 ? 0.0 : (tau_abs / qmax) * range[c];
-        plan_to(rts[c]->r, e0, ks[c]);
+        plan_to(rts[c]->r, e0[c], ks[c]);
     }
     const bool f64 = r0->dtype == MDR_F64;
     uint64_t fetched = 0;
@@ -586,30 +649,34 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
         {
             RetrieveTask tk[3];
             mdr_retrieve_info ri[3];
-            for (int c = 0; c < 3; ++c) {
+            for (uint32_t c = 0; c < nv; ++c) {
                 tk[c].rt = rts[c];
                 tk[c].knew = ks[c];
                 tk[c].out = outs[c];
                 tk[c].info = &ri[c];
                 tk[c].all_levels = it == 1;
             }
-            st = retrieve_many(ctx, tk, 3, s);
+            st = retrieve_many(ctx, tk, nv, s);
             if (st) return st;
-            for (int c = 0; c < 3; ++c) {
+            for (uint32_t c = 0; c < nv; ++c) {
                 fetched += ri[c].bytes_fetched;
                 eps[c] = plan_bound(rts[c]->r, ks[c]);
             }
         }
         {
+            // absent components read the first variable with a zero bound (their
+            // terms add exact zeros)
             std::vector<QoiJob> jobs;
             uint64_t base = 0;
             for (size_t l = 0; l < r0->levels.size(); ++l) {
                 QoiJob j{};
-                j.x = out_x[l];
-                j.y = out_y[l];
-                j.z = out_z[l];
+                j.x = outs[0][l];
+                j.y = nv > 1 ? outs[1][l] : outs[0][l];
+                j.z = nv > 2 ? outs[2][l] : outs[0][l];
                 j.n = r0->levels[l].n;
-                for (int c = 0; c < 3; ++c) j.eps[c] = eps[c];
+                for (uint32_t c = 0; c < nv; ++c) j.eps[c] = eps[c];
+                j.kind = (uint32_t)qkind;
+                j.nvars = nv;
                 j.acc = acc;
                 j.arg = acc + 1;
                 j.base = base;
@@ -624,9 +691,9 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
         MDR_HIP(hipStreamSynchronize(s));
         double worst;
         std::memcpy(&worst, hb, 8);
-        tprime = worst * (1.0 + std::ldexp(1.0, -40));
+        tprime = qoi_estimate_of(qkind, nv, worst, eps);
         bool full = true;
-        for (int c = 0; c < 3; ++c)
+        for (uint32_t c = 0; c < nv; ++c)
             for (uint32_t kl : ks[c]) full = full && kl == rts[c]->r->B;
         if (tprime <= tau_abs || full) break;
         // next bounds from the estimator; none: minimal augmentation only
@@ -635,7 +702,7 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
         if (prm.estimator == MDR_QOI_MAPE) {
             const double p = tau_abs > 0.0 ? tprime / tau_abs : INFINITY;
             if (p > cmape) {
-                for (int c = 0; c < 3; ++c) target[c] = eps[c] / p;
+                for (uint32_t c = 0; c < nv; ++c) target[c] = eps[c] / p;
                 have_target = true;
             }
         } else if (cp) {
@@ -647,12 +714,12 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
             if (l == r0->levels.size()) return fail(MDR_ERR_HIP, "internal: no point attains the estimate");
             const size_t es = f64 ? 8 : 4;
             uint8_t* hv = reinterpret_cast<uint8_t*>(hb + 2);
-            for (int c = 0; c < 3; ++c)
+            for (uint32_t c = 0; c < nv; ++c)
                 MDR_HIP(hipMemcpyAsync(hv + 8 * c, static_cast<const uint8_t*>(outs[c][l]) + at * es, es,
                                        hipMemcpyDeviceToHost, s));
             MDR_HIP(hipStreamSynchronize(s));
-            double a[3];
-            for (int c = 0; c < 3; ++c) {
+            double a[3] = {0, 0, 0};
+            for (uint32_t c = 0; c < nv; ++c) {
                 if (f64) {
                     std::memcpy(&a[c], hv + 8 * c, 8);
                 } else {
@@ -664,17 +731,15 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
                 target[c] = eps[c];
             }
             auto at_point = [&](const double* e) {
-                double sum = 0.0;
-                for (int c = 0; c < 3; ++c) sum = sum + e[c] * ((2.0 * a[c]) + e[c]);
-                return sum * (1.0 + std::ldexp(1.0, -40));
+                return qoi_estimate_of(qkind, nv, qoi_score_at(qkind, nv, a, e), e);
             };
             for (int step = 0; step < 2200 && at_point(target) > tau_abs; ++step)
-                for (int c = 0; c < 3; ++c) target[c] = target[c] * decay;
+                for (uint32_t c = 0; c < nv; ++c) target[c] = target[c] * decay;
             have_target = true;
         }
         bool moved = false;
         if (have_target) {
-            for (int c = 0; c < 3; ++c) {
+            for (uint32_t c = 0; c < nv; ++c) {
                 std::vector<uint32_t> knew = ks[c];
                 plan_to(rts[c]->r, target[c], knew);
                 moved = moved || knew != ks[c];
@@ -682,12 +747,12 @@ mdr_status mdr_retrieve_qoi_vtotal_with(mdr_retriever* vx, mdr_retriever* vy, md
             }
         }
         if (!moved)
-            for (int c = 0; c < 3; ++c) plan_step(rts[c]->r, ks[c]);
+            for (uint32_t c = 0; c < nv; ++c) plan_step(rts[c]->r, ks[c]);
     }
     if (info) {
         info->tau_abs = tau_abs;
         info->tau_est = tprime;
-        for (int c = 0; c < 3; ++c) info->eps[c] = eps[c];
+        for (int c = 0; c < 3; ++c) info->eps[c] = c < (int)nv ? eps[c] : 0.0;
         info->bytes_fetched = fetched;
         info->iterations = it;
         info->met = tprime <= tau_abs ? 1 : 0;

@@ -113,34 +113,52 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
     }
 }
 
-// V_total error estimate (Sec. 5.2): with |v - vhat| <= eps_c per component,
-// |v^2 - vhat^2| <= eps_c (2|vhat| + eps_c); the estimate is the maximum over
-// points of the sum over x, y, z, evaluated in double in that order (no
-// contraction: the library is built with -ffp-contract=off).
-// Many (request, level) jobs in one launch; each job folds its maximum into
-// its own accumulator.
+// QoI error estimates (Sec. 5.2).  With |v_c - vhat_c| <= eps_c per variable,
+// each family's score at a point, evaluated in double in this order (no
+// contraction: the library is built with -ffp-contract=off):
+//   sum of squares (V_total for three variables): D = sum_c eps_c (2|vhat_c| + eps_c),
+//     since |v^2 - vhat^2| <= eps (2|vhat| + eps);
+//   magnitude sqrt(sum v_c^2): D^2 / Shat, Shat = (vx^2 + vy^2) + vz^2 (+inf
+//     when Shat = 0), since |M - Mhat| <= |S - Shat| / Mhat; the host takes
+//     the root of its minimum with sum eps_c^2 (the norm of the error vector);
+//   product v_0 v_1: (|vhat_0| eps_1 + |vhat_1| eps_0) + eps_0 eps_1.
+// Absent variables have zero bounds (their terms are exact zeros); the
+// magnitude also leaves them out of Shat.  Many (request, level) jobs in one
+// launch; each job folds its maximum into its own accumulator.
 template <bool F64>
-__global__ __launch_bounds__(kThreads) void k_qoi_vtotal_batch(const QoiJob* __restrict__ jobs,
-                                                               const uint32_t* __restrict__ wg_job)
+__device__ __forceinline__ double qoi_score(const QoiJob& j, double vx, double vy, double vz)
+{
+    const double ex = j.eps[0], ey = j.eps[1], ez = j.eps[2];
+    const double ax = fabs(vx), ay = fabs(vy), az = fabs(vz);
+    if (j.kind == kQoiProduct) {
+        double r = (ax * ey) + (ay * ex);
+        return r + (ex * ey);
+    }
+    double s = 0.0;
+    s = s + ex * ((2.0 * ax) + ex);
+    s = s + ey * ((2.0 * ay) + ey);
+    s = s + ez * ((2.0 * az) + ez);
+    if (j.kind == kQoiSumsq) return s;
+    double sh = vx * vx;
+    if (j.nvars > 1) sh = sh + (vy * vy);
+    if (j.nvars > 2) sh = sh + (vz * vz);
+    return sh == 0.0 ? __builtin_huge_val() : (s * s) / sh;
+}
+
+template <bool F64>
+__global__ __launch_bounds__(kThreads) void k_qoi_batch(const QoiJob* __restrict__ jobs,
+                                                        const uint32_t* __restrict__ wg_job)
 {
     using T = std::conditional_t<F64, double, float>;
     const QoiJob& j = jobs[wg_job[blockIdx.x]];
     const auto x = gmem(static_cast<const T*>(j.x));
     const auto y = gmem(static_cast<const T*>(j.y));
     const auto z = gmem(static_cast<const T*>(j.z));
-    const double ex = j.eps[0], ey = j.eps[1], ez = j.eps[2];
     double worst = 0.0;
     const uint64_t stride = (uint64_t)j.grid * blockDim.x;
     for (uint64_t i = (uint64_t)(blockIdx.x - j.wg_base) * blockDim.x + threadIdx.x; i < j.n; i += stride) {
-        double ax = fabs((double)x[i]), ay = fabs((double)y[i]), az = fabs((double)z[i]);
-        double tx = ex * ((2.0 * ax) + ex);
-        double ty = ey * ((2.0 * ay) + ey);
-        double tz = ez * ((2.0 * az) + ez);
-        double s = 0.0;
-        s = s + tx;
-        s = s + ty;
-        s = s + tz;
-        worst = s > worst ? s : worst;
+        const double sc = qoi_score<F64>(j, (double)x[i], (double)y[i], (double)z[i]);
+        worst = sc > worst ? sc : worst;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -156,32 +174,24 @@ __global__ __launch_bounds__(kThreads) void k_qoi_vtotal_batch(const QoiJob* __r
     }
 }
 
-// The point the CP estimator works on: the smallest index whose estimate,
+// The point the CP estimator works on: the smallest index whose score,
 // evaluated exactly as above, has the bit pattern of the maximum the previous
 // launch left in *acc.
 template <bool F64>
-__global__ __launch_bounds__(kThreads) void k_qoi_vtotal_argmax_batch(const QoiJob* __restrict__ jobs,
-                                                                      const uint32_t* __restrict__ wg_job)
+__global__ __launch_bounds__(kThreads) void k_qoi_argmax_batch(const QoiJob* __restrict__ jobs,
+                                                               const uint32_t* __restrict__ wg_job)
 {
     using T = std::conditional_t<F64, double, float>;
     const QoiJob& j = jobs[wg_job[blockIdx.x]];
     const auto x = gmem(static_cast<const T*>(j.x));
     const auto y = gmem(static_cast<const T*>(j.y));
     const auto z = gmem(static_cast<const T*>(j.z));
-    const double ex = j.eps[0], ey = j.eps[1], ez = j.eps[2];
     const unsigned long long target = *j.acc;
     unsigned long long first = ~0ull;
     const uint64_t stride = (uint64_t)j.grid * blockDim.x;
     for (uint64_t i = (uint64_t)(blockIdx.x - j.wg_base) * blockDim.x + threadIdx.x; i < j.n; i += stride) {
-        double ax = fabs((double)x[i]), ay = fabs((double)y[i]), az = fabs((double)z[i]);
-        double tx = ex * ((2.0 * ax) + ex);
-        double ty = ey * ((2.0 * ay) + ey);
-        double tz = ez * ((2.0 * az) + ez);
-        double s = 0.0;
-        s = s + tx;
-        s = s + ty;
-        s = s + tz;
-        if ((unsigned long long)__double_as_longlong(s) == target) {
+        const double sc = qoi_score<F64>(j, (double)x[i], (double)y[i], (double)z[i]);
+        if ((unsigned long long)__double_as_longlong(sc) == target) {
             first = j.base + i;  // a thread's indices only grow: its first match is its smallest
             break;
         }
@@ -226,9 +236,9 @@ hipError_t launch_qoi_vtotal_argmax_batch(const QoiJob* jobs, const uint32_t* wg
 {
     if (grid == 0) return hipSuccess;
     if (f64)
-        hipLaunchKernelGGL((k_qoi_vtotal_argmax_batch<true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+        hipLaunchKernelGGL((k_qoi_argmax_batch<true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     else
-        hipLaunchKernelGGL((k_qoi_vtotal_argmax_batch<false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+        hipLaunchKernelGGL((k_qoi_argmax_batch<false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     return hipGetLastError();
 }
 
@@ -237,9 +247,9 @@ hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, u
 {
     if (grid == 0) return hipSuccess;
     if (f64)
-        hipLaunchKernelGGL((k_qoi_vtotal_batch<true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+        hipLaunchKernelGGL((k_qoi_batch<true>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     else
-        hipLaunchKernelGGL((k_qoi_vtotal_batch<false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+        hipLaunchKernelGGL((k_qoi_batch<false>), dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
     return hipGetLastError();
 }
 
