@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmdr.so")
-SOURCES = ["k_refactor.hip", "k_lossless.hip", "k_retrieve.hip", "k_ablation.hip", "k_multilevel.hip", "k_l2.hip", "api.cpp", "refactor.cpp", "retrieve.cpp", "server.cpp", "pipeline.cpp", "format.cpp"]
+SOURCES = ["k_refactor.hip", "k_lossless.hip", "k_retrieve.hip", "k_ablation.hip", "k_multilevel.hip", "k_l2.hip", "api.cpp", "refactor.cpp", "retrieve.cpp", "server.cpp", "pipeline.cpp", "format.cpp", "tune.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

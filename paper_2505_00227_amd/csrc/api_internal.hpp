@@ -244,6 +244,24 @@ struct BatchGraph {
 };
 }  // namespace mdr
 
+namespace mdr {
+// one tuning-table entry: key = (dtype, nplanes, group size, floor(log2(values
+// in the pass)), floor(log2(levels in the pass))) and the launch shape to use
+struct TuneEntry {
+    uint32_t key[5];
+    mdr_launch_shape shape;
+    double ms;
+};
+void tune_key(mdr_dtype dtype, uint32_t B, uint32_t m, uint64_t values, uint64_t levels, uint32_t key[5]);
+// the shape a pass with this key runs at: its table entry, else the context's default
+mdr_launch_shape effective_shape(const mdr_context* ctx, const uint32_t key[5]);
+// MDR_AUTOTUNE: tune the pass's key first when the table has no entry for it
+mdr_status tune_on_first_use(mdr_context* ctx, const VarLevels* vars, uint32_t nvars, mdr_dtype dtype,
+                             uint32_t B, const mdr_codec_params& prm, hipStream_t s);
+// MDR_TUNE_CACHE / MDR_AUTOTUNE at context creation
+void tune_from_env(mdr_context* ctx);
+}  // namespace mdr
+
 struct mdr_context {
     int device = 0;
     std::shared_ptr<mdr::DevicePool> pool;  // device memory of refactored data and retrievers
@@ -262,6 +280,12 @@ struct mdr_context {
     // batch refactor: launch shape and captured graphs
     uint32_t enc_target_wg = 2304;   // encoder workgroups a batch aims for
     uint32_t stats_wg_values = 65536;  // values per statistics workgroup (at most kStatsMaxWg per level)
+    uint32_t select_threads = 512;     // selection workgroup size
+    // launch-shape tuning table, its file, and tune-on-first-use
+    std::vector<mdr::TuneEntry> tune;
+    std::string tune_path;
+    bool autotune = false;
+    bool tuning = false;  // inside a sweep: passes use the candidate shape as the default
     bool graphs = true;
     hipStream_t capture_stream = nullptr;
     std::vector<std::unique_ptr<mdr::BatchGraph>> graph_cache;
