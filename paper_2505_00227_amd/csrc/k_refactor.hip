@@ -226,11 +226,14 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     __shared__ uint32_t s_trans[kMaxRows];
     __shared__ uint32_t s_key32[F64 ? 1 : kKeyStride];
     __shared__ unsigned long long s_key64[F64 ? kKeyStride : 1];
-    __shared__ uint32_t s_zero[FAST ? 1 : kThreads];  // sink for zero bytes (one slot per thread)
+    __shared__ uint32_t s_zero[FAST && !F64 ? 1 : kThreads];  // sink for zero bytes (one slot per thread)
     // FAST: the byte histograms at fixed LDS addresses, so each unit's offset is
     // an instruction immediate
     constexpr int FUNITS = F64 ? 17 : 9;  // FAST: units (sign + 16 or 8 groups)
-    __shared__ uint32_t s_hist_fast[FAST ? FUNITS * 256 : 1];
+    // f64 FAST: each unit's 256 bins are followed by one sink slot per lane for
+    // zero bytes (counted by difference), at the same offset from every unit
+    constexpr int HSTRIDE = F64 ? 320 : 256;
+    __shared__ uint32_t s_hist_fast[FAST ? FUNITS * HSTRIDE : 1];
 
     __shared__ uint32_t s_hoff[kMaxRows];  // row -> its unit's histogram offset
     // FAST: each wave's last words of every row for the next wave's first lanes
@@ -240,9 +243,9 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     __shared__ uint32_t s_first64[FAST && F64 ? 4 : 1][kThreads / 64][2][FAST && F64 ? 65 : 1];
     __shared__ uint32_t s_last64[FAST && F64 ? 4 : 1][kThreads / 64][2][FAST && F64 ? 65 : 1];
     uint32_t edge_trc[2] = {0, 0};  // f64 FAST: transitions at the wave's left edge, rows lane and lane + 64
-    uint32_t trc[FAST ? FUNITS : 1];  // FAST: word transitions per unit (f32: this thread's; f64: the wave's)
+    uint32_t trc[FAST && !F64 ? 9 : 1];  // f32 FAST: this thread's word transitions per unit
 #pragma unroll
-    for (int i = 0; i < (FAST ? FUNITS : 1); ++i) trc[i] = 0;
+    for (int i = 0; i < (FAST && !F64 ? 9 : 1); ++i) trc[i] = 0;
     const uint32_t tid = threadIdx.x, lane = tid & 63;
     // every field the tile loop needs, in registers: stores through the row
     // pointer could otherwise alias the job table and force reloads
@@ -260,7 +263,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     uint32_t* s_hist = FAST ? s_hist_fast : s_dyn;
     uint32_t* s_pl = FAST ? s_dyn : s_dyn + nunits * 256;  // [rows of one pass][256]
 
-    for (uint32_t i = tid; i < nunits * 256; i += kThreads) s_hist[i] = 0;
+    for (uint32_t i = tid; i < nunits * (FAST ? HSTRIDE : 256); i += kThreads) s_hist[i] = 0;
     if (tid < kMaxRows) s_trans[tid] = 0;
     if (tid < kKeyStride) {
         if constexpr (F64)
@@ -282,8 +285,13 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
     __syncthreads();
 
     // ---- 32 consecutive values of tile tt (zeros past the level's end)
+    // the u32 word of the tile this thread encodes: its own index, except on
+    // the f64 fast path, where lane l of a wave takes half l / 32 (low half
+    // first) of the wave's W-bit word l % 32, so that the same half of the
+    // previous word is one lane down
+    const uint32_t slot = (FAST && F64) ? ((tid & ~63u) | ((lane & 31u) << 1) | (lane >> 5)) : tid;
     auto load_tile = [&](uint32_t tt, T (&vv)[32]) {
-        const uint32_t b = tt * kTileBlocks + tid;
+        const uint32_t b = tt * kTileBlocks + slot;
         const uint64_t bs = (uint64_t)b * 32;
         if (VEC && b < nbd && bs + 32 <= n) {
             if constexpr (F64) {
@@ -311,7 +319,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         }
     };
     for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t blk = t * kTileBlocks + tid;
+        const uint32_t blk = t * kTileBlocks + slot;
         const bool valid = blk < nbd;
         // the fast path shares nothing between tiles but the edge buffers (four
         // of them), so its waves need no barrier here
@@ -430,23 +438,33 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                     }
                 }
             };
-            if (S12 == (B > 1 ? (1ull << (B - 1)) - 1ull : 0ull))
+            if (S12 == (B > 1 ? (1ull << (B - 1)) - 1ull : 0ull)) {
                 key_pass(std::true_type{});
-            else
+            } else {
                 key_pass(std::false_type{});
-            const uint64_t all = B > 1 ? (1ull << (B - 1)) - 1ull : 0ull;  // cuts 1 .. B-1
-            uint64_t weak = all & ~strong;
-            while (weak) {
-                const int c = __ffsll((unsigned long long)weak);
-                weak &= weak - 1;
-                double km = 0.0;
+                const uint64_t all = B > 1 ? (1ull << (B - 1)) - 1ull : 0ull;  // cuts 1 .. B-1
+                uint64_t weak = all & ~strong;
+                while (weak) {
+                    const int c = __ffsll((unsigned long long)weak);
+                    weak &= weak - 1;
+                    double km = 0.0;
 #pragma unroll
-                for (int j = 0; j < 32; ++j) {
-                    const double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(v[j], -c));
-                    km = key > km ? key : km;
+                    for (int j = 0; j < 32; ++j) {
+                        const double key = __builtin_amdgcn_fract(__builtin_amdgcn_ldexp(v[j], -c));
+                        km = key > km ? key : km;
+                    }
+                    km = wave_max(km);
+                    if (lane == 0) atomicMax(&s_key64[B - c], (unsigned long long)__double_as_longlong(km));
                 }
-                km = wave_max(km);
-                if (lane == 0) atomicMax(&s_key64[B - c], (unsigned long long)__double_as_longlong(km));
+            }
+            // mag = hi:lo (0 when tiny), converted afresh: reusing the key
+            // pass's conversions would keep 64 more registers alive through it
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                asm volatile("" : "+v"(v[j]));
+                const double yh = __builtin_trunc(v[j] * 0x1p-32);
+                hi[j] = (uint32_t)yh;
+                lo[j] = (uint32_t)(v[j] - yh * 0x1p32);
             }
         } else {
             // Cut c = B - k (k = 1..B-1) is bit c-1 of y; k = B is the fraction
@@ -529,15 +547,6 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 asm volatile("" : "+v"(v[j]));
                 lo[j] = (uint32_t)v[j];
             }
-        } else {
-            // the same for f64: mag = hi:lo (0 when tiny)
-#pragma unroll
-            for (int j = 0; j < 32; ++j) {
-                asm volatile("" : "+v"(v[j]));
-                const double yh = __builtin_trunc(v[j] * 0x1p-32);
-                hi[j] = (uint32_t)yh;
-                lo[j] = (uint32_t)(v[j] - yh * 0x1p32);
-            }
         }
         // ---- bit transpose: lo[c] (and hi[c]) become the plane words of bit c (32 + c);
         // row 0 = sign, row r >= 1 = plane r-1 = bit B-r
@@ -545,24 +554,24 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         if constexpr (F64) transpose32(hi);
         if constexpr (FAST && F64) {
             // row r (0..64) is sgn, hi[32 - r] (r <= 32) or lo[64 - r]; unit
-            // of row r is (r + 3) / 4.  A W-bit word is the u32 pair of lanes
-            // 2j, 2j+1 (low half first).  Transitions inside a wave: against
-            // the pair two lanes down (two wave shifts).  At the wave's left
-            // edge: lanes 0, 1 and 62, 63 of every wave leave their words in
-            // LDS, and after the tile's barrier lane r of each wave compares
-            // row r of its first word with the left wave's last word (wave 0:
-            // wave 3 of the previous tile), so the row loop reads no LDS.
-            const uint32_t wave = tid >> 6;
+            // of row r is (r + 3) / 4.  Lanes l and l + 32 hold the halves of
+            // the wave's W-bit word l (l < 32), so the same half of the
+            // previous word comes by one wave shift.  At the wave's left edge:
+            // lanes 0 and 32 (its first word) and 31 and 63 (its last) leave
+            // their words in LDS, and after the tile's barrier lane r of each
+            // wave compares row r of its first word with the left wave's last
+            // (wave 0: wave 3 of the previous tile), so the row loop reads no LDS.
+            const uint32_t wave = tid >> 6, h = lane >> 5, lw32 = lane & 31u;
             const uint32_t par = (t - t0) & 3;  // edge buffers in use, as for f32
 #define MDR_ROW64(r) ((r) == 0 ? sgn : ((r) <= 32 ? hi[32 - (r)] : lo[64 - (r)]))
-            if (lane < 2 || lane >= 62) {
-                uint32_t* dst = lane < 2 ? &s_first64[par][wave][lane][0] : &s_last64[par][wave][lane - 62][0];
+            if (lw32 == 0 || lw32 == 31) {
+                uint32_t* dst = lw32 == 0 ? &s_first64[par][wave][h][0] : &s_last64[par][wave][h][0];
 #pragma unroll
                 for (int r = 0; r <= 64; ++r) dst[r] = MDR_ROW64(r);
             }
-            if (t == t0 && tid < 2) {
+            if (t == t0 && wave == 0 && lw32 == 0) {
 #pragma unroll
-                for (int r = 0; r <= 64; ++r) recs[((uint64_t)wg * kMaxRows + r) * 4 + tid] = MDR_ROW64(r);
+                for (int r = 0; r <= 64; ++r) recs[((uint64_t)wg * kMaxRows + r) * 4 + h] = MDR_ROW64(r);
             }
             if (valid && blk + 2 > last_blk) {
 #pragma unroll
@@ -575,44 +584,53 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
                 // first word (wave 0 of its first tile) has none
                 const uint32_t first_blk = t * kTileBlocks + wave * 64;
                 if (first_blk < nbd && (wave > 0 || t > t0)) {
-                    const uint32_t lp = wave ? par : ((par + 3) & 3), lw = wave ? wave - 1 : 3;
+                    const uint32_t lp = wave ? par : ((par + 3) & 3), lwv = wave ? wave - 1 : 3;
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const uint32_t r = lane + 64u * h;
+                    for (int hh = 0; hh < 2; ++hh) {
+                        const uint32_t r = lane + 64u * hh;
                         if (r <= 64) {
-                            const bool ne = s_first64[par][wave][0][r] != s_last64[lp][lw][0][r] ||
-                                            s_first64[par][wave][1][r] != s_last64[lp][lw][1][r];
-                            edge_trc[h] += ne ? 1u : 0u;
+                            const bool ne = s_first64[par][wave][0][r] != s_last64[lp][lwv][0][r] ||
+                                            s_first64[par][wave][1][r] != s_last64[lp][lwv][1][r];
+                            edge_trc[hh] += ne ? 1u : 0u;
                         }
                     }
                 }
             }
-            const bool even = (lane & 1) == 0;
+            const uint32_t zsink = (256u + lane) * 4u;  // this lane's sink, bytes past a unit's bins
             auto rows_out = [&](auto full_tile) {
                 constexpr bool FULL = decltype(full_tile)::value;
                 uint64_t rb = reinterpret_cast<uint64_t>(job.rows);
                 asm volatile("" : "+s"(rb));
                 const uint32_t boff = blk * 4u;
+                // lanes whose word has a left neighbour in the wave
+                const unsigned long long keep = __ballot((FULL || valid) && lw32 != 0);
+                uint32_t ucnt = 0;  // the current unit's transitions (wave-wide)
 #pragma unroll
                 for (int r = 0; r <= 64; ++r) {
                     const uint32_t w = MDR_ROW64(r);
                     const int unit = (r + 3) / 4;
                     if (FULL || valid) {
                         *gmem(reinterpret_cast<uint32_t*>(rb + boff)) = w;
+                        // nonzero bytes into the unit's bins, zero bytes into this
+                        // lane's sink slot after them (no branches)
+                        uint8_t* hb = reinterpret_cast<uint8_t*>(&s_hist_fast[unit * HSTRIDE]);
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
                             const uint32_t byte = (w >> (8 * q)) & 0xFFu;
-                            if (byte) atomicAdd(&s_hist_fast[unit * 256 + byte], 1u);
+                            atomicAdd(reinterpret_cast<uint32_t*>(hb + (byte ? byte * 4u : zsink)), 1u);
                         }
                     }
-                    // the same half of the previous word: two wave_shr:1 (lane l <- lane
-                    // l-2); lanes 0 and 1 see their own word (counted at the edge above)
+                    // the same half of the previous word: one wave_shr:1 (lanes 0
+                    // and 32 compare at the edge above instead)
                     const int p1 = __builtin_amdgcn_update_dpp((int)w, (int)w, 0x138, 0xF, 0xF, false);
-                    const int p2 = __builtin_amdgcn_update_dpp((int)w, p1, 0x138, 0xF, 0xF, false);
-                    const int ne = (lane >= 2 && (int)w != p2) ? 1 : 0;
-                    // the partner half's verdict: quad_perm [1, 0, 3, 2]
-                    const int ne_pair = ne | __builtin_amdgcn_update_dpp(0, ne, 0xB1, 0xF, 0xF, false);
-                    trc[unit] += (uint32_t)__popcll(__ballot((FULL || valid) && even && ne_pair));
+                    const unsigned long long ne = __ballot((int)w != p1) & keep;
+                    // a word differs if either half does; a unit's count goes to
+                    // its first row's slot (the selection sums a unit's rows)
+                    ucnt += (uint32_t)__popc((uint32_t)ne | (uint32_t)(ne >> 32));
+                    if (r == 0 || r % 4 == 0) {
+                        if (lane == 0 && ucnt) atomicAdd(&s_trans[r == 0 ? 0 : r - 3], ucnt);
+                        ucnt = 0;
+                    }
                     rb += 4ull * nbd;
                 }
             };
@@ -765,11 +783,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
 
     // ---- flush: per-workgroup partials (reduced by the selection kernel)
     if constexpr (FAST && F64) {
-        // wave-wide counts already; a unit's transitions go to its first row's
-        // slot (the selection sums a unit's rows), the edge counts to their row's
-#pragma unroll
-        for (int i = 0; i < FUNITS; ++i)
-            if (lane == 0 && trc[i]) atomicAdd(&s_trans[i == 0 ? 0 : 1 + (i - 1) * 4], trc[i]);
+        // the rows' counts are in their slots already; the edge counts go to their row's
         if (edge_trc[0]) atomicAdd(&s_trans[lane], edge_trc[0]);
         if (lane == 0 && edge_trc[1]) atomicAdd(&s_trans[64], edge_trc[1]);
     } else if constexpr (FAST) {
@@ -805,7 +819,7 @@ __device__ __forceinline__ void encode_body(const EncodeJob& job, const uint32_t
         if (kv) atomicMax(&job.keys[tid], kv);
     }
     for (uint32_t i = tid; i < nunits * 256; i += kThreads) {
-        const uint32_t hv = s_hist[i];
+        const uint32_t hv = s_hist[FAST ? (i >> 8) * HSTRIDE + (i & 255u) : i];
         if (hv) atomicAdd(&job.hist[i], hv);
     }
     if (tid < kMaxRows && s_trans[tid]) atomicAdd(&job.trans[tid], s_trans[tid]);
