@@ -505,19 +505,29 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
             for (uint32_t q = 0; q < kHufGroups; ++q) {
                 if (!ok[q]) continue;
                 uint32_t* buf = bufs + (wpl <= kHufGroups ? (q / wpl) * buf_words : 0);
-                uint32_t p = pos[q];
+                // the word's four codes, concatenated first (at most 4 * 12 bits),
+                // then ORed into the chunk buffer in one to three pieces
+                uint64_t v = 0;
+                uint32_t T = 0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const uint32_t sym = (wv[q] >> (8 * b)) & 0xFF;
-                    const uint32_t Ls = L[sym], cd = C[sym];
-                    const uint32_t wi = p >> 5, o = p & 31;
-                    if (o + Ls <= 32) {
-                        atomicOr(&buf[wi], cd << (32 - o - Ls));
+                    const uint32_t Ls = L[sym];
+                    v = (v << Ls) | C[sym];
+                    T += Ls;
+                }
+                const uint32_t p = pos[q], wi = p >> 5, o = p & 31, head = 32 - o;
+                if (T <= head) {
+                    atomicOr(&buf[wi], (uint32_t)(v << (head - T)));
+                } else {
+                    const uint32_t R = T - head;  // bits after the first word (1 .. 47)
+                    atomicOr(&buf[wi], (uint32_t)(v >> R));
+                    if (R <= 32) {
+                        atomicOr(&buf[wi + 1], (uint32_t)(v << (32 - R)));
                     } else {
-                        atomicOr(&buf[wi], cd >> (o + Ls - 32));
-                        atomicOr(&buf[wi + 1], cd << (64 - o - Ls));
+                        atomicOr(&buf[wi + 1], (uint32_t)(v >> (R - 32)));
+                        atomicOr(&buf[wi + 2], (uint32_t)(v << (64 - R)));
                     }
-                    p += Ls;
                 }
             }
         }
