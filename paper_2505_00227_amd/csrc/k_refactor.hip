@@ -843,9 +843,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     encode_body<true, VEC, FAST>(job, blockIdx.x - job.wg_base);
 }
 
-// the f64 fast path holds no staged rows: four waves per SIMD (128 registers)
+// the f64 fast path: two waves per SIMD (up to 256 registers); at four (128
+// registers) it spilled and ran 12% slower, at three (168) within 4% of two
 template <bool VEC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_encode_f64_fast(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_encode_f64_fast(
     const EncodeJob* __restrict__ jobs, const uint32_t* __restrict__ wg_job)
 {
     const EncodeJob& job = jobs[wg_job[blockIdx.x]];
