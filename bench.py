@@ -695,19 +695,22 @@ def roofline_from(stages, steps, kbytes, workload):
 
 def copy_rate():
     """Measured device-to-device copy bandwidth (read + write) of 256 MiB: the
-    practical ceiling; the same copy scales the FETCH_SIZE / WRITE_SIZE
-    counters when this run is profiled."""
+    practical ceiling.  The copy is a plain elementwise kernel (a negation of
+    2^26 float32 values: 256 MiB read, 256 MiB written), so that it appears in
+    a rocprofv3 counter run as a kernel of known traffic that scales the
+    FETCH_SIZE / WRITE_SIZE counters."""
     import torch
-    ref = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-    ref_copy = ref.clone()
+    ref = torch.zeros(1 << 26, dtype=torch.float32, device="cuda")
+    ref_copy = torch.empty_like(ref)
+    torch.neg(ref, out=ref_copy)  # warm (the first launch loads the kernel)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
     for _ in range(10):
-        ref_copy.copy_(ref)
+        torch.neg(ref, out=ref_copy)
     ev1.record()
     torch.cuda.synchronize()
-    return 2 * ref.numel() * 10 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    return 2 * ref.numel() * 4 * 10 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
 
 
 def cpu_baseline_slab(levels, B, m):
@@ -956,20 +959,7 @@ def bench_field512(args, cfg, steps, warmup, cpu=True):
     elapsed = time.perf_counter() - t0
     stages = ctx.timing(reset=True)
     ctx.set_timing(False)
-    # a plain device copy of known size (256 MiB): the reference that scales the
-    # FETCH_SIZE / WRITE_SIZE counters when this run is profiled
-    ref = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-    ref_copy = ref.clone()
-    torch.cuda.synchronize()
-    # measured device-to-device copy bandwidth (read + write): the practical ceiling
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(10):
-        ref_copy.copy_(ref)
-    ev1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 2 * ref.numel() * 10 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
-    del ref, ref_copy
+    copy_gbps = copy_rate()
 
     ms_step = elapsed / steps * 1e3
     moved = nbytes * (1 + len(w["tols"]))
