@@ -132,3 +132,26 @@ def test_retrieve_batch_matches_oracle(mdr, ctx):
             ref = np.concatenate([np.asarray(a, np.float64) for a in vals])
             assert_same_bits(got, ref, ("var", i, "round", rnd))
             k_prev[i] = k
+
+
+@pytest.mark.parametrize("dtype,B", [(np.float32, 32), (np.float64, 64)])
+@pytest.mark.parametrize("graphs", [False, True])
+def test_large_batch_matches_single_and_oracle(mdr, ctx, dtype, B, graphs):
+    """A pass of more than 2^24 values over several variables (many tiles per
+    encoder workgroup, a replayed graph): every variable equals its own
+    single-variable refactor and the oracle."""
+    ctx.set_launch(graphs=1 if graphs else 0)
+    rng = np.random.default_rng(71)
+    sizes = [workloads.level_sizes((e, e, e), 4) for e in (180, 200, 160)]
+    vs = [workloads.laplace_levels(sz, 1.0 + i, rng, dtype) for i, sz in enumerate(sizes)]
+    assert sum(a.size for v in vs for a in v) >= 1 << 24
+    dev = [upload(v) for v in vs]
+    p = mdr.default_params()
+    say("large batch", np.dtype(dtype).name, "graphs", graphs, [sum(a.size for a in v) for v in vs])
+    for rep in range(2):  # a replay of the captured pass too
+        rs = mdr.refactor_batch(ctx, dev, B, p)
+        for i, (r, v) in enumerate(zip(rs, vs)):
+            single = mdr.refactor(ctx, dev[i], B, p)
+            assert single.serialize() == r.serialize(), ("batch vs single", i, rep)
+    compare_refactor(rs[1], oracle.refactor(vs[1], B, to_oracle_params(p)))
+    ctx.set_launch(graphs=1)
