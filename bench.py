@@ -638,7 +638,10 @@ def unit_table(r, B, m):
 def kernel_bytes(tables, s, B, m, k_retrieved):
     """Algorithmic bytes per pass of each kernel: what its job must move.
 
-    k_encode: read every value, write every plane row (sign + B);
+    k_encode: the refactor's bytes of the method (read every value, write
+    every final stream and the B+1 error bounds; the rows of Huffman- or
+    run-length-coded groups, which the encoder also writes, are intermediate
+    and not counted);
     k_stats: read every value; lossless: read the rows of each coded unit,
     write its payload; k_huf_decode: read the Huffman payloads of the fetched
     units, write their rows; k_reconstruct: read the sign row and the k plane
@@ -646,7 +649,7 @@ def kernel_bytes(tables, s, B, m, k_retrieved):
     enc = stats = lossless = huf = rec = 0
     for t, k in zip(tables, k_retrieved):
         for (n, nbd, units), kl in zip(t, k):
-            enc += n * s + 4 * (B + 1) * nbd
+            enc += n * s + sum(nb for _, nb, _ in units) + (B + 1) * s
             stats += n * s
             fetched = 1 + -(-kl // m) if kl else 0
             for i, (meth, nb, rows) in enumerate(units):
@@ -978,14 +981,15 @@ def bench_field512(args, cfg, steps, warmup, cpu=True):
                                  "bytes_fetched": v[0][1]["bytes_fetched"]}
                 for tol, v in per_tol.items()}
 
-    # roofline of the dominant kernel (the bitplane encoder): algorithmic bytes =
-    # input values + all B+1 plane rows, per launch; time from HIP events on its stream
+    # roofline of the dominant kernel (the bitplane encoder): the refactor's
+    # bytes of the method (values in, final streams and error bounds out), per
+    # launch; time from HIP events on its stream
     enc_ms, enc_n = stages["encode"]
-    plane_bytes = 0
-    for a in levels:
-        nbd = (a.size + 31) // 32
-        plane_bytes += 4 * (B + 1) * nbd
-    enc_bytes_per_step = nbytes + plane_bytes
+    r = mdr.refactor(ctx, dev, B, params)
+    s_bytes = levels[0].itemsize
+    enc_bytes_per_step = sum(n * s_bytes + sum(nb for _, nb, _ in units) + (B + 1) * s_bytes
+                             for n, _, units in unit_table(r, B, m))
+    r.close()
     enc_launches_per_step = enc_n / steps
     achieved = (enc_bytes_per_step * steps) / (enc_ms / 1e3) / 1e9 if enc_ms else 0.0
     rec_ms, rec_n = stages["reconstruct"]
