@@ -129,6 +129,17 @@ mdr_status mdr_context_timing(mdr_context* ctx, double* ms, uint64_t* launches, 
 mdr_status mdr_context_set_launch(mdr_context* ctx, uint32_t enc_target_wg, uint32_t stats_wg_values,
                                   int graphs);
 
+/* Lanes that decode one Huffman chunk in a retrieval (Sec. 4.2's chunked
+ * codes; results do not depend on it, bit for bit).  1: one thread a chunk,
+ * a serial walk of its codes through a table of up to three symbols a
+ * lookup (the launch for many chunks).  4, 8, 16, 32 or 64: the chunk's
+ * bits are cut into that many ranges, decoded at once and brought into step
+ * (a prefix code resynchronises), which shortens a launch with few chunks;
+ * raised to chunk/64 where a stream's chunk needs it.  0 (the default):
+ * chosen per launch, one lane from 3 x 2^24 symbols on, else 16 symbols a
+ * lane (capped at 64 lanes).  Other values: MDR_ERR_INVALID_ARG. */
+mdr_status mdr_context_set_decode_lanes(mdr_context* ctx, uint32_t lanes);
+
 /* ---- Launch-shape autotuner (the batched pass's block and tile shapes) ----
  * A launch shape is the three knobs of the refactor pass: enc_target_wg and
  * stats_wg_values (above) and select_threads, the workgroup size of the

@@ -144,6 +144,7 @@ _SIGS = {
     "mdr_refactor": ([_vp, _P(mdr_level_view), _u32, C.c_int, _u32, _P(mdr_codec_params), _vp,
                       _P(_vp)], C.c_int),
     "mdr_context_set_launch": ([_vp, _u32, _u32, C.c_int], C.c_int),
+    "mdr_context_set_decode_lanes": ([_vp, _u32], C.c_int),
     "mdr_refactor_batch": ([_vp, _P(_P(mdr_level_view)), _P(_u32), _u32, C.c_int, _u32,
                             _P(mdr_codec_params), _vp, _P(_vp)], C.c_int),
     "mdr_refactored_destroy": ([_vp], None),
@@ -292,6 +293,10 @@ class Context:
         """Refactor launch shape (0 / -1 leave a knob unchanged); see mdr_context_set_launch."""
         _check(_lib.mdr_context_set_launch(self.handle, int(enc_target_wg), int(stats_wg_values),
                                            int(graphs)))
+
+    def set_decode_lanes(self, lanes: int) -> None:
+        """Lanes a Huffman chunk is decoded by (0 = per launch, 1, 4..64)."""
+        _check(_lib.mdr_context_set_decode_lanes(self.handle, int(lanes)))
 
     def set_select_threads(self, threads: int) -> None:
         """Workgroup size of the selection kernel (256, 512 or 1024)."""

@@ -399,6 +399,16 @@ mdr_status mdr_context_set_launch(mdr_context* ctx, uint32_t enc_target_wg, uint
     return MDR_OK;
 }
 
+mdr_status mdr_context_set_decode_lanes(mdr_context* ctx, uint32_t lanes)
+{
+    g_err.clear();
+    if (!ctx) return fail(MDR_ERR_INVALID_ARG, "ctx is NULL");
+    if (lanes != 0 && lanes != 1 && lanes != 4 && lanes != 8 && lanes != 16 && lanes != 32 && lanes != 64)
+        return fail(MDR_ERR_INVALID_ARG, "decode lanes must be 0, 1, 4, 8, 16, 32 or 64");
+    ctx->decode_lanes = lanes;
+    return MDR_OK;
+}
+
 void mdr_refactored_destroy(mdr_refactored* r)
 {
     if (!r) return;

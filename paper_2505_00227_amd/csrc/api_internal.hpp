@@ -290,6 +290,8 @@ struct mdr_context {
     hipStream_t capture_stream = nullptr;
     std::vector<std::unique_ptr<mdr::BatchGraph>> graph_cache;
     uint64_t graph_clock = 0;
+    // Huffman decode: lanes per chunk (0 = chosen per launch by its chunk count)
+    uint32_t decode_lanes = 0;
     // job tables of retrieval launches
     mdr::DescSlot ring[mdr::kDescSlots];
     uint32_t ring_next = 0;

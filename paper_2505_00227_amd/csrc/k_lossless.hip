@@ -635,32 +635,21 @@ __global__ __launch_bounds__(kThreads) void k_rle_len(const LosslessArgs* __rest
 }
 
 // ------------------------------------------------------------------ Huffman decode
-// One thread per chunk, kThreads chunks per workgroup.  Every workgroup builds
-// the stream's decode table in LDS from the 256 code lengths of the header: a
-// 2^lmax-entry table mapping the next lmax bits to up to three symbols (every
-// code lying wholly inside the window is decoded by that one lookup; codes are
-// prefix-free, so the bits after a whole code do not change it).  Skewed
-// groups, whose frequent symbols have 1-3 bit codes, take a third of the
-// dependent lookups of a one-symbol table; a 4-byte entry keeps the table at
-// 16 KiB, so that six workgroups fit a CU.  Compressed words are loaded eight
-// ahead of their use, and decoded bytes leave in 16-byte stores.
-__global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
-                                                         const uint32_t* __restrict__ wg_job)
+// The first-code table of a stream, built in LDS by a 256-thread workgroup
+// from the 256 code lengths of its header: entry i of the 2^lmax-entry table
+// holds (length << 8) | symbol of the code that the lmax-bit window i starts
+// with (codes are prefix-free, so the bits after it do not matter).  A window
+// that starts with no code (possible only for an incomplete code) consumes
+// lmax bits as symbol 0.  Ends with a barrier.
+__device__ void build_first_code_table(const uint8_t* __restrict__ payload, uint32_t lmax,
+                                       uint16_t* s_one, uint32_t (*s_wcnt)[kLutBitsMax + 1],
+                                       uint8_t* s_sym)
 {
-    const DecodeJob& job = jobs[wg_job[blockIdx.x]];
-    const uint8_t* payload = job.payload;
-    const uint64_t S = job.S;
-    const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
-    __shared__ uint32_t s_multi[1 << kLutBitsMax];  // symbols | count << 24 | bits << 26
-    __shared__ uint16_t s_one[1 << kLutBitsMax];  // (length << 8) | symbol of the window's first code
-    __shared__ uint32_t s_wcnt[kThreads / 64][kLutBitsMax + 1];  // codes per length, per wavefront
-    __shared__ uint8_t s_sym[256];                // symbols in canonical (length, symbol) order
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t nent = 1u << lmax, mask = nent - 1;
-
-    // ---- canonical code of symbol `tid`: the first code of its length plus
-    // the smaller symbols of that length (wavefront ballots, then the counts
-    // of the earlier wavefronts)
+    const uint32_t nent = 1u << lmax;
+    // canonical code of symbol `tid`: the first code of its length plus the
+    // smaller symbols of that length (wavefront ballots, then the counts of
+    // the earlier wavefronts)
     const uint32_t L = payload[8 + tid];
     const bool has = L != 0 && L <= lmax;
     uint32_t before = 0;
@@ -693,9 +682,7 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
         }
     }
     __syncthreads();
-    // ---- first code of every window (independent entries); a window that
-    // starts with no code (possible only for an incomplete code) consumes
-    // lmax bits as symbol 0
+    // first code of every window (independent entries)
     for (uint32_t i = tid; i < nent; i += kThreads) {
         uint32_t Lx = 1, bx = base[1];
 #pragma unroll
@@ -708,8 +695,33 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
         s_one[i] = code ? (uint16_t)((Lx << 8) | s_sym[bx + (i >> (lmax - Lx))]) : (uint16_t)(lmax << 8);
     }
     __syncthreads();
-    // ---- up to three whole codes per window: chains of first-code lookups,
-    // four windows at a time so their LDS latencies overlap
+}
+
+// The decode tables of a launch, one workgroup per stream, built once and
+// stored to the job's table slot (the decoders' workgroups copy them to LDS
+// instead of each building them).  MULTI: the multi-symbol table of the
+// one-thread decoder, 2^lmax entries mapping the next lmax bits to up to
+// three symbols (every code lying wholly inside the window is decoded by that
+// one lookup): symbols | count << 24 | bits << 26.  Otherwise the first-code
+// table (length << 8 | symbol) of the G-lane decoder.
+template <bool MULTI>
+__global__ __launch_bounds__(kThreads) void k_huf_tables(const DecodeJob* __restrict__ jobs)
+{
+    const DecodeJob& job = jobs[blockIdx.x];
+    const uint32_t lmax = job.lmax, nent = 1u << lmax, mask = nent - 1, tid = threadIdx.x;
+    __shared__ uint16_t s_one[1 << kLutBitsMax];
+    __shared__ uint32_t s_wcnt[kThreads / 64][kLutBitsMax + 1];
+    __shared__ uint8_t s_sym[256];
+    build_first_code_table(job.payload, lmax, s_one, s_wcnt, s_sym);
+    if (!MULTI) {
+        const auto t = gmem(reinterpret_cast<uint32_t*>(job.table));
+        for (uint32_t i = tid; i < nent / 2; i += kThreads)
+            t[i] = reinterpret_cast<const uint32_t*>(s_one)[i];
+        return;
+    }
+    // up to three whole codes per window: chains of first-code lookups, four
+    // windows at a time so their LDS latencies overlap
+    const auto t = gmem(reinterpret_cast<uint32_t*>(job.table));
     for (uint32_t i0 = tid; i0 < nent; i0 += 4 * kThreads) {
         uint32_t syms[4] = {0, 0, 0, 0}, k[4] = {0, 0, 0, 0}, used[4] = {0, 0, 0, 0};
         bool open[4] = {true, true, true, true};
@@ -733,10 +745,37 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t i = i0 + q * kThreads;
-            if (i < nent) s_multi[i] = syms[q] | (k[q] << 24) | (used[q] << 26);
+            if (i < nent) t[i] = syms[q] | (k[q] << 24) | (used[q] << 26);
         }
     }
-    __syncthreads();  // the last barrier
+}
+
+// copies a job's table of `words` 32-bit words to LDS with 16-byte loads
+// (tables sit at 16 KiB strides, and 2^lmax / 2 words is a multiple of 4 for lmax >= 3)
+__device__ __forceinline__ void load_table(const void* table, uint32_t words, uint32_t* lds)
+{
+    const auto src = gmem(reinterpret_cast<const u32x4*>(table));
+    u32x4* dst = reinterpret_cast<u32x4*>(lds);
+    for (uint32_t i = threadIdx.x; i < (words + 3) / 4; i += kThreads) dst[i] = src[i];
+}
+
+// One thread per chunk, kThreads chunks per workgroup (the launch for many
+// chunks), through the multi-symbol table: skewed groups, whose frequent
+// symbols have 1-3 bit codes, take a third of the dependent lookups of a
+// one-symbol table; a 4-byte entry keeps the table at 16 KiB, so that eight
+// workgroups fit a CU.  Compressed words are loaded eight ahead of their use,
+// and decoded bytes leave in 16-byte stores.
+__global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
+                                                         const uint32_t* __restrict__ wg_job)
+{
+    const DecodeJob& job = jobs[wg_job[blockIdx.x]];
+    const uint8_t* payload = job.payload;
+    const uint64_t S = job.S;
+    const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
+    __shared__ __align__(16) uint32_t s_multi[1 << kLutBitsMax];  // symbols | count << 24 | bits << 26
+    const uint32_t tid = threadIdx.x;
+    load_table(job.table, 1u << lmax, s_multi);
+    __syncthreads();  // the only barrier
 
     const uint32_t c = (blockIdx.x - job.wg_base) * kThreads + tid;
     if (c >= nchunks) return;
@@ -838,6 +877,153 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     }
 }
 
+// ------------------------------------------------------------------ Huffman decode, G lanes a chunk
+// For launches with too few chunks to fill the chip, where one thread per
+// chunk leaves a 256-symbol chain of dependent lookups as the launch's
+// latency.  A chunk's compressed bits are cut into G equal ranges and lane g
+// of the chunk's G lanes decodes the codes that start in range g.  Only lane 0
+// knows where its first code starts; lane g > 0 starts at its range's first
+// bit, decodes to past its range's end, and the end it reaches becomes lane
+// g+1's next start, until no start moves.  The chain of starts is then the
+// one a serial decode passes through (lane 0's is right from the first round,
+// and each round makes at least one more lane right, so G rounds always end
+// it; a prefix code falls back into step with the true boundaries within a
+// few codes, so two or three rounds are usual).  A prefix sum of the lanes'
+// counts places their symbols, a last walk writes them to LDS, and the
+// workgroup stores its chunks' bytes with 16-byte stores.
+constexpr uint32_t kSplitOut = 16384;                            // decoded bytes a workgroup holds
+constexpr uint32_t kSplitWords = kSplitOut * kLutBitsMax / 32;   // their compressed words, at most
+constexpr uint32_t kSplitWordsPer = kSplitWords / kThreads;
+
+// Walks the codes of a chunk (words W[qb..ql], bits MSB first) that start in
+// [pos, hi); returns where the walk stops (the start of the first code at or
+// past hi) and their count in n; kWrite: the first `room` symbols go to out.
+template <bool kWrite>
+__device__ __forceinline__ uint32_t huf_walk(const uint32_t* W, uint32_t qb, uint32_t ql,
+                                             const uint16_t* tab, uint32_t lmax, uint32_t pos,
+                                             uint32_t hi, uint32_t& n, uint8_t* out, uint32_t room)
+{
+    uint32_t q = qb + (pos >> 5);
+    const uint32_t sh = pos & 31u;
+    uint64_t buf = ((((uint64_t)W[min(q, ql)]) << 32) | W[min(q + 1, ql)]) << sh;
+    uint32_t nb = 64 - sh;  // valid bits at the top of buf, never fewer than 32 at a lookup
+    q += 2;
+    uint32_t j = 0;
+    while (pos < hi) {
+        if (nb < 32) {
+            buf |= (uint64_t)W[min(q, ql)] << (32 - nb);
+            nb += 32;
+            ++q;
+        }
+        const uint32_t e = tab[buf >> (64 - lmax)];
+        const uint32_t L = e >> 8;
+        if (kWrite && j < room) out[j] = (uint8_t)e;
+        buf <<= L;
+        nb -= L;
+        pos += L;
+        ++j;
+    }
+    n = j;
+    return pos;
+}
+
+// Dynamic LDS of a launch whose largest chunk is cap_chunk symbols: the
+// first-code table, then the compressed words and the decoded bytes of the
+// workgroup's chunks.
+__host__ __device__ constexpr uint32_t split_words_cap(uint32_t cpw, uint32_t cap_chunk)
+{
+    return cpw * cap_chunk * kLutBitsMax / 32;
+}
+__host__ __device__ constexpr uint32_t split_lds_bytes(uint32_t cpw, uint32_t cap_chunk)
+{
+    return (2u << kLutBitsMax) + 4 * split_words_cap(cpw, cap_chunk) + cpw * cap_chunk;
+}
+
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_huf_decode_split(const DecodeJob* __restrict__ jobs,
+                                                               const uint32_t* __restrict__ wg_job,
+                                                               uint32_t cap_chunk)
+{
+    static_assert(G >= 4 && G <= 64 && (G & (G - 1)) == 0, "G lanes a chunk: 4..64, a power of two");
+    constexpr uint32_t kCpw = kThreads / G;  // chunks per workgroup
+    const DecodeJob& job = jobs[wg_job[blockIdx.x]];
+    const uint8_t* payload = job.payload;
+    const uint64_t S = job.S;
+    const uint32_t chunk = job.chunk, lmax = job.lmax, nchunks = job.nchunks;
+    // the launcher sizes LDS for cap_chunk and raises G so that kCpw * cap_chunk <= kSplitOut
+    if (chunk > cap_chunk || kCpw * cap_chunk > kSplitOut) return;
+    extern __shared__ __align__(16) uint8_t s_dyn[];
+    uint16_t* s_one = reinterpret_cast<uint16_t*>(s_dyn);
+    const uint32_t wcap = split_words_cap(kCpw, cap_chunk);
+    uint32_t* s_words = reinterpret_cast<uint32_t*>(s_dyn + (2u << kLutBitsMax));
+    uint8_t* s_out = s_dyn + (2u << kLutBitsMax) + 4 * wcap;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t c0 = (blockIdx.x - job.wg_base) * kCpw, c1 = min(c0 + kCpw, nchunks);
+    const auto off = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader));
+    const auto wp = gmem(reinterpret_cast<const uint32_t*>(payload + kHufHeader + 4ull * (nchunks + 1)));
+    // the workgroup's compressed words (its chunks are adjacent) and the
+    // stream's table, both loads in flight at once
+    const uint32_t w0 = off[c0], nw = min(off[c1] - w0, wcap);
+    uint32_t held[kSplitWordsPer];
+#pragma unroll
+    for (uint32_t r = 0; r < kSplitWordsPer; ++r) {
+        const uint32_t i = tid + r * kThreads;
+        held[r] = i < nw ? wp[w0 + i] : 0u;
+    }
+    load_table(job.table, (1u << lmax) / 2, reinterpret_cast<uint32_t*>(s_one));
+#pragma unroll
+    for (uint32_t r = 0; r < kSplitWordsPer; ++r) {
+        const uint32_t i = tid + r * kThreads;
+        if (i < nw) s_words[i] = held[r];
+    }
+    __syncthreads();
+
+    const uint32_t g = tid % G, cl = tid / G, c = c0 + cl;
+    const bool live = c < c1;
+    uint32_t qb = 0, ql = 0, nbits = 0, cnt = 0;
+    if (live) {
+        qb = min(off[c] - w0, wcap - 1);
+        const uint32_t qe = min(off[c + 1] - w0, wcap);
+        ql = qe > qb ? qe - 1 : qb;
+        nbits = (qe > qb ? qe - qb : 0) * 32;
+        const uint64_t lo = (uint64_t)c * chunk;
+        cnt = (uint32_t)(lo + chunk <= S ? chunk : S - lo);
+    }
+    const uint32_t Lb = (nbits + G - 1) / G;
+    const uint32_t lo_g = min(g * Lb, nbits), hi_g = min(lo_g + Lb, nbits);
+    uint32_t start = lo_g, n = 0;
+    for (int round = 0; round < G; ++round) {
+        const uint32_t end = huf_walk<false>(s_words, qb, ql, s_one, lmax, start, hi_g, n, nullptr, 0);
+        const uint32_t prev = __shfl_up(end, 1, G);
+        // a lane whose range is empty (past the chunk's bits) decodes nothing
+        // from any start: left out, it cannot hold the others up
+        const bool moved = live && g != 0 && lo_g < hi_g && prev != start;
+        if (__ballot(moved) == 0) break;  // every start is the end of the lane before
+        if (moved) start = prev;
+    }
+    uint32_t incl = n;  // inclusive prefix sum of the counts over the chunk's lanes
+#pragma unroll
+    for (uint32_t d = 1; d < (uint32_t)G; d <<= 1) {
+        const uint32_t t = __shfl_up(incl, d, G);
+        if (g >= d) incl += t;
+    }
+    const uint32_t o = incl - n;
+    if (live && o < cnt)
+        huf_walk<true>(s_words, qb, ql, s_one, lmax, start, hi_g, n, s_out + cl * chunk + o, cnt - o);
+    __syncthreads();
+    // the chunks' bytes are adjacent in the output too: a multiple of 4 bytes
+    const uint64_t lo0 = (uint64_t)c0 * chunk;
+    const uint32_t T = (uint32_t)(min((uint64_t)c1 * chunk, S) - lo0);
+    const auto dst4 = gmem(reinterpret_cast<u32x4*>(job.out + lo0));
+    const u32x4* src4 = reinterpret_cast<const u32x4*>(s_out);
+    for (uint32_t i = tid; i < T / 16; i += kThreads) dst4[i] = src4[i];
+    const uint32_t tw = (T & 15u) / 4;
+    if (tid < tw) {
+        const uint32_t i = (T & ~15u) / 4 + tid;
+        gmem(reinterpret_cast<uint32_t*>(job.out + lo0))[i] = reinterpret_cast<const uint32_t*>(s_out)[i];
+    }
+}
+
 // ------------------------------------------------------------------ RLE decode
 __global__ void k_rle_expand(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
                              const uint32_t* starts, uint32_t* g)
@@ -920,11 +1106,45 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
 }
 
 hipError_t launch_huf_decode_batch(const DecodeJob* jobs, uint32_t njobs, const uint32_t* wg_job,
-                                   uint32_t grid, hipStream_t s)
+                                   uint32_t grid, uint32_t lanes, uint32_t cap_chunk, hipStream_t s)
 {
     if (grid == 0 || njobs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_huf_decode, dim3(grid), dim3(kThreads), 0, s, jobs, wg_job);
+    const dim3 P(grid), T(kThreads);
+    if (lanes == 1)
+        hipLaunchKernelGGL(k_huf_tables<true>, dim3(njobs), T, 0, s, jobs);
+    else
+        hipLaunchKernelGGL(k_huf_tables<false>, dim3(njobs), T, 0, s, jobs);
+    switch (lanes) {
+    case 1: hipLaunchKernelGGL(k_huf_decode, P, T, 0, s, jobs, wg_job); break;
+#define MDR_SPLIT(g)                                                                              \
+    case g:                                                                                       \
+        hipLaunchKernelGGL(k_huf_decode_split<g>, P, T, split_lds_bytes(kThreads / g, cap_chunk), s, jobs, \
+                           wg_job, cap_chunk);                                                    \
+        break;
+    MDR_SPLIT(4)
+    MDR_SPLIT(8)
+    MDR_SPLIT(16)
+    MDR_SPLIT(32)
+    MDR_SPLIT(64)
+#undef MDR_SPLIT
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+uint32_t huf_decode_lanes(uint32_t want, uint64_t total_chunks, uint32_t max_chunk)
+{
+    uint32_t g = want;
+    if (g == 0) {
+        // measured on 256-symbol chunks: 16 lanes (16 symbols a lane) were
+        // fastest from 112 to 131040 chunks, 1.3-3.6x faster than one thread a
+        // chunk; at 262080 chunks one thread a chunk was 4% ahead of 8 lanes
+        if (total_chunks * max_chunk >= kHufOneLaneSymbols) return 1;
+        g = min(64u, 16 * max(1u, max_chunk / 256));
+    }
+    if (g == 1) return 1;
+    while (g < 64 && (uint64_t)g * kSplitOut < (uint64_t)kThreads * max_chunk) g <<= 1;  // staging fits
+    return g;
 }
 
 hipError_t launch_rle_decode(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,

@@ -156,13 +156,24 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
 struct DecodeJob {
     const uint8_t* payload;
     uint8_t* out;           // S decoded bytes
+    void* table;            // kHufTableBytes of device scratch, 16-byte aligned: the stream's decode table
     uint64_t S;
     uint32_t nchunks, chunk, lmax;
     uint32_t wg_base;       // first workgroup of this job in the launch
 };
-// kThreads chunks per workgroup; each workgroup builds its job's decode table
+constexpr uint64_t kHufTableBytes = 4ull << kLutBitsMax;  // 2^lmax 32-bit entries at most
+// lanes per chunk: 1 (kThreads chunks per workgroup) or 4..64 (kThreads / lanes
+// chunks per workgroup); cap_chunk: the largest chunk of the jobs.  A first
+// launch builds every job's decode table into its table slot, which the
+// decoding workgroups copy
 hipError_t launch_huf_decode_batch(const DecodeJob* jobs, uint32_t njobs, const uint32_t* wg_job,
-                                   uint32_t grid, hipStream_t s);
+                                   uint32_t grid, uint32_t lanes, uint32_t cap_chunk, hipStream_t s);
+// lanes per chunk for a launch of total_chunks chunks, the largest chunk
+// max_chunk symbols: want = 0 picks by the symbol count (16 symbols a lane
+// below kHufOneLaneSymbols); 1 stays 1; 4..64 is raised where a workgroup's
+// chunks would not fit its LDS staging
+constexpr uint64_t kHufOneLaneSymbols = 196608ull * 256;  // one thread a chunk from this many symbols on
+uint32_t huf_decode_lanes(uint32_t want, uint64_t total_chunks, uint32_t max_chunk);
 // RLE decode: payload u32 nruns | u32 wbytes | symbols[nruns] | u32 lengths[nruns]
 hipError_t launch_rle_decode(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
                              uint8_t* g, uint32_t* temp, hipStream_t s);

@@ -205,9 +205,17 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
 
     // descriptor: decode jobs, reconstruction jobs, workgroup maps
     std::vector<uint32_t> map_dec, map_r[2];
+    uint64_t dec_chunks = 0;
+    uint32_t dec_chunk_max = 0;
+    for (const DecodeJob& d : dec) {
+        dec_chunks += d.nchunks;
+        dec_chunk_max = std::max(dec_chunk_max, d.chunk);
+    }
+    const uint32_t lanes = huf_decode_lanes(ctx->decode_lanes, dec_chunks, dec_chunk_max);
+    const uint32_t cpw = kThreads / lanes;
     for (uint32_t i = 0; i < dec.size(); ++i) {
         dec[i].wg_base = (uint32_t)map_dec.size();
-        map_dec.insert(map_dec.end(), (dec[i].nchunks + kThreads - 1) / kThreads, i);
+        map_dec.insert(map_dec.end(), (dec[i].nchunks + cpw - 1) / cpw, i);
     }
     for (int d = 0; d < 2; ++d)
         for (uint32_t i = 0; i < rj[d].size(); ++i) {
@@ -227,11 +235,14 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
     const uint64_t o_m0 = take(4 * map_r[0].size());
     const uint64_t o_m1 = take(4 * map_r[1].size());
     if (o) {
+        // the decode tables follow the descriptor on the device (never copied)
+        const uint64_t o_tab = o, tab_bytes = kHufTableBytes * dec.size();
         mdr_status st;
-        DescSlot* slot = acquire_slot(ctx, o, st);
+        DescSlot* slot = acquire_slot(ctx, o_tab + tab_bytes, st);
         if (!slot) return st;
         uint8_t* h = static_cast<uint8_t*>(slot->host);
         uint8_t* dv = static_cast<uint8_t*>(slot->dev.p);
+        for (size_t i = 0; i < dec.size(); ++i) dec[i].table = dv + o_tab + kHufTableBytes * i;
         auto put = [&](uint64_t at, const void* src, uint64_t bytes) {
             if (bytes) std::memcpy(h + at, src, bytes);
         };
@@ -246,7 +257,7 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
             StageTimer tm(ctx, MDR_STAGE_HUF_DECODE, s);
             MDR_HIP(launch_huf_decode_batch(reinterpret_cast<const DecodeJob*>(dv + o_dec), (uint32_t)dec.size(),
                                             reinterpret_cast<const uint32_t*>(dv + o_md),
-                                            (uint32_t)map_dec.size(), s));
+                                            (uint32_t)map_dec.size(), lanes, dec_chunk_max, s));
         }
         for (int d = 0; d < 2; ++d) {
             if (map_r[d].empty()) continue;
