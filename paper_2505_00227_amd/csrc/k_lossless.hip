@@ -184,7 +184,17 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
     return v;
 }
 
-// code bits of every Huffman chunk -> chunk_words[c] (words)
+// code bits of every Huffman chunk -> chunk_words[c] (words).  A wavefront
+// walks its share in batches of kCountGroups 64-word groups (lane l loads word
+// l of each: sixteen loads in flight), adds the code lengths of each word's
+// four bytes, and sums the sixteen per-lane values over the wavefront by
+// exchange: at each of the strides 32, 16, 8, 4 a lane keeps half of its
+// values and sends the other half to its partner, so after four rounds lane l
+// holds part of group l / 4, and two more rounds complete it (17 lane
+// exchanges instead of 6 for each group).
+constexpr uint32_t kCountGroups = 16;  // 64-word groups per batch; a chunk is at most 16 groups
+static_assert(4096 / 256 <= kCountGroups, "a chunk of the largest size fits one batch");
+
 __device__ __forceinline__ void huf_count_body(const LosslessArgs& A)
 {
     __shared__ uint32_t s_len[kThreads / 64][256];
@@ -193,7 +203,7 @@ __device__ __forceinline__ void huf_count_body(const LosslessArgs& A)
     if (blockIdx.x == 0 && tid == 0) A.chunk_words[total] = 0;
     uint32_t* L = s_len[wave];
     const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;  // words, groups per chunk
-    const uint32_t cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;   // whole chunks per batch
+    const uint32_t cpb = kCountGroups / wpl;                         // whole chunks per batch
     uint32_t c0, c1;
     wave_share(total, c0, c1);
     uint32_t u = 0, cb_lo = 1, cb_hi = 0;  // chunks [cb_lo, cb_hi) belong to unit u
@@ -211,33 +221,38 @@ __device__ __forceinline__ void huf_count_body(const LosslessArgs& A)
         }
         const auto g = gmem(unit_rows(A, u));
         const uint32_t nbt = min(cpb, min(c1, cb_hi) - c);  // chunks in this batch
-        // one chunk of more than kHufGroups groups goes in several rounds
-        uint32_t acc = 0;
-        for (uint32_t r0 = 0; r0 < (wpl > kHufGroups ? wpl : 1); r0 += kHufGroups) {
-            const uint32_t ng = wpl > kHufGroups ? min(kHufGroups, wpl - r0) : nbt * wpl;
-            const uint64_t w0 = (uint64_t)(c - cb_lo) * cw + (uint64_t)r0 * 64 + lane;
-            uint32_t bits[kHufGroups];
+        const uint32_t ng = nbt * wpl;
+        const uint64_t w0 = (uint64_t)(c - cb_lo) * cw + lane;
+        uint32_t v[kCountGroups], okm = 0;  // okm bit q: word q of this lane lies in the unit
 #pragma unroll
-            for (uint32_t q = 0; q < kHufGroups; ++q) {
-                const uint64_t wi = w0 + q * 64;
-                const bool ok = q < ng && wi < nwu;
-                const uint32_t w = ok ? g[wi] : 0u;
-                bits[q] = ok ? L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24] : 0u;
-            }
+        for (uint32_t q = 0; q < kCountGroups; ++q) {
+            const uint64_t wi = w0 + q * 64;
+            const bool ok = q < ng && wi < nwu;
+            v[q] = ok ? g[wi] : 0u;
+            okm |= ok ? 1u << q : 0u;
+        }
 #pragma unroll
-            for (uint32_t q = 0; q < kHufGroups; ++q) bits[q] = wave_sum_u32(bits[q]);
-            if (wpl > kHufGroups) {
+        for (uint32_t q = 0; q < kCountGroups; ++q) {
+            const uint32_t w = v[q];
+            const uint32_t bits = L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
+            v[q] = (okm >> q) & 1u ? bits : 0u;
+        }
+        // exchange rounds: stride M, half H of the values still held
 #pragma unroll
-                for (uint32_t q = 0; q < kHufGroups; ++q) acc += bits[q];
-            } else {
-                // lane j < nbt: chunk c + j = groups [j wpl, (j + 1) wpl)
-                uint32_t tot = 0;
+        for (uint32_t M = 32, H = kCountGroups / 2; H >= 1; M >>= 1, H >>= 1) {
+            const bool up = (lane & M) != 0;
 #pragma unroll
-                for (uint32_t q = 0; q < kHufGroups; ++q) tot += (q >= lane * wpl && q < (lane + 1) * wpl) ? bits[q] : 0u;
-                if (lane < nbt) A.chunk_words[c + lane] = (tot + 31) / 32;
+            for (uint32_t i = 0; i < H; ++i) {
+                const uint32_t send = up ? v[i] : v[i + H], keep = up ? v[i + H] : v[i];
+                v[i] = keep + __shfl_xor(send, M, 64);
             }
         }
-        if (wpl > kHufGroups && lane == 0) A.chunk_words[c] = (acc + 31) / 32;
+        // lane l holds part of group l / 4: the four lanes of a group, then the
+        // wpl groups of a chunk
+        uint32_t t = v[0];
+        for (uint32_t d = 1; d < 4 * wpl; d <<= 1) t += __shfl_xor(t, d, 64);
+        const uint32_t j = lane / (4 * wpl);  // chunk of the batch whose total lane l holds
+        if ((lane & (4 * wpl - 1)) == 0 && j < nbt) A.chunk_words[c + j] = (t + 31) / 32;
         c += nbt;
     }
 }
@@ -444,12 +459,11 @@ __global__ __launch_bounds__(1024) void k_unit_sizes(const LosslessArgs* __restr
 __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t buf_words)
 {
     extern __shared__ uint32_t s_buf[];  // [kThreads / 64][cpb][buf_words]
-    __shared__ uint32_t s_len[kThreads / 64][256], s_code[kThreads / 64][256];
+    __shared__ uint32_t s_lc[kThreads / 64][256];  // code | length << 16 of each symbol
     if (A.counts[2]) return;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = A.counts[0];
-    uint32_t* L = s_len[wave];
-    uint32_t* C = s_code[wave];
+    uint32_t* LC = s_lc[wave];
     const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;
     const uint32_t cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;
     uint32_t* bufs = s_buf + wave * cpb * buf_words;
@@ -468,10 +482,8 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
             cb_lo = A.chunk_base[u];
             cb_hi = A.chunk_base[u + 1];
             nwu = A.units[u].S / 4;
-            for (uint32_t k = lane; k < 256; k += 64) {
-                L[k] = A.lens[(uint64_t)u * 256 + k];
-                C[k] = A.codes[(uint64_t)u * 256 + k];
-            }
+            for (uint32_t k = lane; k < 256; k += 64)
+                LC[k] = A.codes[(uint64_t)u * 256 + k] | ((uint32_t)A.lens[(uint64_t)u * 256 + k] << 16);
         }
         const uint32_t nbt = min(cpb, min(c1, cb_hi) - c);
         for (uint32_t i = lane; i < nbt * buf_words; i += 64) bufs[i] = 0;
@@ -481,7 +493,7 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
         for (uint32_t r0 = 0; r0 < (wpl > kHufGroups ? wpl : 1); r0 += kHufGroups) {
             const uint32_t ng = wpl > kHufGroups ? min(kHufGroups, wpl - r0) : nbt * wpl;
             const uint64_t w0 = (uint64_t)(c - cb_lo) * cw + (uint64_t)r0 * 64 + lane;
-            uint32_t wv[kHufGroups], pos[kHufGroups];
+            uint32_t wv[kHufGroups], pos[kHufGroups], lc[kHufGroups][4];
             bool ok[kHufGroups];
 #pragma unroll
             for (uint32_t q = 0; q < kHufGroups; ++q) {
@@ -491,8 +503,13 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
             }
 #pragma unroll
             for (uint32_t q = 0; q < kHufGroups; ++q) {
-                const uint32_t w = wv[q];
-                const uint32_t bits = ok[q] ? L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24] : 0u;
+                uint32_t bits = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    lc[q][b] = LC[(wv[q] >> (8 * b)) & 0xFF];
+                    bits += lc[q][b] >> 16;
+                }
+                bits = ok[q] ? bits : 0u;
                 const uint32_t inc = wave_incl_scan(bits, lane);
                 pos[q] = inc - bits;
                 const uint32_t gt = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);  // the group's bits
@@ -511,9 +528,8 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
                 uint32_t T = 0;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const uint32_t sym = (wv[q] >> (8 * b)) & 0xFF;
-                    const uint32_t Ls = L[sym];
-                    v = (v << Ls) | C[sym];
+                    const uint32_t Ls = lc[q][b] >> 16;
+                    v = (v << Ls) | (lc[q][b] & 0xFFFFu);
                     T += Ls;
                 }
                 const uint32_t p = pos[q], wi = p >> 5, o = p & 31, head = 32 - o;
@@ -548,8 +564,8 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
             if (lc == 0) {
                 if (lane == 0) *reinterpret_cast<uint64_t*>(pay) = ui.S;
                 const uint32_t b4 = lane * 4;
-                reinterpret_cast<uint32_t*>(pay + 8)[lane] =
-                    L[b4] | (L[b4 + 1] << 8) | (L[b4 + 2] << 16) | (L[b4 + 3] << 24);
+                reinterpret_cast<uint32_t*>(pay + 8)[lane] = (LC[b4] >> 16) | ((LC[b4 + 1] >> 16) << 8) |
+                                                             ((LC[b4 + 2] >> 16) << 16) | ((LC[b4 + 3] >> 16) << 24);
             }
         }
         sync_wave();  // the buffers are cleared again by the next batch
