@@ -315,6 +315,5 @@ struct mdr_retriever {
     const mdr_refactored* r = nullptr;
     std::vector<uint32_t> k;                      // planes held per level
     std::vector<std::vector<mdr::PoolBuf>> dec;   // [level][slot] decoded non-DC units
-    mdr::PoolBuf temp;                            // RLE decode scratch
     uint64_t bytes_held = 0;
 };

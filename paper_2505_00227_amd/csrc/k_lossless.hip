@@ -10,14 +10,21 @@ namespace {
 constexpr int kScanItems = 4;                          // per thread
 constexpr int kScanTile = kThreads * kScanItems;       // per workgroup
 
+// Inclusive scan over the wavefront with data-parallel moves between lanes (no
+// LDS traffic): within each row of 16 lanes by shifts of 1, 2, 4 and 8 (a lane
+// whose source lies before its row adds 0), then row 0's last lane into row 1
+// and row 2's into row 3, then lane 31 into rows 2 and 3.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
 {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t o = __shfl_up(v, off, 64);
-        if (lane >= (uint32_t)off) v += o;
-    }
-    return v;
+    (void)lane;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+    return (uint32_t)x;
 }
 
 // exclusive scan of one tile; returns the tile total
@@ -1041,17 +1048,40 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode_split(const DecodeJob* 
 }
 
 // ------------------------------------------------------------------ RLE decode
-__global__ void k_rle_expand(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
-                             const uint32_t* starts, uint32_t* g)
+// Every run-length group of a retrieval in one pass of three launches: the run
+// lengths of all groups are gathered into one array, one exclusive scan turns
+// them into run starts (a group's starts are its entries minus its first, so
+// the scan's sums may wrap), and every W-bit word of every group finds its run
+// by binary search over its group's starts.
+__global__ __launch_bounds__(kThreads) void k_rle_gather(const RleJob* __restrict__ jobs,
+                                                         const uint32_t* __restrict__ wg_job,
+                                                         uint32_t* __restrict__ lens)
 {
-    const uint32_t* sym = reinterpret_cast<const uint32_t*>(payload + 8);
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) {
-        // last run whose start is <= i
-        uint64_t lo = 0, hi = nruns;  // invariant: starts[lo] <= i, answer in [lo, hi)
+    const RleJob& job = jobs[wg_job[blockIdx.x]];
+    const uint64_t r0 = (uint64_t)(blockIdx.x - job.wg_gather) * kRlePerWg;
+    const uint64_t r1 = min(r0 + kRlePerWg, job.nruns);
+    const auto src = gmem(reinterpret_cast<const uint32_t*>(job.payload + 8 + 4ull * job.G * job.nruns));
+    for (uint64_t r = r0 + threadIdx.x; r < r1; r += kThreads) lens[job.run_base + r] = src[r];
+}
+
+__global__ __launch_bounds__(kThreads) void k_rle_expand(const RleJob* __restrict__ jobs,
+                                                         const uint32_t* __restrict__ wg_job,
+                                                         const uint32_t* __restrict__ starts)
+{
+    const RleJob& job = jobs[wg_job[blockIdx.x]];
+    const uint32_t* st = starts + job.run_base;
+    const uint32_t s0 = st[0];
+    const auto sym = gmem(reinterpret_cast<const uint32_t*>(job.payload + 8));
+    const auto g = gmem(reinterpret_cast<uint32_t*>(job.out));
+    const uint32_t G = job.G;
+    const uint64_t i0 = (uint64_t)(blockIdx.x - job.wg_expand) * kRlePerWg;
+    const uint64_t i1 = min(i0 + kRlePerWg, job.nwords);
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kThreads) {
+        // last run whose start is <= i (starts relative to the group's first)
+        uint64_t lo = 0, hi = job.nruns;  // invariant: start[lo] <= i, answer in [lo, hi)
         while (hi - lo > 1) {
-            uint64_t mid = (lo + hi) / 2;
-            if (starts[mid] <= i)
+            const uint64_t mid = (lo + hi) / 2;
+            if ((uint64_t)(uint32_t)(st[mid] - s0) <= i)
                 lo = mid;
             else
                 hi = mid;
@@ -1163,17 +1193,15 @@ uint32_t huf_decode_lanes(uint32_t want, uint64_t total_chunks, uint32_t max_chu
     return g;
 }
 
-hipError_t launch_rle_decode(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
-                             uint8_t* g, uint32_t* temp, hipStream_t s)
+hipError_t launch_rle_decode_batch(const RleJob* jobs, const uint32_t* wg_gather, uint32_t n_gather,
+                                   const uint32_t* wg_expand, uint32_t n_expand, uint64_t total_runs,
+                                   uint32_t* lens, uint32_t* starts, uint32_t* temp, hipStream_t s)
 {
-    if (nwords == 0 || nruns == 0) return hipSuccess;
-    const uint32_t* lens = reinterpret_cast<const uint32_t*>(payload + 8 + 4ull * G * nruns);
-    uint32_t* starts = temp;
-    uint32_t* scratch = temp + nruns + 64;
-    hipError_t err = launch_scan_exclusive(lens, starts, nruns, scratch, s);
+    if (n_gather == 0 || n_expand == 0 || total_runs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rle_gather, dim3(n_gather), dim3(kThreads), 0, s, jobs, wg_gather, lens);
+    hipError_t err = launch_scan_exclusive(lens, starts, total_runs, temp, s);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_rle_expand, dim3(blocks_for(nwords, kThreads, 8192)), dim3(kThreads), 0,
-                       s, payload, nwords, G, nruns, starts, reinterpret_cast<uint32_t*>(g));
+    hipLaunchKernelGGL(k_rle_expand, dim3(n_expand), dim3(kThreads), 0, s, jobs, wg_expand, starts);
     return hipGetLastError();
 }
 

@@ -174,9 +174,22 @@ hipError_t launch_huf_decode_batch(const DecodeJob* jobs, uint32_t njobs, const 
 // chunks would not fit its LDS staging
 constexpr uint64_t kHufOneLaneSymbols = 196608ull * 256;  // one thread a chunk from this many symbols on
 uint32_t huf_decode_lanes(uint32_t want, uint64_t total_chunks, uint32_t max_chunk);
-// RLE decode: payload u32 nruns | u32 wbytes | symbols[nruns] | u32 lengths[nruns]
-hipError_t launch_rle_decode(const uint8_t* payload, uint64_t nwords, uint32_t G, uint64_t nruns,
-                             uint8_t* g, uint32_t* temp, hipStream_t s);
+// RLE decode of every run-length group of a retrieval: payload u32 nruns |
+// u32 wbytes | symbols[nruns][G] | u32 lengths[nruns]
+struct RleJob {
+    const uint8_t* payload;
+    uint8_t* out;        // nwords W-bit words (G 32-bit words each)
+    uint64_t nwords, nruns;
+    uint64_t run_base;   // first run of this group in the launch's run arrays
+    uint32_t G;
+    uint32_t wg_gather;  // first workgroup of this group in the gather launch
+    uint32_t wg_expand;  // first workgroup of this group in the expand launch
+};
+constexpr uint32_t kRlePerWg = kThreads * 16;  // runs (gather) or words (expand) per workgroup
+// lens, starts: total_runs u32 each; temp: scan_temp_words(total_runs) u32
+hipError_t launch_rle_decode_batch(const RleJob* jobs, const uint32_t* wg_gather, uint32_t n_gather,
+                                   const uint32_t* wg_expand, uint32_t n_expand, uint64_t total_runs,
+                                   uint32_t* lens, uint32_t* starts, uint32_t* temp, hipStream_t s);
 
 // ---- launchers (k_retrieve.hip) ----
 struct ReconJob {

@@ -97,6 +97,8 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
     // groups entering each plan; state is committed only at the end
     std::vector<Fresh> fresh;
     std::vector<DecodeJob> dec;
+    std::vector<RleJob> rle;
+    uint64_t rle_runs = 0;
     std::vector<uint64_t> fetched(ntasks, 0);
     std::vector<uint32_t> groups(ntasks, 0);
     struct SyncOnFail {
@@ -135,15 +137,18 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
                     dj.lmax = r->prm.huf_lmax;
                     dec.push_back(dj);
                 } else if (ur.method == MDR_RLE) {
-                    const uint64_t need = 4 * (ur.nruns + 64 + scan_temp_words(ur.nruns));
-                    if (rt->temp.bytes < need) {
-                        MDR_HIP(hipStreamSynchronize(s));
-                        hipError_t e2 = rt->temp.alloc(rt->ctx->pool, need);
-                        if (e2 != hipSuccess) return hip_fail(e2, "hipMalloc(decode scratch)");
+                    RleJob rj{};
+                    rj.payload = ur.dev;
+                    rj.out = static_cast<uint8_t*>(f.buf.p);
+                    rj.nwords = ur.S / 4 / G;
+                    rj.nruns = ur.nruns;
+                    rj.G = G;
+                    if (rj.nwords >= (1ull << 32)) return fail(MDR_ERR_UNSUPPORTED, "run-length group of 2^32 words");
+                    if (rj.nwords && rj.nruns) {
+                        rj.run_base = rle_runs;
+                        rle_runs += rj.nruns;
+                        rle.push_back(rj);
                     }
-                    StageTimer tm(ctx, MDR_STAGE_RLE_DECODE, s);
-                    MDR_HIP(launch_rle_decode(ur.dev, ur.S / 4 / G, G, ur.nruns, static_cast<uint8_t*>(f.buf.p),
-                                              static_cast<uint32_t*>(rt->temp.p), s));
                 } else {
                     return fail(MDR_ERR_CORRUPT_STREAM, "unknown lossless method");
                 }
@@ -211,6 +216,13 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
         dec_chunks += d.nchunks;
         dec_chunk_max = std::max(dec_chunk_max, d.chunk);
     }
+    std::vector<uint32_t> map_rg, map_re;
+    for (uint32_t i = 0; i < rle.size(); ++i) {
+        rle[i].wg_gather = (uint32_t)map_rg.size();
+        map_rg.insert(map_rg.end(), (rle[i].nruns + kRlePerWg - 1) / kRlePerWg, i);
+        rle[i].wg_expand = (uint32_t)map_re.size();
+        map_re.insert(map_re.end(), (rle[i].nwords + kRlePerWg - 1) / kRlePerWg, i);
+    }
     const uint32_t lanes = huf_decode_lanes(ctx->decode_lanes, dec_chunks, dec_chunk_max);
     const uint32_t cpw = kThreads / lanes;
     for (uint32_t i = 0; i < dec.size(); ++i) {
@@ -234,11 +246,18 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
     const uint64_t o_md = take(4 * map_dec.size());
     const uint64_t o_m0 = take(4 * map_r[0].size());
     const uint64_t o_m1 = take(4 * map_r[1].size());
+    const uint64_t o_rle = take(sizeof(RleJob) * rle.size());
+    const uint64_t o_mrg = take(4 * map_rg.size());
+    const uint64_t o_mre = take(4 * map_re.size());
     if (o) {
-        // the decode tables follow the descriptor on the device (never copied)
+        // after the descriptor, on the device only (never copied): the decode
+        // tables, then the run lengths, run starts and scan scratch
         const uint64_t o_tab = o, tab_bytes = kHufTableBytes * dec.size();
+        const uint64_t o_lens = o_tab + tab_bytes, o_starts = o_lens + align256(4 * rle_runs);
+        const uint64_t o_stemp = o_starts + align256(4 * rle_runs);
+        const uint64_t dev_bytes = rle_runs ? o_stemp + 4 * scan_temp_words(rle_runs) : o_lens;
         mdr_status st;
-        DescSlot* slot = acquire_slot(ctx, o_tab + tab_bytes, st);
+        DescSlot* slot = acquire_slot(ctx, dev_bytes, st);
         if (!slot) return st;
         uint8_t* h = static_cast<uint8_t*>(slot->host);
         uint8_t* dv = static_cast<uint8_t*>(slot->dev.p);
@@ -252,7 +271,19 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
         put(o_md, map_dec.data(), 4 * map_dec.size());
         put(o_m0, map_r[0].data(), 4 * map_r[0].size());
         put(o_m1, map_r[1].data(), 4 * map_r[1].size());
+        put(o_rle, rle.data(), sizeof(RleJob) * rle.size());
+        put(o_mrg, map_rg.data(), 4 * map_rg.size());
+        put(o_mre, map_re.data(), 4 * map_re.size());
         MDR_HIP(launch_copy_in(dv, h, o, s));
+        if (!rle.empty()) {
+            StageTimer tm(ctx, MDR_STAGE_RLE_DECODE, s);
+            MDR_HIP(launch_rle_decode_batch(reinterpret_cast<const RleJob*>(dv + o_rle),
+                                            reinterpret_cast<const uint32_t*>(dv + o_mrg), (uint32_t)map_rg.size(),
+                                            reinterpret_cast<const uint32_t*>(dv + o_mre), (uint32_t)map_re.size(),
+                                            rle_runs, reinterpret_cast<uint32_t*>(dv + o_lens),
+                                            reinterpret_cast<uint32_t*>(dv + o_starts),
+                                            reinterpret_cast<uint32_t*>(dv + o_stemp), s));
+        }
         if (!map_dec.empty()) {
             StageTimer tm(ctx, MDR_STAGE_HUF_DECODE, s);
             MDR_HIP(launch_huf_decode_batch(reinterpret_cast<const DecodeJob*>(dv + o_dec), (uint32_t)dec.size(),

@@ -188,3 +188,13 @@ def test_empty_level_and_run_twice_identical(mdr, ctx):
     a = mdr.refactor(ctx, upload(levels), 32, params).serialize()
     b = mdr.refactor(ctx, upload(levels), 32, params).serialize()
     assert a == b
+
+
+@pytest.mark.parametrize("m", [1, 4])
+def test_run_length_groups_in_one_pass(mdr, ctx, m):
+    """Every run-length group of a retrieval decodes in one gather / scan /
+    expand pass: groups of one run (constant planes), of long runs, and of
+    words that change at every position, over several levels at once."""
+    levels = [workloads.piecewise_constant_level(seed=90, n=70_000), workloads.ones_runs_level(seed=91, n=150_001),
+              workloads.plain_level(seed=92, n=40_000)]
+    run_case(mdr, ctx, levels, 32, mdr.default_params(group_planes=m, force_method=1), ks=[1, 4, 9, 32])
