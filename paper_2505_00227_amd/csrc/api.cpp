@@ -276,7 +276,13 @@ mdr_status mdr_context_create(int hip_device, mdr_context** out)
     MDR_HIP(l2_scratch_init(hip_device));  // the fixed scratch of mdr_l2_table_noalloc, on this device
     auto* c = new mdr_context();
     c->device = hip_device;
-    c->pool = std::make_shared<DevicePool>(kPoolCacheBytes);
+    // freed device blocks are kept for reuse up to an eighth of the device's
+    // memory (at least kPoolCacheBytes): a resident working set of passes
+    // (plane rows, payload arenas, decoded groups) then cycles through the
+    // cache instead of through hipFree / hipMalloc, which synchronise
+    size_t mem_free = 0, mem_total = 0;
+    MDR_HIP(hipMemGetInfo(&mem_free, &mem_total));
+    c->pool = std::make_shared<DevicePool>(std::max<uint64_t>(kPoolCacheBytes, mem_total / 8));
     tune_from_env(c);
     *out = c;
     return MDR_OK;

@@ -217,7 +217,8 @@ constexpr int kDescSlots = 4;
 struct DescSlot {
     DevBuf dev;
     void* host = nullptr;
-    uint64_t bytes = 0;
+    uint64_t bytes = 0;       // of host (the descriptor)
+    uint64_t dev_bytes = 0;   // of dev (the descriptor and device-only scratch after it)
     hipEvent_t done = nullptr;
     bool pending = false;
     DescSlot() = default;

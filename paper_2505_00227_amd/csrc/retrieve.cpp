@@ -15,7 +15,10 @@ namespace {
 
 // A descriptor slot: pinned host staging plus its device copy.  A slot is
 // reused only after the event recorded behind the kernels that read it.
-DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st)
+// a descriptor slot whose pinned host buffer holds `bytes` and whose device
+// buffer holds `dev_bytes` (>= bytes: device-only scratch follows the
+// descriptor), once the slot's previous launches have finished
+DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, uint64_t dev_bytes, mdr_status& st)
 {
     DescSlot& d = ctx->ring[ctx->ring_next++ % kDescSlots];
     st = MDR_OK;
@@ -44,12 +47,18 @@ DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, mdr_status& st)
             st = hip_fail(e, "hipHostMalloc(descriptor)");
             return nullptr;
         }
-        e = d.dev.alloc(want);
+        d.bytes = want;
+    }
+    dev_bytes = std::max(dev_bytes, bytes);
+    if (d.dev_bytes < dev_bytes) {
+        const uint64_t want = std::max<uint64_t>(dev_bytes + dev_bytes / 2, 64 << 10);
+        d.dev_bytes = 0;
+        hipError_t e = d.dev.alloc(want);
         if (e != hipSuccess) {
             st = hip_fail(e, "hipMalloc(descriptor)");
             return nullptr;
         }
-        d.bytes = want;
+        d.dev_bytes = want;
     }
     return &d;
 }
@@ -257,7 +266,7 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
         const uint64_t o_stemp = o_starts + align256(4 * rle_runs);
         const uint64_t dev_bytes = rle_runs ? o_stemp + 4 * scan_temp_words(rle_runs) : o_lens;
         mdr_status st;
-        DescSlot* slot = acquire_slot(ctx, dev_bytes, st);
+        DescSlot* slot = acquire_slot(ctx, o, dev_bytes, st);
         if (!slot) return st;
         uint8_t* h = static_cast<uint8_t*>(slot->host);
         uint8_t* dv = static_cast<uint8_t*>(slot->dev.p);
@@ -347,7 +356,7 @@ mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const 
     const uint64_t om[2] = {take(4 * maps[0].size()), take(4 * maps[1].size())};
     if (!o) return MDR_OK;
     mdr_status st;
-    DescSlot* slot = acquire_slot(ctx, o, st);
+    DescSlot* slot = acquire_slot(ctx, o, o, st);
     if (!slot) return st;
     uint8_t* h = static_cast<uint8_t*>(slot->host);
     uint8_t* dv = static_cast<uint8_t*>(slot->dev.p);
