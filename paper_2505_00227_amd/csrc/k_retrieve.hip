@@ -145,21 +145,58 @@ __device__ __forceinline__ double qoi_score(const QoiJob& j, double vx, double v
     return sh == 0.0 ? __builtin_huge_val() : (s * s) / sh;
 }
 
+// Points of a job in vectors of 16 bytes (4 f32 or 2 f64 values of each
+// variable), two vectors in flight per thread, then the scalar tail; a
+// variable the family does not use is not read (its bound is 0, its term an
+// exact zero).  F(value index, vx, vy, vz) is called once per point, in index
+// order within each thread.
+template <bool F64, class F>
+__device__ __forceinline__ void qoi_points(const QoiJob& j, F&& f)
+{
+    using T = std::conditional_t<F64, double, float>;
+    using V = std::conditional_t<F64, f64x2, f32x4>;
+    constexpr uint32_t P = 16 / sizeof(T);
+    const auto x = gmem(static_cast<const T*>(j.x));
+    const auto y = gmem(static_cast<const T*>(j.y));
+    const auto z = gmem(static_cast<const T*>(j.z));
+    const bool use_y = j.nvars > 1, use_z = j.nvars > 2;
+    const uint64_t t0 = (uint64_t)(blockIdx.x - j.wg_base) * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)j.grid * blockDim.x;
+    uint64_t done = 0;  // points covered by whole vectors
+    if (j.vec) {
+        const uint64_t nv = j.n / P;
+        const auto xv = gmem(reinterpret_cast<const V*>(static_cast<const T*>(j.x)));
+        const auto yv = gmem(reinterpret_cast<const V*>(static_cast<const T*>(j.y)));
+        const auto zv = gmem(reinterpret_cast<const V*>(static_cast<const T*>(j.z)));
+        const V zero{};
+        for (uint64_t v = t0; v < nv; v += 2 * stride) {
+            const uint64_t w = v + stride;
+            const bool two = w < nv;
+            const V ax = xv[v], ay = use_y ? yv[v] : zero, az = use_z ? zv[v] : zero;
+            const V bx = two ? xv[w] : zero, by = two && use_y ? yv[w] : zero, bz = two && use_z ? zv[w] : zero;
+#pragma unroll
+            for (uint32_t q = 0; q < P; ++q) f(v * P + q, (double)ax[q], (double)ay[q], (double)az[q]);
+            if (two) {
+#pragma unroll
+                for (uint32_t q = 0; q < P; ++q) f(w * P + q, (double)bx[q], (double)by[q], (double)bz[q]);
+            }
+        }
+        done = nv * P;
+    }
+    for (uint64_t i = done + t0; i < j.n; i += stride)
+        f(i, (double)x[i], use_y ? (double)y[i] : 0.0, use_z ? (double)z[i] : 0.0);
+}
+
 template <bool F64>
 __global__ __launch_bounds__(kThreads) void k_qoi_batch(const QoiJob* __restrict__ jobs,
                                                         const uint32_t* __restrict__ wg_job)
 {
-    using T = std::conditional_t<F64, double, float>;
     const QoiJob& j = jobs[wg_job[blockIdx.x]];
-    const auto x = gmem(static_cast<const T*>(j.x));
-    const auto y = gmem(static_cast<const T*>(j.y));
-    const auto z = gmem(static_cast<const T*>(j.z));
     double worst = 0.0;
-    const uint64_t stride = (uint64_t)j.grid * blockDim.x;
-    for (uint64_t i = (uint64_t)(blockIdx.x - j.wg_base) * blockDim.x + threadIdx.x; i < j.n; i += stride) {
-        const double sc = qoi_score<F64>(j, (double)x[i], (double)y[i], (double)z[i]);
+    qoi_points<F64>(j, [&](uint64_t, double vx, double vy, double vz) {
+        const double sc = qoi_score<F64>(j, vx, vy, vz);
         worst = sc > worst ? sc : worst;
-    }
+    });
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         double o = __shfl_xor(worst, off, 64);
@@ -181,21 +218,14 @@ template <bool F64>
 __global__ __launch_bounds__(kThreads) void k_qoi_argmax_batch(const QoiJob* __restrict__ jobs,
                                                                const uint32_t* __restrict__ wg_job)
 {
-    using T = std::conditional_t<F64, double, float>;
     const QoiJob& j = jobs[wg_job[blockIdx.x]];
-    const auto x = gmem(static_cast<const T*>(j.x));
-    const auto y = gmem(static_cast<const T*>(j.y));
-    const auto z = gmem(static_cast<const T*>(j.z));
     const unsigned long long target = *j.acc;
     unsigned long long first = ~0ull;
-    const uint64_t stride = (uint64_t)j.grid * blockDim.x;
-    for (uint64_t i = (uint64_t)(blockIdx.x - j.wg_base) * blockDim.x + threadIdx.x; i < j.n; i += stride) {
-        const double sc = qoi_score<F64>(j, (double)x[i], (double)y[i], (double)z[i]);
-        if ((unsigned long long)__double_as_longlong(sc) == target) {
-            first = j.base + i;  // a thread's indices only grow: its first match is its smallest
-            break;
-        }
-    }
+    qoi_points<F64>(j, [&](uint64_t i, double vx, double vy, double vz) {
+        const double sc = qoi_score<F64>(j, vx, vy, vz);
+        const unsigned long long at = j.base + i;
+        if ((unsigned long long)__double_as_longlong(sc) == target && at < first) first = at;
+    });
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const unsigned long long o = __shfl_xor(first, off, 64);

@@ -218,6 +218,7 @@ struct QoiJob {
     uint64_t base;            // index of the job's first point in its variable
     uint32_t kind, nvars;     // QoI family (kQoi*) and its variables (absent ones: zero bounds)
     uint32_t wg_base, grid;   // this job's workgroups in the launch
+    uint32_t vec;             // x, y and z are 16-byte aligned (set by the launcher)
 };
 hipError_t launch_qoi_vtotal_batch(const QoiJob* jobs, const uint32_t* wg_job, uint32_t grid, bool f64,
                                    hipStream_t s);

@@ -13,11 +13,10 @@ namespace mdr {
 
 namespace {
 
-// A descriptor slot: pinned host staging plus its device copy.  A slot is
-// reused only after the event recorded behind the kernels that read it.
-// a descriptor slot whose pinned host buffer holds `bytes` and whose device
-// buffer holds `dev_bytes` (>= bytes: device-only scratch follows the
-// descriptor), once the slot's previous launches have finished
+// A descriptor slot: pinned host staging plus its device copy, whose host
+// buffer holds `bytes` and whose device buffer holds `dev_bytes` (>= bytes:
+// device-only scratch follows the descriptor).  A slot is reused only after
+// the event recorded behind the kernels that read it.
 DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, uint64_t dev_bytes, mdr_status& st)
 {
     DescSlot& d = ctx->ring[ctx->ring_next++ % kDescSlots];
@@ -341,6 +340,8 @@ mdr_status enqueue_qoi(mdr_context* ctx, const std::vector<QoiJob>& jobs, const 
         if (jobs[i].n == 0) continue;
         const int d = f64[i] ? 1 : 0;
         QoiJob j = jobs[i];
+        const auto a16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; };
+        j.vec = a16(j.x) && a16(j.y) && a16(j.z) ? 1u : 0u;
         j.grid = (uint32_t)std::min<uint64_t>(1024, (j.n + kThreads * 8 - 1) / (kThreads * 8));
         j.wg_base = (uint32_t)maps[d].size();
         maps[d].insert(maps[d].end(), j.grid, (uint32_t)js[d].size());

@@ -294,6 +294,8 @@ mdr_status step(mdr_server* S)
                 j.z = q->outp[2][l];
                 j.n = r0->levels[l].n;
                 for (int c = 0; c < 3; ++c) j.eps[c] = q->eps[c];
+                j.kind = kQoiSumsq;  // V_total: the sum of squares of three variables
+                j.nvars = 3;
                 j.acc = acc + slot_of[i];
                 jobs.push_back(j);
                 f64.push_back(r0->dtype == MDR_F64);
