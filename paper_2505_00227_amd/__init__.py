@@ -438,18 +438,42 @@ def refactor(ctx: Context, levels, nplanes: int, params: mdr_codec_params | None
     return Refactored(ctx, h)
 
 
+class BatchViews:
+    """The marshalled level views of a batch of variables (each a list of
+    contiguous device tensors of one dtype), built once for passes repeated on
+    the same tensors; it holds the tensors, so they stay allocated."""
+
+    def __init__(self, variables):
+        if not variables:
+            raise ValueError("no variables")
+        self.variables = [list(v) for v in variables]
+        self.dt = _dtype_code(self.variables[0][0])
+        self._keep = [_views(levels, self.dt)[0] for levels in self.variables]
+        self.vp = (_P(mdr_level_view) * len(self._keep))(*[C.cast(v, _P(mdr_level_view)) for v in self._keep])
+        self.nl = (_u32 * len(self._keep))(*[len(levels) for levels in self.variables])
+        self.n = len(self._keep)
+
+
+class BatchOutputs:
+    """The marshalled output pointers of a batch retrieval (per variable, one
+    device tensor per level), built once for retrievals repeated into the
+    same tensors; it holds the tensors."""
+
+    def __init__(self, outs_per_var):
+        self.outs = [list(o) for o in outs_per_var]
+        self._keep = [Retriever._outs(o) for o in self.outs]
+        self.op = (_P(_vp) * len(self._keep))(*[C.cast(o, _P(_vp)) for o in self._keep])
+        self.n = len(self._keep)
+
+
 def refactor_batch(ctx: Context, variables, nplanes: int, params: mdr_codec_params | None = None,
                    stream=None) -> list:
     """mdr_refactor_batch: one pass over every level of every variable (each a
-    list of contiguous device tensors of one dtype); returns one Refactored each."""
-    if not variables:
-        raise ValueError("no variables")
-    dt = _dtype_code(variables[0][0])
-    keep = [_views(levels, dt)[0] for levels in variables]
-    vp = (_P(mdr_level_view) * len(keep))(*[C.cast(v, _P(mdr_level_view)) for v in keep])
-    nl = (_u32 * len(keep))(*[len(levels) for levels in variables])
-    hs = (_vp * len(keep))()
-    _check(_lib.mdr_refactor_batch(ctx.handle, vp, nl, len(keep), dt, nplanes,
+    list of contiguous device tensors of one dtype, or a BatchViews of them);
+    returns one Refactored each."""
+    bv = variables if isinstance(variables, BatchViews) else BatchViews(variables)
+    hs = (_vp * bv.n)()
+    _check(_lib.mdr_refactor_batch(ctx.handle, bv.vp, bv.nl, bv.n, bv.dt, nplanes,
                                    C.byref(params) if params is not None else None,
                                    _stream_ptr(stream), hs))
     return [Refactored(ctx, _vp(h)) for h in hs]
@@ -505,14 +529,16 @@ class Retriever:
 
 
 def retrieve_batch(rts, tols, outs_per_var, relative: bool = True, stream=None) -> list:
-    """mdr_retrieve_batch: retriever i to tols[i], writing outs_per_var[i] (per level)."""
+    """mdr_retrieve_batch: retriever i to tols[i], writing outs_per_var[i] (per
+    level; or a BatchOutputs of them)."""
     n = len(rts)
     hs = (_vp * n)(*[r.handle.value for r in rts])
     tl = (C.c_double * n)(*[float(t) for t in tols])
-    keep = [Retriever._outs(o) for o in outs_per_var]
-    op = (_P(_vp) * n)(*[C.cast(o, _P(_vp)) for o in keep])
+    bo = outs_per_var if isinstance(outs_per_var, BatchOutputs) else BatchOutputs(outs_per_var)
+    if bo.n != n:
+        raise ValueError("one output list per retriever")
     infos = (mdr_retrieve_info * n)()
-    _check(_lib.mdr_retrieve_batch(hs, n, MDR_REL if relative else MDR_ABS, tl, op,
+    _check(_lib.mdr_retrieve_batch(hs, n, MDR_REL if relative else MDR_ABS, tl, bo.op,
                                    _stream_ptr(stream), infos))
     return [i.as_dict() for i in infos]
 
