@@ -134,6 +134,47 @@ def test_retrieve_batch_matches_oracle(mdr, ctx):
             k_prev[i] = k
 
 
+def test_prepared_views_repeat_passes(mdr, ctx):
+    """BatchViews / BatchOutputs marshal a batch once: passes repeated through
+    them equal passes marshalled per call, for new data in the same tensors too,
+    and the prepared objects keep their tensors alive."""
+    import gc
+    vs = _mixed_vars(53, np.float32, nvars=4)
+    p = mdr.default_params()
+    dev = [upload(v) for v in vs]
+    bv = mdr.BatchViews(dev)
+    outs = [gpu_outputs(v) for v in vs]
+    bo = mdr.BatchOutputs(outs)
+    del outs
+    gc.collect()
+    for rnd in range(2):
+        if rnd:  # new values in the same device tensors
+            rng = np.random.default_rng(54)
+            vs = [[rng.laplace(0, 1, a.size).astype(np.float32) for a in v] for v in vs]
+            for d, v in zip(dev, vs):
+                for t, a in zip(d, v):
+                    t.copy_(torch_from(a))
+        say("prepared views round", rnd)
+        a = [r.serialize() for r in mdr.refactor_batch(ctx, bv, 32, p)]
+        rs = mdr.refactor_batch(ctx, dev, 32, p)
+        assert [r.serialize() for r in rs] == a
+        rts = [mdr.Retriever(ctx, r) for r in rs]
+        infos = mdr.retrieve_batch(rts, [1e-3] * len(rts), bo)
+        orc = [oracle.refactor(v, 32, to_oracle_params(p)) for v in vs]
+        for i, v in enumerate(vs):
+            vals, k, bound, met = oracle.retrieve_to(orc[i], 1e-3)
+            assert rts[i].planes() == list(k) and infos[i]["bound"] == bound
+            got = np.concatenate([host(o).astype(np.float64) for o in bo.outs[i]])
+            assert_same_bits(got, np.concatenate([np.asarray(x, np.float64) for x in vals]), ("var", i))
+    with pytest.raises(ValueError):
+        mdr.retrieve_batch(rts[:2], [1e-3] * 2, bo)
+
+
+def torch_from(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
 @pytest.mark.parametrize("dtype,B", [(np.float32, 32), (np.float64, 64)])
 @pytest.mark.parametrize("graphs", [False, True])
 def test_large_batch_matches_single_and_oracle(mdr, ctx, dtype, B, graphs):
