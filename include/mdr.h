@@ -517,7 +517,9 @@ mdr_status mdr_ablation_decode(int32_t design, const uint32_t* planes, uint64_t 
  * was refactored from (`levels`, nlevels and each n as given to mdr_refactor;
  * device memory, borrowed), keeps them in `r`, and waits for `stream`.
  * Mismatched counts or sizes, NULL, misaligned or non-device data:
- * MDR_ERR_INVALID_ARG.  A deserialized object has no table until this runs.
+ * MDR_ERR_INVALID_ARG; so are values whose largest |x| in some level differs
+ * from the refactored level's (other data than `r` was refactored from: no
+ * table is kept).  A deserialized object has no table until this runs.
  * mdr_refactored_l2: copies level `level`'s table (nplanes + 1 doubles) to
  * host memory; MDR_ERR_INVALID_ARG if there is none.
  * With the tables, mdr_retrieve(kind = MDR_L2, tol) plans the fewest groups
@@ -530,7 +532,7 @@ mdr_status mdr_refactored_l2(const mdr_refactored* r, uint32_t level, double* E2
  * memory (tight serving loops, harnesses that forbid hipMalloc).  Same
  * arguments, tables and errors, computed by the same kernels (bit-identical
  * tables); the partial sums and tables live in a fixed scratch array of the
- * library (552,960 bytes per device, resolved once per device by
+ * library (574,464 bytes per device, resolved once per device by
  * mdr_context_create and held until the process ends) instead of pool memory,
  * and no hipMalloc, hipFree or allocating library routine is called.
  * nlevels above 64: MDR_ERR_UNSUPPORTED.  Every call on one device shares that

@@ -975,23 +975,35 @@ mdr_status l2_run(mdr_refactored* r, const mdr_level_view* levels, uint32_t nlev
     const uint32_t B = r->B;
     hipError_t err = hipSuccess;
     const char* what = nullptr;
+    const size_t W = (size_t)B + 2;  // a level's row: the table, then the largest |x| read
     for (uint32_t l = 0; l < nlevels && err == hipSuccess; ++l) {
         if (levels[l].n == 0) continue;
         // the next level reuses the partial sums: the launches stay in stream order
         err = launch_l2_table(r->dtype == MDR_F64, levels[l].data, levels[l].n, r->levels[l].e, B, part,
-                              out + (size_t)l * (B + 1), s);
+                              out + (size_t)l * W, s);
         what = "launch_l2_table";
     }
-    // one copy of every level's table (a copy to pageable memory costs a staging round trip each)
+    // one copy of every level's row (a copy to pageable memory costs a staging round trip each)
     if (err == hipSuccess && nmax) {
-        err = hipMemcpyAsync(host, out, (size_t)nlevels * (B + 1) * 8, hipMemcpyDeviceToHost, s);
+        err = hipMemcpyAsync(host, out, (size_t)nlevels * W * 8, hipMemcpyDeviceToHost, s);
         what = "hipMemcpyAsync(tables)";
     }
     const hipError_t es = hipStreamSynchronize(s);
     if (err != hipSuccess) return hip_fail(err, what);
     if (es != hipSuccess) return hip_fail(es, "hipStreamSynchronize");
+    // the values must be the refactored ones: the largest |x| the tables read
+    // equals the level's from the refactor, else no table is installed (a
+    // table of other data would make an L2 bound a false guarantee)
     for (uint32_t l = 0; l < nlevels; ++l) {
-        double* t = host + (size_t)l * (B + 1);
+        const LevelRec& L = r->levels[l];
+        if (levels[l].n == 0) continue;
+        const double amax = std::max(std::fabs(L.vmin), std::fabs(L.vmax));
+        if (host[(size_t)l * W + B + 1] != amax)
+            return fail(MDR_ERR_INVALID_ARG, "level " + std::to_string(l) +
+                                                 ": the values differ from the refactored ones (largest |x|)");
+    }
+    for (uint32_t l = 0; l < nlevels; ++l) {
+        double* t = host + (size_t)l * W;
         if (levels[l].n == 0) std::fill(t, t + B + 1, 0.0);
         r->levels[l].E2.assign(t, t + B + 1);
     }
@@ -1011,9 +1023,9 @@ mdr_status mdr_l2_table(mdr_refactored* r, const mdr_level_view* levels, uint32_
     const uint32_t B = r->B;
     MDR_HIP(hipSetDevice(r->ctx->device));
     PoolBuf part, out;
-    MDR_HIP(part.alloc(r->ctx->pool, (uint64_t)l2_table_workgroups(nmax) * (B + 1) * 8));
-    MDR_HIP(out.alloc(r->ctx->pool, (uint64_t)nlevels * (B + 1) * 8));
-    std::vector<double> host((size_t)nlevels * (B + 1), 0.0);
+    MDR_HIP(part.alloc(r->ctx->pool, (uint64_t)l2_table_workgroups(nmax) * (B + 2) * 8));
+    MDR_HIP(out.alloc(r->ctx->pool, (uint64_t)nlevels * (B + 2) * 8));
+    std::vector<double> host((size_t)nlevels * (B + 2), 0.0);
     return l2_run(r, levels, nlevels, nmax, static_cast<double*>(part.p), static_cast<double*>(out.p), host.data(),
                   static_cast<hipStream_t>(stream));
 }
@@ -1030,7 +1042,7 @@ mdr_status mdr_l2_table_noalloc(mdr_refactored* r, const mdr_level_view* levels,
     MDR_HIP(hipSetDevice(r->ctx->device));
     double *part = nullptr, *out = nullptr;
     MDR_HIP(l2_scratch(r->ctx->device, &part, &out));
-    double host[kL2NoAllocLevels * 65];  // nlevels * (B + 1) <= 64 * 65
+    double host[kL2NoAllocLevels * kL2RowMax];  // nlevels * (B + 2) <= 64 * 66
     return l2_run(r, levels, nlevels, nmax, part, out, host, static_cast<hipStream_t>(stream));
 }
 

@@ -20,8 +20,10 @@ namespace {
 
 constexpr uint32_t kL2 = 256;  // threads per workgroup
 
-// table entries KLO..KHI (and <= B) of every workgroup's partial row; f64
-// tables run as two launches so that a thread holds at most 33 accumulators
+// table entries KLO..KHI (and <= B) of every workgroup's partial row (B + 2
+// entries: E2[0..B], then the largest |x| the workgroup read, written by the
+// KLO = 0 launch); f64 tables run as two launches so that a thread holds at
+// most 33 accumulators
 template <typename T, int KLO, int KHI>
 __global__ __launch_bounds__(kL2) void k_l2_partial(const T* __restrict__ x, uint64_t n, int e, uint32_t B,
                                                     double* __restrict__ part)
@@ -29,12 +31,15 @@ __global__ __launch_bounds__(kL2) void k_l2_partial(const T* __restrict__ x, uin
 #pragma clang fp contract(off)
     constexpr int KN = KHI - KLO + 1;
     __shared__ double red[kL2 / 64][KN];
+    __shared__ double s_amax[kL2 / 64];
     double acc[KN];
 #pragma unroll
     for (int j = 0; j < KN; ++j) acc[j] = 0.0;
+    double amax = 0.0;
     const uint64_t stride = (uint64_t)gridDim.x * kL2;
     for (uint64_t i = (uint64_t)blockIdx.x * kL2 + threadIdx.x; i < n; i += stride) {
         const double a = std::fabs((double)x[i]);
+        if (KLO == 0) amax = a > amax ? a : amax;
 #pragma unroll
         for (int j = 0; j < KN; ++j) {
             const int k = KLO + j;
@@ -53,32 +58,51 @@ __global__ __launch_bounds__(kL2) void k_l2_partial(const T* __restrict__ x, uin
         for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
         if (lane == 0) red[wave][j] = v;
     }
+    if (KLO == 0) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const double v = __shfl_xor(amax, o, 64);
+            amax = v > amax ? v : amax;
+        }
+        if (lane == 0) s_amax[wave] = amax;
+    }
     __syncthreads();
     const uint32_t k = KLO + threadIdx.x;
     if (threadIdx.x < (uint32_t)KN && k <= B) {
         double v = 0.0;
 #pragma unroll
         for (uint32_t w = 0; w < kL2 / 64; ++w) v += red[w][threadIdx.x];
-        part[(uint64_t)blockIdx.x * (B + 1) + k] = v;
+        part[(uint64_t)blockIdx.x * (B + 2) + k] = v;
+    }
+    if (KLO == 0 && threadIdx.x == 0) {
+        double m = 0.0;
+        for (uint32_t w = 0; w < kL2 / 64; ++w) m = s_amax[w] > m ? s_amax[w] : m;
+        part[(uint64_t)blockIdx.x * (B + 2) + B + 1] = m;
     }
 }
 
+// out[0..B]: the table (workgroup rows summed in index order); out[B + 1]: the
+// largest |x| read, which the caller checks against the refactored level's
 __global__ void k_l2_final(const double* __restrict__ part, uint32_t nwg, uint32_t B, double* __restrict__ out)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > B) return;
+    if (k > B + 1) return;
     double v = 0.0;
-    for (uint32_t w = 0; w < nwg; ++w) v += part[(uint64_t)w * (B + 1) + k];
+    for (uint32_t w = 0; w < nwg; ++w) {
+        const double p = part[(uint64_t)w * (B + 2) + k];
+        v = k <= B ? v + p : (p > v ? p : v);
+    }
     out[k] = v;
 }
 
 // Fixed scratch of mdr_l2_table_noalloc: the partial rows of at most 1024
-// workgroups, then the tables of at most kL2NoAllocLevels levels, 65 entries
-// (B + 1 for B <= 64) each: 552,960 bytes per device, held until the process
-// ends.  Host code never passes this name to a kernel: it is a host-side
-// stand-in; the device address comes from hipGetSymbolAddress, per device.
-constexpr uint64_t kL2PartDoubles = 1024ull * 65;
-constexpr uint64_t kL2ScratchDoubles = kL2PartDoubles + (uint64_t)kL2NoAllocLevels * 65;
+// workgroups, then the rows of at most kL2NoAllocLevels levels, kL2RowMax
+// entries (B + 2 for B <= 64) each: 574,464 bytes per device, held until the
+// process ends.  Host code never passes this name to a kernel: it is a
+// host-side stand-in; the device address comes from hipGetSymbolAddress, per
+// device.
+constexpr uint64_t kL2PartDoubles = 1024ull * kL2RowMax;
+constexpr uint64_t kL2ScratchDoubles = kL2PartDoubles + (uint64_t)kL2NoAllocLevels * kL2RowMax;
 __device__ __align__(256) double scratch[kL2ScratchDoubles];
 
 constexpr int kMaxDevices = 64;
@@ -143,7 +167,7 @@ hipError_t launch_l2_table(bool f64, const void* x, uint64_t n, int e, uint32_t 
     }
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(128), 0, s, part, nwg, B, out);
+    hipLaunchKernelGGL(k_l2_final, dim3(1), dim3(128), 0, s, part, nwg, B, out);  // B + 2 <= 66 entries
     return hipGetLastError();
 }
 

@@ -239,10 +239,12 @@ hipError_t launch_copy_out(const CopySpans& sp, hipStream_t s);
 // kL2NoAllocLevels levels per call; its device address is resolved once per
 // device (l2_scratch_init, with the device current or made current), after
 // which l2_scratch hands out the partial-row and table areas
+constexpr uint32_t kL2RowMax = 66;  // a level's L2 row: E2[0..B] and the largest |x|, B <= 64
 constexpr uint32_t kL2NoAllocLevels = 64;
 hipError_t l2_scratch_init(int device);
 hipError_t l2_scratch(int device, double** part, double** out);
-// part: l2_table_workgroups(n) * (B + 1) doubles; out: B + 1 doubles; B <= 32 for f32, <= 64 for f64
+// part: l2_table_workgroups(n) * (B + 2) doubles; out: B + 2 doubles (the table, then the
+// largest |x| read); B <= 32 for f32, <= 64 for f64
 uint32_t l2_table_workgroups(uint64_t n);
 hipError_t launch_l2_table(bool f64, const void* x, uint64_t n, int e, uint32_t B, double* part, double* out,
                            hipStream_t s);

@@ -110,6 +110,18 @@ def test_l2_table_argument_checks(mdr, orc):
     r2 = mdr.Refactored.deserialize(ctx, blob)
     with pytest.raises(mdr.MdrError):
         r2.l2(0)                                               # not serialized
+    # values other than the refactored ones: rejected, no table kept; the
+    # deserialized copy takes the tables of the original values
+    other = [t * 2 if t.numel() else t for t in dev]
+    for fn in (r2.l2_table, r2.l2_table_noalloc):
+        with pytest.raises(mdr.MdrError) as ei:
+            fn(other)
+        assert ei.value.status == mdr.MDR_ERR_INVALID_ARG and "differ" in str(ei.value)
+        with pytest.raises(mdr.MdrError):
+            r2.l2(0)
+    r2.l2_table(dev)
+    r.l2_table(dev)
+    assert [r2.l2(l) for l in range(len(dev))] == [r.l2(l) for l in range(len(dev))]
     r2.close()
     r.close()
     ctx.close()
