@@ -170,11 +170,55 @@ __global__ __launch_bounds__(1024) void k_unit_plan(const LosslessArgs* __restri
 }
 
 // Huffman chunks are split among wavefronts in contiguous shares; a wavefront
-// walks its share in batches of 64-word groups (a chunk of huf_chunk symbols is
-// huf_chunk / 256 groups; lane l holds word l of a group), eight groups in
-// flight, never crossing a unit.  Code lengths and codes of the current unit
-// are cached in LDS.
-constexpr uint32_t kHufGroups = 8;  // 64-word groups per batch
+// walks its share in batches of kHufLoads wave-wide loads of 256 words (lane l
+// takes words 4l .. 4l+3 of each: sixteen consecutive symbols), never crossing
+// a unit.  A chunk of huf_chunk symbols is huf_chunk / 4 words: 16, 32 or 64
+// lanes of one load (chunks of 256, 512, 1024 symbols) or 2 or 4 whole loads
+// (2048, 4096), so a batch holds 16 / (huf_chunk / 256) chunks.  Code lengths
+// and codes of the current unit are cached in LDS.
+constexpr uint32_t kHufLoads = 4;
+static_assert(4096 / 256 <= 4 * kHufLoads, "a chunk of the largest size fits one batch");
+
+// inclusive scan of v over segments of `seg` lanes (16, 32 or 64: a uniform
+// value), by data-parallel moves: rows of 16 by shifts of 1, 2, 4, 8, then
+// row 0's last lane into row 1 and row 2's into row 3, then lane 31 into rows
+// 2 and 3
+__device__ __forceinline__ uint32_t seg_incl_scan(uint32_t v, uint32_t seg)
+{
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    if (seg >= 32) x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    if (seg >= 64) x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return (uint32_t)x;
+}
+
+// a batch's words, lane l's four of each load (0 past the batch's chunks or
+// the unit's end; `valid` counts the lane's words that are in)
+struct HufBatch {
+    uint32_t w[kHufLoads][4];
+    uint32_t valid[kHufLoads];
+};
+
+__device__ __forceinline__ void huf_load_batch(const uint32_t* g, uint64_t wb, uint32_t nwb, uint64_t nwu,
+                                               uint32_t lane, HufBatch& hb)
+{
+    const auto gg = gmem(g);
+#pragma unroll
+    for (uint32_t r = 0; r < kHufLoads; ++r) {
+        const uint32_t i0 = r * 256 + 4 * lane;
+        uint32_t nv = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; ++i) {
+            const bool ok = i0 + i < nwb && wb + i0 + i < nwu;
+            hb.w[r][i] = ok ? gg[wb + i0 + i] : 0u;
+            nv += ok ? 1u : 0u;
+        }
+        hb.valid[r] = nv;
+    }
+}
 
 __device__ __forceinline__ void wave_share(uint32_t total, uint32_t& c0, uint32_t& c1)
 {
@@ -191,17 +235,9 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
     return v;
 }
 
-// code bits of every Huffman chunk -> chunk_words[c] (words).  A wavefront
-// walks its share in batches of kCountGroups 64-word groups (lane l loads word
-// l of each: sixteen loads in flight), adds the code lengths of each word's
-// four bytes, and sums the sixteen per-lane values over the wavefront by
-// exchange: at each of the strides 32, 16, 8, 4 a lane keeps half of its
-// values and sends the other half to its partner, so after four rounds lane l
-// holds part of group l / 4, and two more rounds complete it (17 lane
-// exchanges instead of 6 for each group).
-constexpr uint32_t kCountGroups = 16;  // 64-word groups per batch; a chunk is at most 16 groups
-static_assert(4096 / 256 <= kCountGroups, "a chunk of the largest size fits one batch");
-
+// code bits of every Huffman chunk -> chunk_words[c] (words): per lane the
+// code lengths of its sixteen symbols, summed over each chunk's lanes by a
+// segmented scan (chunks over several loads carry their sum across them)
 __device__ __forceinline__ void huf_count_body(const LosslessArgs& A)
 {
     __shared__ uint32_t s_len[kThreads / 64][256];
@@ -209,8 +245,9 @@ __device__ __forceinline__ void huf_count_body(const LosslessArgs& A)
     const uint32_t total = A.counts[0];
     if (blockIdx.x == 0 && tid == 0) A.chunk_words[total] = 0;
     uint32_t* L = s_len[wave];
-    const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;  // words, groups per chunk
-    const uint32_t cpb = kCountGroups / wpl;                         // whole chunks per batch
+    const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;  // words, 256-symbol groups per chunk
+    const uint32_t cpb = 4 * kHufLoads / wpl;                       // chunks per batch
+    const uint32_t seg = min(64u, 16 * wpl), lpc = wpl > 4 ? wpl / 4 : 1;  // lanes a chunk takes of a load; loads a chunk
     uint32_t c0, c1;
     wave_share(total, c0, c1);
     uint32_t u = 0, cb_lo = 1, cb_hi = 0;  // chunks [cb_lo, cb_hi) belong to unit u
@@ -226,40 +263,30 @@ __device__ __forceinline__ void huf_count_body(const LosslessArgs& A)
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        const auto g = gmem(unit_rows(A, u));
         const uint32_t nbt = min(cpb, min(c1, cb_hi) - c);  // chunks in this batch
-        const uint32_t ng = nbt * wpl;
-        const uint64_t w0 = (uint64_t)(c - cb_lo) * cw + lane;
-        uint32_t v[kCountGroups], okm = 0;  // okm bit q: word q of this lane lies in the unit
+        HufBatch hb;
+        huf_load_batch(unit_rows(A, u), (uint64_t)(c - cb_lo) * cw, nbt * cw, nwu, lane, hb);
+        uint32_t run = 0;  // bits of the chunk's earlier loads (chunks over several loads)
 #pragma unroll
-        for (uint32_t q = 0; q < kCountGroups; ++q) {
-            const uint64_t wi = w0 + q * 64;
-            const bool ok = q < ng && wi < nwu;
-            v[q] = ok ? g[wi] : 0u;
-            okm |= ok ? 1u << q : 0u;
-        }
+        for (uint32_t r = 0; r < kHufLoads; ++r) {
+            uint32_t T = 0;
 #pragma unroll
-        for (uint32_t q = 0; q < kCountGroups; ++q) {
-            const uint32_t w = v[q];
-            const uint32_t bits = L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
-            v[q] = (okm >> q) & 1u ? bits : 0u;
-        }
-        // exchange rounds: stride M, half H of the values still held
-#pragma unroll
-        for (uint32_t M = 32, H = kCountGroups / 2; H >= 1; M >>= 1, H >>= 1) {
-            const bool up = (lane & M) != 0;
-#pragma unroll
-            for (uint32_t i = 0; i < H; ++i) {
-                const uint32_t send = up ? v[i] : v[i + H], keep = up ? v[i + H] : v[i];
-                v[i] = keep + __shfl_xor(send, M, 64);
+            for (uint32_t i = 0; i < 4; ++i) {
+                const uint32_t w = hb.w[r][i];
+                const uint32_t bits = L[w & 0xFF] + L[(w >> 8) & 0xFF] + L[(w >> 16) & 0xFF] + L[w >> 24];
+                T += i < hb.valid[r] ? bits : 0u;
+            }
+            const uint32_t x = seg_incl_scan(T, seg);
+            if (lpc == 1) {
+                const uint32_t cj = (r * 256 + 4 * lane) / cw;
+                if ((lane & (seg - 1)) == seg - 1 && cj < nbt) A.chunk_words[c + cj] = (x + 31) / 32;
+            } else {
+                if (r % lpc == 0) run = 0;
+                run += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+                const uint32_t cj = r / lpc;
+                if (r % lpc == lpc - 1 && lane == 0 && cj < nbt) A.chunk_words[c + cj] = (run + 31) / 32;
             }
         }
-        // lane l holds part of group l / 4: the four lanes of a group, then the
-        // wpl groups of a chunk
-        uint32_t t = v[0];
-        for (uint32_t d = 1; d < 4 * wpl; d <<= 1) t += __shfl_xor(t, d, 64);
-        const uint32_t j = lane / (4 * wpl);  // chunk of the batch whose total lane l holds
-        if ((lane & (4 * wpl - 1)) == 0 && j < nbt) A.chunk_words[c + j] = (t + 31) / 32;
         c += nbt;
     }
 }
@@ -472,7 +499,8 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
     const uint32_t total = A.counts[0];
     uint32_t* LC = s_lc[wave];
     const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;
-    const uint32_t cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;
+    const uint32_t cpb = 4 * kHufLoads / wpl;  // chunks per batch
+    const uint32_t seg = min(64u, 16 * wpl), lpc = wpl > 4 ? wpl / 4 : 1;
     uint32_t* bufs = s_buf + wave * cpb * buf_words;
     uint32_t c0, c1;
     wave_share(total, c0, c1);
@@ -495,64 +523,59 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
         const uint32_t nbt = min(cpb, min(c1, cb_hi) - c);
         for (uint32_t i = lane; i < nbt * buf_words; i += 64) bufs[i] = 0;
         sync_wave();
-        const auto g = gmem(unit_rows(A, u));
-        uint32_t run = 0;  // bits of the current chunk's earlier groups (wpl > kHufGroups)
-        for (uint32_t r0 = 0; r0 < (wpl > kHufGroups ? wpl : 1); r0 += kHufGroups) {
-            const uint32_t ng = wpl > kHufGroups ? min(kHufGroups, wpl - r0) : nbt * wpl;
-            const uint64_t w0 = (uint64_t)(c - cb_lo) * cw + (uint64_t)r0 * 64 + lane;
-            uint32_t wv[kHufGroups], pos[kHufGroups], lc[kHufGroups][4];
-            bool ok[kHufGroups];
+        HufBatch hb;
+        huf_load_batch(unit_rows(A, u), (uint64_t)(c - cb_lo) * cw, nbt * cw, nwu, lane, hb);
+        uint32_t run = 0;  // bits of the chunk's earlier loads (chunks over several loads)
 #pragma unroll
-            for (uint32_t q = 0; q < kHufGroups; ++q) {
-                const uint64_t wi = w0 + q * 64;
-                ok[q] = q < ng && wi < nwu;
-                wv[q] = ok[q] ? g[wi] : 0u;
-            }
+        for (uint32_t r = 0; r < kHufLoads; ++r) {
+            // the lane's sixteen (code, length) pairs, its bits, and where they start in the chunk
+            uint32_t lc[4][4], T = 0;
 #pragma unroll
-            for (uint32_t q = 0; q < kHufGroups; ++q) {
+            for (uint32_t i = 0; i < 4; ++i) {
                 uint32_t bits = 0;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    lc[q][b] = LC[(wv[q] >> (8 * b)) & 0xFF];
-                    bits += lc[q][b] >> 16;
+                for (uint32_t b = 0; b < 4; ++b) {
+                    lc[i][b] = LC[(hb.w[r][i] >> (8 * b)) & 0xFF];
+                    bits += lc[i][b] >> 16;
                 }
-                bits = ok[q] ? bits : 0u;
-                const uint32_t inc = wave_incl_scan(bits, lane);
-                pos[q] = inc - bits;
-                const uint32_t gt = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);  // the group's bits
-                // group q starts a chunk when q is a multiple of wpl (batches of whole chunks)
-                if (wpl <= kHufGroups && q % wpl == 0) run = 0;
-                pos[q] += run;
-                run += gt;
+                T += i < hb.valid[r] ? bits : 0u;
             }
+            const uint32_t x = seg_incl_scan(T, seg);
+            if (lpc > 1 && r % lpc == 0) run = 0;
+            const uint32_t pos = run + x - T;
+            if (lpc > 1) run += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+            if (T == 0) continue;
+            const uint32_t cj = lpc > 1 ? r / lpc : (r * 256 + 4 * lane) / cw;
+            uint32_t* buf = bufs + cj * buf_words;
+            // codes in order into a 64-bit accumulator that starts with the
+            // (pos mod 32) bits of the word before them: each filled word goes
+            // out, the first with an atomic OR (the lane before may hold its
+            // leading bits), later ones with plain stores (no other lane
+            // writes them), the last partial one with an atomic OR
+            uint64_t acc = 0;
+            uint32_t na = pos & 31u, wi = pos >> 5;
+            bool lead = true;
 #pragma unroll
-            for (uint32_t q = 0; q < kHufGroups; ++q) {
-                if (!ok[q]) continue;
-                uint32_t* buf = bufs + (wpl <= kHufGroups ? (q / wpl) * buf_words : 0);
-                // the word's four codes, concatenated first (at most 4 * 12 bits),
-                // then ORed into the chunk buffer in one to three pieces
-                uint64_t v = 0;
-                uint32_t T = 0;
+            for (uint32_t i = 0; i < 4; ++i) {
+                if (i >= hb.valid[r]) break;
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const uint32_t Ls = lc[q][b] >> 16;
-                    v = (v << Ls) | (lc[q][b] & 0xFFFFu);
-                    T += Ls;
-                }
-                const uint32_t p = pos[q], wi = p >> 5, o = p & 31, head = 32 - o;
-                if (T <= head) {
-                    atomicOr(&buf[wi], (uint32_t)(v << (head - T)));
-                } else {
-                    const uint32_t R = T - head;  // bits after the first word (1 .. 47)
-                    atomicOr(&buf[wi], (uint32_t)(v >> R));
-                    if (R <= 32) {
-                        atomicOr(&buf[wi + 1], (uint32_t)(v << (32 - R)));
-                    } else {
-                        atomicOr(&buf[wi + 1], (uint32_t)(v >> (R - 32)));
-                        atomicOr(&buf[wi + 2], (uint32_t)(v << (64 - R)));
+                for (uint32_t b = 0; b < 4; ++b) {
+                    const uint32_t Ls = lc[i][b] >> 16;
+                    acc = (acc << Ls) | (lc[i][b] & 0xFFFFu);
+                    na += Ls;
+                    if (na >= 32) {
+                        na -= 32;
+                        const uint32_t word = (uint32_t)(acc >> na);
+                        if (lead)
+                            atomicOr(&buf[wi], word);
+                        else
+                            buf[wi] = word;
+                        lead = false;
+                        ++wi;
                     }
                 }
             }
+            if (na) atomicOr(&buf[wi], (uint32_t)(acc << (32 - na)));
         }
         sync_wave();
         const UnitInfo& ui = A.units[u];
@@ -1144,7 +1167,7 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
     hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, sp);
     hipLaunchKernelGGL(k_unit_sizes, dim3(1), dim3(1024), 0, s, a_dev);
     const uint32_t buf_words = (a.huf_chunk * kLutBitsMax + 31) / 32 + 2;
-    const uint32_t wpl = a.huf_chunk / 256, cpb = wpl <= kHufGroups ? kHufGroups / wpl : 1;
+    const uint32_t wpl = a.huf_chunk / 256, cpb = 4 * kHufLoads / wpl;
     const size_t shmem = (size_t)(kThreads / 64) * cpb * buf_words * sizeof(uint32_t);
     hipLaunchKernelGGL(k_write, P, T, shmem, s, a_dev, buf_words);
     hipLaunchKernelGGL(k_rle_len, P, T, 0, s, a_dev);
