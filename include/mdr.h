@@ -60,7 +60,7 @@ typedef struct {
     uint32_t group_planes; /* m: planes per lossless group (default 4; >= 1, capped at nplanes) */
     uint32_t t_cr_milli;   /* T_cr x 1000: ratio threshold (default 2000)                       */
     uint64_t t_s_bytes;    /* T_s: groups of at most this many bytes are copied (default 4096)   */
-    uint32_t huf_chunk;    /* byte symbols per Huffman chunk (default 256; 256..4096, x256)     */
+    uint32_t huf_chunk;    /* byte symbols per Huffman chunk (default 256; 256, 512 .. 4096)    */
     uint32_t huf_lmax;     /* longest Huffman code (default 12; 8..12)                           */
     int32_t force_method;  /* -1: Alg. 2 decides (default); MDR_DC/RLE/HUF: used for every unit  */
 } mdr_codec_params;

@@ -142,8 +142,8 @@ mdr_status check_params(const mdr_codec_params& p, uint32_t B)
 {
     if (p.group_planes < 1 || p.group_planes > B)
         return fail(MDR_ERR_INVALID_ARG, "group_planes must be in [1, nplanes]");
-    if (p.huf_chunk < 256 || p.huf_chunk > 4096 || p.huf_chunk % 256)
-        return fail(MDR_ERR_UNSUPPORTED, "huf_chunk must be a multiple of 256 in [256, 4096]");
+    if (p.huf_chunk < 256 || p.huf_chunk > 4096 || (p.huf_chunk & (p.huf_chunk - 1)))
+        return fail(MDR_ERR_UNSUPPORTED, "huf_chunk must be 256, 512, 1024, 2048 or 4096");
     if (p.huf_lmax < 8 || p.huf_lmax > (uint32_t)kLutBitsMax)
         return fail(MDR_ERR_UNSUPPORTED, "huf_lmax must be in [8, 12]");
     if (p.force_method < -1 || p.force_method > MDR_HUF)

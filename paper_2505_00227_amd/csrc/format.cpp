@@ -252,7 +252,7 @@ mdr_status mdr_deserialize(mdr_context* ctx, const void* host, uint64_t bytes, m
     R->prm.huf_chunk = get<uint32_t>(in + 24);
     R->prm.huf_lmax = get<uint32_t>(in + 28);
     R->prm.force_method = get<int32_t>(in + 32);
-    if (R->prm.huf_chunk < 256 || R->prm.huf_chunk > 4096 || R->prm.huf_chunk % 256 ||
+    if (R->prm.huf_chunk < 256 || R->prm.huf_chunk > 4096 || (R->prm.huf_chunk & (R->prm.huf_chunk - 1)) ||
         R->prm.huf_lmax < 8 || R->prm.huf_lmax > (uint32_t)kLutBitsMax)
         return fail(MDR_ERR_UNSUPPORTED, "Huffman parameters not supported by this build");
     if (nlevels == 0 || nlevels > (bytes - kHeader) / record_bytes(B)) return corrupt("bad level count");

@@ -202,9 +202,24 @@ struct HufBatch {
     uint32_t valid[kHufLoads];
 };
 
-__device__ __forceinline__ void huf_load_batch(const uint32_t* g, uint64_t wb, uint32_t nwb, uint64_t nwu,
+__device__ __forceinline__ bool huf_load_batch(const uint32_t* g, uint64_t wb, uint32_t nwb, uint64_t nwu,
                                                uint32_t lane, HufBatch& hb)
 {
+    // a whole batch from a 16-byte boundary: one 16-byte load per lane and load
+    if (nwb == 256 * kHufLoads && wb + 256 * kHufLoads <= nwu &&
+        (reinterpret_cast<uintptr_t>(g + wb) & 15u) == 0) {
+        const auto p = gmem(reinterpret_cast<const u32x4*>(g + wb));
+#pragma unroll
+        for (uint32_t r = 0; r < kHufLoads; ++r) {
+            const u32x4 q = p[r * 64 + lane];
+            hb.w[r][0] = q.x;
+            hb.w[r][1] = q.y;
+            hb.w[r][2] = q.z;
+            hb.w[r][3] = q.w;
+            hb.valid[r] = 4;
+        }
+        return true;
+    }
     const auto gg = gmem(g);
 #pragma unroll
     for (uint32_t r = 0; r < kHufLoads; ++r) {
@@ -218,6 +233,7 @@ __device__ __forceinline__ void huf_load_batch(const uint32_t* g, uint64_t wb, u
         }
         hb.valid[r] = nv;
     }
+    return false;
 }
 
 __device__ __forceinline__ void wave_share(uint32_t total, uint32_t& c0, uint32_t& c1)
@@ -485,15 +501,86 @@ __global__ __launch_bounds__(1024) void k_unit_sizes(const LosslessArgs* __restr
     }
 }
 
-// Huffman payloads.  Per batch every chunk gets an LDS buffer: a lane's bits
-// start at the exclusive scan of its group plus the bits of the chunk's earlier
-// groups, codes go in with atomic ORs, and each chunk's words leave coalesced.
-// A chunk's wavefront writes its offset; the first chunk's the header, the last
-// one's the closing offset.
+// Huffman payloads.  A batch's chunks go back to back into the wave's LDS
+// buffer, each from a word boundary as in the stream: a lane's bits start at
+// its chunk's word offset (the batch's earlier chunks, from their segment
+// totals) plus the exclusive scan of its group plus the bits of the chunk's
+// earlier loads.  A lane's sixteen codes go in as eight pairs (at most 24 bits,
+// so one or two words each) with atomic ORs; the batch then leaves as one
+// coalesced run of words, and each chunk's first lane writes its offset.  The
+// first chunk's wavefront writes the header, the last one's the closing offset.
+template <bool FULL>
+__device__ __forceinline__ void huf_emit_load(const HufBatch& hb, uint32_t r, const uint32_t* LC, uint32_t* buf,
+                                              uint32_t seg, uint32_t lpc, uint32_t nbt, uint32_t lane,
+                                              uint32_t& boff, uint32_t& run, uint32_t* off, uint32_t gw)
+{
+    // the lane's eight code pairs (code, length), in stream order
+    uint32_t cp[8], lp[8], T = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+        const uint32_t w = hb.w[r][i];
+        const bool in = FULL || i < hb.valid[r];
+#pragma unroll
+        for (uint32_t p = 0; p < 2; ++p) {
+            const uint32_t a = LC[(w >> (16 * p)) & 0xFF], b = LC[(w >> (16 * p + 8)) & 0xFF];
+            const uint32_t lb = b >> 16, L = (a >> 16) + lb;
+            cp[2 * i + p] = in ? ((a & 0xFFFFu) << lb) | (b & 0xFFFFu) : 0u;
+            lp[2 * i + p] = in ? L : 0u;
+            T += in ? L : 0u;
+        }
+    }
+    const uint32_t x = seg_incl_scan(T, seg);
+    uint32_t pos;
+    if (lpc == 1) {
+        // chunks of this load: one per segment; the lane's chunk starts after
+        // the earlier segments' words
+        const uint32_t sg = lane / seg;
+        uint32_t coff = boff, add = 0;
+        for (uint32_t k = 0; k < 64 / seg; ++k) {
+            const uint32_t wk = ((uint32_t)__builtin_amdgcn_readlane((int)x, (int)(k * seg + seg - 1)) + 31) / 32;
+            coff += sg > k ? wk : 0u;
+            add += wk;
+        }
+        const uint32_t cj = r * (64 / seg) + sg;
+        if ((lane & (seg - 1)) == 0 && cj < nbt) *gmem(off + cj) = gw + coff;
+        pos = 32 * coff + x - T;
+        boff += add;
+    } else {
+        if (r % lpc == 0) {
+            run = 0;
+            if (lane == 0 && r / lpc < nbt) *gmem(off + r / lpc) = gw + boff;
+        }
+        pos = 32 * boff + run + x - T;
+        run += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+        if (r % lpc == lpc - 1) boff += (run + 31) / 32;
+    }
+    if (T != 0) {
+        uint32_t P = pos;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            // bits [P, P + lp) of the stream, most significant first: in the
+            // 64-bit window of words P / 32 and P / 32 + 1 the pair's last bit
+            // sits 64 - lp - P % 32 bits up (an empty pair adds nothing)
+            const uint64_t v = (uint64_t)cp[k] << ((64u - lp[k] - (P & 31u)) & 63u);
+            uint32_t* q = buf + (P >> 5);
+            atomicOr(q, (uint32_t)(v >> 32));
+            atomicOr(q + 1, (uint32_t)v);
+            P += lp[k];
+        }
+    }
+}
+
+// LDS words of one wave's batch buffer: cpb chunks of at most chunk * 12 bits,
+// plus the word after the last (a pair's second OR may touch it), in 16-byte units
+__host__ __device__ constexpr uint32_t huf_buf_words(uint32_t huf_chunk)
+{
+    return ((4 * kHufLoads / (huf_chunk / 256)) * ((huf_chunk * kLutBitsMax + 31) / 32) + 4 + 3) / 4 * 4;
+}
+
 __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t buf_words)
 {
-    extern __shared__ uint32_t s_buf[];  // [kThreads / 64][cpb][buf_words]
-    __shared__ uint32_t s_lc[kThreads / 64][256];  // code | length << 16 of each symbol
+    extern __shared__ __align__(16) uint32_t s_buf[];  // [kThreads / 64][buf_words]
+    __shared__ uint32_t s_lc[kThreads / 64][256];      // code | length << 16 of each symbol
     if (A.counts[2]) return;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t total = A.counts[0];
@@ -501,11 +588,13 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
     const uint32_t cw = A.huf_chunk / 4, wpl = A.huf_chunk / 256;
     const uint32_t cpb = 4 * kHufLoads / wpl;  // chunks per batch
     const uint32_t seg = min(64u, 16 * wpl), lpc = wpl > 4 ? wpl / 4 : 1;
-    uint32_t* bufs = s_buf + wave * cpb * buf_words;
+    const uint32_t cmax = (A.huf_chunk * kLutBitsMax + 31) / 32;  // words of a chunk at most
+    uint32_t* buf = s_buf + wave * buf_words;
     uint32_t c0, c1;
     wave_share(total, c0, c1);
-    uint32_t u = 0, cb_lo = 1, cb_hi = 0;
+    uint32_t u = 0, cb_lo = 1, cb_hi = 0, nch = 0, base = 0;
     uint64_t nwu = 0;
+    uint8_t* pay = nullptr;
     auto sync_wave = [] {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -517,88 +606,45 @@ __device__ __forceinline__ void huf_write_body(const LosslessArgs& A, uint32_t b
             cb_lo = A.chunk_base[u];
             cb_hi = A.chunk_base[u + 1];
             nwu = A.units[u].S / 4;
+            nch = A.units[u].nchunks;
+            base = A.chunk_words[cb_lo];
+            pay = A.arena + A.pay_off[u];
             for (uint32_t k = lane; k < 256; k += 64)
                 LC[k] = A.codes[(uint64_t)u * 256 + k] | ((uint32_t)A.lens[(uint64_t)u * 256 + k] << 16);
         }
         const uint32_t nbt = min(cpb, min(c1, cb_hi) - c);
-        for (uint32_t i = lane; i < nbt * buf_words; i += 64) bufs[i] = 0;
+        // zero the batch's words (and the one after them) for the ORs
+        const uint32_t nclr = (nbt * cmax + 4) / 4;
+        for (uint32_t i = lane; i < nclr; i += 64) reinterpret_cast<u32x4*>(buf)[i] = u32x4{0u, 0u, 0u, 0u};
         sync_wave();
         HufBatch hb;
-        huf_load_batch(unit_rows(A, u), (uint64_t)(c - cb_lo) * cw, nbt * cw, nwu, lane, hb);
-        uint32_t run = 0;  // bits of the chunk's earlier loads (chunks over several loads)
+        const bool full = huf_load_batch(unit_rows(A, u), (uint64_t)(c - cb_lo) * cw, nbt * cw, nwu, lane, hb);
+        const uint32_t lc0 = c - cb_lo;               // the batch's first chunk in the unit
+        const uint32_t gw = A.chunk_words[c] - base;  // and its first word in the stream
+        uint32_t* const poff = reinterpret_cast<uint32_t*>(pay + kHufHeader);
+        const auto off = gmem(poff);
+        const auto words = off + nch + 1;
+        uint32_t boff = 0, run = 0;  // words of the batch's finished chunks; bits of the chunk's earlier loads
+        if (full) {
 #pragma unroll
-        for (uint32_t r = 0; r < kHufLoads; ++r) {
-            // the lane's sixteen (code, length) pairs, its bits, and where they start in the chunk
-            uint32_t lc[4][4], T = 0;
+            for (uint32_t r = 0; r < kHufLoads; ++r)
+                huf_emit_load<true>(hb, r, LC, buf, seg, lpc, nbt, lane, boff, run, poff + lc0, gw);
+        } else {
 #pragma unroll
-            for (uint32_t i = 0; i < 4; ++i) {
-                uint32_t bits = 0;
-#pragma unroll
-                for (uint32_t b = 0; b < 4; ++b) {
-                    lc[i][b] = LC[(hb.w[r][i] >> (8 * b)) & 0xFF];
-                    bits += lc[i][b] >> 16;
-                }
-                T += i < hb.valid[r] ? bits : 0u;
-            }
-            const uint32_t x = seg_incl_scan(T, seg);
-            if (lpc > 1 && r % lpc == 0) run = 0;
-            const uint32_t pos = run + x - T;
-            if (lpc > 1) run += (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-            if (T == 0) continue;
-            const uint32_t cj = lpc > 1 ? r / lpc : (r * 256 + 4 * lane) / cw;
-            uint32_t* buf = bufs + cj * buf_words;
-            // codes in order into a 64-bit accumulator that starts with the
-            // (pos mod 32) bits of the word before them: each filled word goes
-            // out, the first with an atomic OR (the lane before may hold its
-            // leading bits), later ones with plain stores (no other lane
-            // writes them), the last partial one with an atomic OR
-            uint64_t acc = 0;
-            uint32_t na = pos & 31u, wi = pos >> 5;
-            bool lead = true;
-#pragma unroll
-            for (uint32_t i = 0; i < 4; ++i) {
-                if (i >= hb.valid[r]) break;
-#pragma unroll
-                for (uint32_t b = 0; b < 4; ++b) {
-                    const uint32_t Ls = lc[i][b] >> 16;
-                    acc = (acc << Ls) | (lc[i][b] & 0xFFFFu);
-                    na += Ls;
-                    if (na >= 32) {
-                        na -= 32;
-                        const uint32_t word = (uint32_t)(acc >> na);
-                        if (lead)
-                            atomicOr(&buf[wi], word);
-                        else
-                            buf[wi] = word;
-                        lead = false;
-                        ++wi;
-                    }
-                }
-            }
-            if (na) atomicOr(&buf[wi], (uint32_t)(acc << (32 - na)));
+            for (uint32_t r = 0; r < kHufLoads; ++r)
+                huf_emit_load<false>(hb, r, LC, buf, seg, lpc, nbt, lane, boff, run, poff + lc0, gw);
         }
         sync_wave();
-        const UnitInfo& ui = A.units[u];
-        const uint32_t nch = ui.nchunks, first = cb_lo;
-        uint8_t* pay = A.arena + A.pay_off[u];
-        const auto off = gmem(reinterpret_cast<uint32_t*>(pay + kHufHeader));
-        const auto words = off + nch + 1;
-        const uint32_t base = A.chunk_words[first];
-        for (uint32_t j = 0; j < nbt; ++j) {
-            const uint32_t cc = c + j, lc = cc - first;
-            const uint32_t w0 = A.chunk_words[cc] - base, nw = A.chunk_words[cc + 1] - A.chunk_words[cc];
-            const uint32_t* buf = bufs + j * buf_words;
-            for (uint32_t i = lane; i < nw; i += 64) words[w0 + i] = buf[i];
-            if (lane == 0) off[lc] = w0;
-            if (lc + 1 == nch && lane == 0) off[nch] = A.chunk_words[first + nch] - base;
-            if (lc == 0) {
-                if (lane == 0) *reinterpret_cast<uint64_t*>(pay) = ui.S;
-                const uint32_t b4 = lane * 4;
-                reinterpret_cast<uint32_t*>(pay + 8)[lane] = (LC[b4] >> 16) | ((LC[b4 + 1] >> 16) << 8) |
-                                                             ((LC[b4 + 2] >> 16) << 16) | ((LC[b4 + 3] >> 16) << 24);
-            }
+        for (uint32_t i = lane; i < boff; i += 64) words[gw + i] = buf[i];
+        if (lane == 0 && lc0 + nbt == nch) off[nch] = gw + boff;
+        if (lc0 == 0) {
+            const UnitInfo& ui = A.units[u];
+            if (lane == 0) *reinterpret_cast<uint64_t*>(pay) = ui.S;
+            const uint32_t b4 = lane * 4;
+            reinterpret_cast<uint32_t*>(pay + 8)[lane] = (LC[b4] >> 16) | ((LC[b4 + 1] >> 16) << 8) |
+                                                         ((LC[b4 + 2] >> 16) << 16) | ((LC[b4 + 3] >> 16) << 24);
         }
-        sync_wave();  // the buffers are cleared again by the next batch
+        sync_wave();  // the buffer is cleared again by the next batch
         c += nbt;
     }
 }
@@ -1166,9 +1212,8 @@ hipError_t launch_lossless_batch(const LosslessArgs& a, const LosslessArgs* a_de
     hipLaunchKernelGGL(k_scan_dev_mid, dim3(1), dim3(1024), 0, s, sp, kPersistWg);
     hipLaunchKernelGGL(k_scan_dev_fin, P, T, 0, s, sp);
     hipLaunchKernelGGL(k_unit_sizes, dim3(1), dim3(1024), 0, s, a_dev);
-    const uint32_t buf_words = (a.huf_chunk * kLutBitsMax + 31) / 32 + 2;
-    const uint32_t wpl = a.huf_chunk / 256, cpb = 4 * kHufLoads / wpl;
-    const size_t shmem = (size_t)(kThreads / 64) * cpb * buf_words * sizeof(uint32_t);
+    const uint32_t buf_words = huf_buf_words(a.huf_chunk);
+    const size_t shmem = (size_t)(kThreads / 64) * buf_words * sizeof(uint32_t);
     hipLaunchKernelGGL(k_write, P, T, shmem, s, a_dev, buf_words);
     hipLaunchKernelGGL(k_rle_len, P, T, 0, s, a_dev);
     return hipGetLastError();

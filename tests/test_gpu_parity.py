@@ -79,11 +79,19 @@ def test_ratio_thresholds(mdr, ctx, t_cr):
     run_case(mdr, ctx, [x], 32, mdr.default_params(group_planes=4, t_cr_milli=t_cr))
 
 
-@pytest.mark.parametrize("chunk,lmax", [(256, 8), (512, 10), (4096, 12)])
+@pytest.mark.parametrize("chunk,lmax", [(256, 8), (512, 10), (2048, 11), (4096, 12)])
 def test_huffman_params(mdr, ctx, chunk, lmax):
     x = workloads.plain_level(seed=50, n=100000)
     run_case(mdr, ctx, [x], 32, mdr.default_params(group_planes=2, huf_chunk=chunk, huf_lmax=lmax,
                                                    force_method=2))
+
+
+@pytest.mark.parametrize("chunk", [128, 768, 3840, 8192])
+def test_huffman_chunk_not_power_of_two_rejected(mdr, ctx, chunk):
+    x = workloads.plain_level(seed=51, n=10000)
+    with pytest.raises(mdr.MdrError) as ei:
+        mdr.refactor(ctx, upload([x]), 32, mdr.default_params(huf_chunk=chunk))
+    assert ei.value.status == mdr.MDR_ERR_UNSUPPORTED
 
 
 def test_special_values(mdr, ctx):
