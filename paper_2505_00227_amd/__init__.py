@@ -276,7 +276,10 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.mdr_context_destroy(self.handle)
+            # at interpreter exit the module may already be torn down:
+            # the process releases everything then
+            if _lib is not None:
+                _lib.mdr_context_destroy(self.handle)
             self.handle = None
 
     def set_timing(self, enable: bool = True) -> None:
@@ -358,7 +361,8 @@ class Refactored:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.mdr_refactored_destroy(self.handle)
+            if _lib is not None:
+                _lib.mdr_refactored_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -489,7 +493,8 @@ class Retriever:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.mdr_retriever_destroy(self.handle)
+            if _lib is not None:
+                _lib.mdr_retriever_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -651,7 +656,8 @@ class Server:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.mdr_server_destroy(self.handle)
+            if _lib is not None:
+                _lib.mdr_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -716,7 +722,8 @@ class Pipeline:
 
     def close(self):
         if getattr(self, "handle", None):
-            _lib.mdr_pipeline_destroy(self.handle)
+            if _lib is not None:
+                _lib.mdr_pipeline_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -206,6 +206,29 @@ bool plan_step(const mdr_refactored* r, std::vector<uint32_t>& k, ErrTable tab)
 double plan_to(const mdr_refactored* r, double tol, std::vector<uint32_t>& k, ErrTable tab)
 {
     double b = plan_bound(r, k, tab);
+    if (b <= tol) return b;
+    // When every table is non-increasing along the steps the greedy can take,
+    // so is the bound (a sum in fixed order of non-increasing terms), and if
+    // even every plane of every level leaves it above tol the greedy can only
+    // end with all of them: take that plan at once (a retrieval of everything
+    // would otherwise walk one group at a time through every level).
+    {
+        const uint32_t B = r->B, m = r->m;
+        bool monotone = true;
+        for (size_t l = 0; l < r->levels.size() && monotone; ++l) {
+            const std::vector<double>& E = r->levels[l].*tab;
+            for (uint32_t kl = k[l]; kl < B && monotone; kl = std::min(B, kl + m))
+                monotone = E[std::min(B, kl + m)] <= E[kl];
+        }
+        if (monotone) {
+            std::vector<uint32_t> all(k.size(), B);
+            const double ball = plan_bound(r, all, tab);
+            if (ball > tol) {
+                k = all;
+                return ball;
+            }
+        }
+    }
     while (b > tol) {
         if (!plan_step(r, k, tab)) break;
         b = plan_bound(r, k, tab);

@@ -296,6 +296,7 @@ struct mdr_context {
     // job tables of retrieval launches
     mdr::DescSlot ring[mdr::kDescSlots];
     uint32_t ring_next = 0;
+    uint64_t ring_hw_host = 0, ring_hw_dev = 0;  // largest descriptor / device part requested
     void* stage = nullptr;  // pinned host staging
     uint64_t stage_bytes = 0;
 };

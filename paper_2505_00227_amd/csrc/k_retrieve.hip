@@ -96,6 +96,38 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
             return;
         }
     }
+    if constexpr (F64) {
+        // a wavefront of full blocks writes its 2048 consecutive values through
+        // LDS in two halves: each store instruction then fills eight whole
+        // 128-byte lines (half a block each) instead of a 16-byte piece of 64
+        // lines (rows padded to 17 values)
+        __shared__ double s_o64[kThreads / 64][64 * 17];
+        const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const uint64_t wblk0 = (uint64_t)(blockIdx.x - j.wg_base) * kThreads + wave * 64;
+        // uniform per wavefront: every block of it is full (none returned early)
+        if (vec && (wblk0 + 64) * 32 <= n) {
+            double* so = s_o64[wave];
+            const auto p = gmem(reinterpret_cast<f64x2*>(static_cast<double*>(j.out) + wblk0 * 32));
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int t = 0; t < 16; ++t) so[lane * 17 + t] = v[16 * h + t];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint32_t i2 = q * 64 + lane;            // 16-byte slot of the half
+                    const uint32_t b = i2 >> 3, t = (i2 & 7) * 2;  // its block and first value
+                    p[b * 16 + h * 8 + (i2 & 7)] = f64x2{so[b * 17 + t], so[b * 17 + t + 1]};
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            return;
+        }
+    }
     if (vec && cnt == 32) {
         if constexpr (F64) {
             const auto p = gmem(reinterpret_cast<f64x2*>(outg));

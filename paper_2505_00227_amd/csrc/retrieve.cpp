@@ -17,8 +17,40 @@ namespace {
 // buffer holds `bytes` and whose device buffer holds `dev_bytes` (>= bytes:
 // device-only scratch follows the descriptor).  A slot is reused only after
 // the event recorded behind the kernels that read it.
+// Grow a slot that no launch still reads to the ring's high-water sizes.
+static mdr_status grow_slot(mdr_context* ctx, DescSlot& d)
+{
+    if (d.bytes < ctx->ring_hw_host) {
+        const uint64_t want = std::max<uint64_t>(ctx->ring_hw_host + ctx->ring_hw_host / 2, 64 << 10);
+        if (d.host) (void)hipHostFree(d.host);
+        d.host = nullptr;
+        d.bytes = 0;
+        hipError_t e = hipHostMalloc(&d.host, want, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(descriptor)");
+        d.bytes = want;
+    }
+    if (d.dev_bytes < ctx->ring_hw_dev) {
+        const uint64_t want = std::max<uint64_t>(ctx->ring_hw_dev + ctx->ring_hw_dev / 2, 64 << 10);
+        d.dev_bytes = 0;
+        hipError_t e = d.dev.alloc(want);
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(descriptor)");
+        d.dev_bytes = want;
+    }
+    return MDR_OK;
+}
+
 DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, uint64_t dev_bytes, mdr_status& st)
 {
+    dev_bytes = std::max(dev_bytes, bytes);
+    // Calls of different kinds (a refactor's tables, a retrieval's with its
+    // decode-table scratch) take turns on the ring, so a slot sized for one
+    // kind meets the other a few calls later.  Every slot is therefore sized
+    // to the largest request seen so far, and a new largest one grows the idle
+    // slots too, at once: otherwise the calls after the first would each pay a
+    // pinned and a device reallocation.
+    const bool larger = bytes > ctx->ring_hw_host || dev_bytes > ctx->ring_hw_dev;
+    ctx->ring_hw_host = std::max(ctx->ring_hw_host, bytes);
+    ctx->ring_hw_dev = std::max(ctx->ring_hw_dev, dev_bytes);
     DescSlot& d = ctx->ring[ctx->ring_next++ % kDescSlots];
     st = MDR_OK;
     if (d.pending) {
@@ -36,29 +68,18 @@ DescSlot* acquire_slot(mdr_context* ctx, uint64_t bytes, uint64_t dev_bytes, mdr
             return nullptr;
         }
     }
-    if (d.bytes < bytes) {
-        const uint64_t want = std::max<uint64_t>(bytes + bytes / 2, 64 << 10);
-        if (d.host) (void)hipHostFree(d.host);
-        d.host = nullptr;
-        d.bytes = 0;
-        hipError_t e = hipHostMalloc(&d.host, want, hipHostMallocDefault);
-        if (e != hipSuccess) {
-            st = hip_fail(e, "hipHostMalloc(descriptor)");
-            return nullptr;
+    if ((st = grow_slot(ctx, d)) != MDR_OK) return nullptr;
+    if (larger)
+        for (DescSlot& o : ctx->ring) {
+            if (&o == &d) continue;
+            if (o.pending) {
+                const hipError_t q = hipEventQuery(o.done);
+                (void)hipGetLastError();  // a not-ready answer must not reach the launch checks
+                if (q != hipSuccess) continue;  // still read: grown on its next turn
+                o.pending = false;
+            }
+            if ((st = grow_slot(ctx, o)) != MDR_OK) return nullptr;
         }
-        d.bytes = want;
-    }
-    dev_bytes = std::max(dev_bytes, bytes);
-    if (d.dev_bytes < dev_bytes) {
-        const uint64_t want = std::max<uint64_t>(dev_bytes + dev_bytes / 2, 64 << 10);
-        d.dev_bytes = 0;
-        hipError_t e = d.dev.alloc(want);
-        if (e != hipSuccess) {
-            st = hip_fail(e, "hipMalloc(descriptor)");
-            return nullptr;
-        }
-        d.dev_bytes = want;
-    }
     return &d;
 }
 
