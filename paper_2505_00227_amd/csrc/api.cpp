@@ -134,6 +134,7 @@ mdr_status ensure_stage(mdr_context* ctx, uint64_t need)
     ctx->stage = nullptr;
     ctx->stage_bytes = 0;
     MDR_HIP(hipHostMalloc(&ctx->stage, need + need / 4, hipHostMallocDefault));
+    std::memset(ctx->stage, 0, need + need / 4);  // fault the pages in now, not in the calls that write them
     ctx->stage_bytes = need + need / 4;
     return MDR_OK;
 }

@@ -548,6 +548,7 @@ mdr_status refactor_batch(mdr_context* ctx, const VarLevels* vars, uint32_t nvar
             hipError_t e = ng->ws.alloc(ctx->pool, L.ws_bytes);
             if (e != hipSuccess) return hip_fail(e, "hipMalloc(batch workspace)");
             MDR_HIP(hipHostMalloc(&ng->stage, L.desc_bytes + L.meta_bytes, hipHostMallocDefault));
+            std::memset(ng->stage, 0, L.desc_bytes + L.meta_bytes);  // fault the pages in before capture
             ng->stage_bytes = L.desc_bytes + L.meta_bytes;
             if (!ctx->capture_stream)
                 MDR_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));

@@ -27,6 +27,9 @@ static mdr_status grow_slot(mdr_context* ctx, DescSlot& d)
         d.bytes = 0;
         hipError_t e = hipHostMalloc(&d.host, want, hipHostMallocDefault);
         if (e != hipSuccess) return hip_fail(e, "hipHostMalloc(descriptor)");
+        // touch every page now: the first writes to fresh pinned pages fault
+        // one page at a time (about 0.3 ms for a retrieval's tables)
+        std::memset(d.host, 0, want);
         d.bytes = want;
     }
     if (d.dev_bytes < ctx->ring_hw_dev) {
