@@ -855,8 +855,9 @@ __device__ __forceinline__ void load_table(const void* table, uint32_t words, ui
 // chunks), through the multi-symbol table: skewed groups, whose frequent
 // symbols have 1-3 bit codes, take a third of the dependent lookups of a
 // one-symbol table; a 4-byte entry keeps the table at 16 KiB, so that eight
-// workgroups fit a CU.  Compressed words are loaded eight ahead of their use,
-// and decoded bytes leave in 16-byte stores.
+// workgroups fit a CU.  Compressed words arrive in 16-byte blocks one block
+// ahead of their use, each iteration takes at most one word and makes two
+// lookups, and decoded bytes leave in 64-byte pieces.
 __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __restrict__ jobs,
                                                          const uint32_t* __restrict__ wg_job)
 {
@@ -890,72 +891,73 @@ __global__ __launch_bounds__(kThreads) void k_huf_decode(const DecodeJob* __rest
     const auto blk4 = gmem(reinterpret_cast<const u32x4*>(wbase & ~(uintptr_t)15));
     const uint32_t b0 = (wb + delta) >> 2, j0 = (wb + delta) & 3u, bl = (wl + delta) >> 2;
     u32x4 qa = blk4[b0], qb = blk4[min(b0 + 1, bl)];
-    uint32_t bnext = b0 + 2;
-    bool first = true;
+    uint32_t bnext = b0 + 2, jq = j0;  // qa's next word (the first block may begin before the chunk)
     uint64_t buf = 0;
     int nb = 0;
-    uint64_t pend = 0;  // decoded bytes not yet in a whole word (fewer than 4 between iterations)
+    uint64_t pend = 0;  // decoded bytes not yet in a whole word (at most three between lookups)
     uint32_t npend = 0, done = 0, wo = 0, nob = 0, nsl = 0;
     // decoded words leave in whole 64-byte pieces: ob collects four words, the
     // slots s0..s2 the three vectors before it (a line written at once is
     // written once; 16-byte pieces of lines far apart were written back piecemeal)
     u32x4 ob = {0, 0, 0, 0}, s0 = {0, 0, 0, 0}, s1 = {0, 0, 0, 0}, s2 = {0, 0, 0, 0};
-    bool more = done < cnt;
-    while (more) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (!more) break;
-            if (first && (uint32_t)j < j0) continue;  // words of the first block before the chunk
-            const uint32_t wj = j < 4 ? qa[j] : qb[j - 4];
-            buf |= (uint64_t)wj << (32 - nb);
-            nb += 32;
-            if (j == 3) qa = blk4[min(bnext++, bl)];
-            if (j == 7) {
-                qb = blk4[min(bnext++, bl)];
-                first = false;
-            }
-            // more than 32 bits in the buffer: a whole window for every lookup.
-            // The last lookup may decode up to two symbols past the chunk's
-            // end; they never complete a word, so they are never stored.
-            while (nb > 32 && done < cnt) {
-                const uint32_t e = s_multi[buf >> (64 - lmax)];
-                const uint32_t k = (e >> 24) & 3u, used = e >> 26;
-                pend |= (uint64_t)(e & 0xFFFFFFu) << (8 * npend);  // bytes past the k symbols are 0
-                npend += k;
-                done += k;
-                buf <<= used;
-                nb -= (int)used;
-                if (npend >= 4) {
-                    ob = u32x4{ob.y, ob.z, ob.w, (uint32_t)pend};  // oldest word first once full
-                    pend >>= 32;
-                    npend -= 4;
-                    if (++nob == 4) {
-                        nob = 0;
-                        if (nsl == 0) {
-                            s0 = ob;
-                        } else if (nsl == 1) {
-                            s1 = ob;
-                        } else if (nsl == 2) {
-                            s2 = ob;
-                        } else {
-                            dst4[wo] = s0;
-                            dst4[wo + 1] = s1;
-                            dst4[wo + 2] = s2;
-                            dst4[wo + 3] = ob;
-                            wo += 4;
-                        }
-                        nsl = (nsl + 1) & 3u;
-                    }
+    // One lookup: up to three symbols into pend, and a whole word out of it
+    // when there is one.  The window is whole: at least lmax bits are in the
+    // buffer (or the chunk's data has ended; symbols from the bits past it lie
+    // past its end, never complete a word, and are never stored).
+    auto lookup = [&]() {
+        const uint32_t e = s_multi[buf >> (64 - lmax)];
+        const uint32_t k = (e >> 24) & 3u, used = e >> 26;
+        pend |= (uint64_t)(e & 0xFFFFFFu) << (8 * npend);  // bytes past the k symbols are 0
+        npend += k;
+        done += k;
+        buf <<= used;
+        nb -= (int)used;
+        if (npend >= 4) {
+            ob = u32x4{ob.y, ob.z, ob.w, (uint32_t)pend};  // oldest word first once full
+            pend >>= 32;
+            npend -= 4;
+            if (++nob == 4) {
+                nob = 0;
+                if (nsl == 3) {
+                    dst4[wo] = s0;
+                    dst4[wo + 1] = s1;
+                    dst4[wo + 2] = s2;
+                    dst4[wo + 3] = ob;
+                    wo += 4;
+                    nsl = 0;
+                } else {
+                    // the held vectors move down one slot: after three, s0..s2 hold them in order
+                    s0 = s1;
+                    s1 = s2;
+                    s2 = ob;
+                    ++nsl;
                 }
             }
-            more = done < cnt;
         }
+    };
+    // Every lane takes at most one word and makes two lookups per iteration
+    // (a lookup uses at most lmax <= 12 bits, and after the refill at least 32
+    // are held), so a wavefront iterates as often as its longest chunk needs
+    // lookups, halved, instead of the sum over words of each word's slowest lane.
+    while (done < cnt) {
+        if (nb <= 32) {
+            const uint32_t w = jq == 0 ? qa.x : jq == 1 ? qa.y : jq == 2 ? qa.z : qa.w;
+            buf |= (uint64_t)w << (32 - nb);
+            nb += 32;
+            if (++jq == 4) {
+                jq = 0;
+                qa = qb;
+                qb = blk4[min(bnext++, bl)];
+            }
+        }
+        lookup();
+        if (done < cnt) lookup();
     }
     // a chunk ends on a word: the whole vectors held in the slots, then up to
     // three words, the newest nob of ob (in order)
-    if (nsl > 0) dst4[wo++] = s0;
+    if (nsl > 2) dst4[wo++] = s0;
     if (nsl > 1) dst4[wo++] = s1;
-    if (nsl > 2) dst4[wo++] = s2;
+    if (nsl > 0) dst4[wo++] = s2;
     const auto dst = gmem(reinterpret_cast<uint32_t*>(job.out + lo)) + 4 * wo;
     if (nob == 3) {
         dst[0] = ob.y;
