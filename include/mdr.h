@@ -143,8 +143,9 @@ mdr_status mdr_context_set_decode_lanes(mdr_context* ctx, uint32_t lanes);
 /* ---- Launch-shape autotuner (the batched pass's block and tile shapes) ----
  * A launch shape is the three knobs of the refactor pass: enc_target_wg and
  * stats_wg_values (above) and select_threads, the workgroup size of the
- * Alg. 2 selection kernel (256, 512 or 1024; default 512).  No knob changes a
- * result, bit for bit; only time.
+ * Alg. 2 selection kernel (256, 512 or 1024, or 0: chosen per pass, 256 when
+ * the pass selects at least 1024 units (levels x groups), 512 below; default
+ * 0).  No knob changes a result, bit for bit; only time.
  *
  * The context keeps a tuning table keyed by (dtype, nplanes, group size,
  * floor(log2(values in the pass)), floor(log2(levels in the pass))); a pass

@@ -302,7 +302,7 @@ class Context:
         _check(_lib.mdr_context_set_decode_lanes(self.handle, int(lanes)))
 
     def set_select_threads(self, threads: int) -> None:
-        """Workgroup size of the selection kernel (256, 512 or 1024)."""
+        """Workgroup size of the selection kernel (256, 512 or 1024; 0: by the pass's unit count)."""
         _check(_lib.mdr_context_set_select_threads(self.handle, int(threads)))
 
     def autotune(self, variables, nplanes: int, params: mdr_codec_params | None = None, reps: int = 2,

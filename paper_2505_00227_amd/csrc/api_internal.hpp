@@ -281,7 +281,7 @@ struct mdr_context {
     // batch refactor: launch shape and captured graphs
     uint32_t enc_target_wg = 2304;   // encoder workgroups a batch aims for
     uint32_t stats_wg_values = 65536;  // values per statistics workgroup (at most kStatsMaxWg per level)
-    uint32_t select_threads = 512;     // selection workgroup size
+    uint32_t select_threads = 0;       // selection workgroup size (0: by the pass's unit count)
     // launch-shape tuning table, its file, and tune-on-first-use
     std::vector<mdr::TuneEntry> tune;
     std::string tune_path;

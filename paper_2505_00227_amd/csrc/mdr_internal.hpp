@@ -102,6 +102,7 @@ struct SelectParams {
 // stage needs no host round trip; payloads go to one arena of capacity `cap`.
 constexpr uint32_t kRleTileWords = 4096;  // W-bit words per run-length tile
 constexpr uint32_t kPersistWg = 1024;     // workgroups of the persistent lossless kernels
+constexpr uint32_t kSelectManyUnits = 1024;  // units of a pass from which the selection runs 256-thread workgroups
 
 struct LosslessArgs {
     const EncodeJob* jobs;  // rows and nbd of each level

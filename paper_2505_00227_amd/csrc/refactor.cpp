@@ -163,6 +163,11 @@ mdr_status make_layout(const mdr_context* ctx, const VarLevels* vars, uint32_t n
         uint32_t tk[5];
         tune_key(dtype, B, L.m, total_values, L.J, tk);
         L.shape = effective_shape(ctx, tk);
+        // the selection builds each unit's code on one lane: with many units,
+        // smaller workgroups let more of them build at once (the 4896 units
+        // of 32 slabs of the 1024^3 field: 0.19 ms at 256 threads, 0.25 at
+        // 512), with few the larger ones' faster histogram and rank steps win
+        if (L.shape.select_threads == 0) L.shape.select_threads = L.U >= kSelectManyUnits ? 256u : 512u;
     }
 
     // every encoder workgroup walks about the same number of tiles, so that a

@@ -183,7 +183,7 @@ mdr_status load_file(mdr_context* ctx, const std::string& path)
             !json_uint(line, "select_threads", sel))
             return fail(MDR_ERR_CORRUPT_STREAM, "malformed tuning entry in " + path + ": " + line);
         if (d > 1 || B < 1 || B > 64 || m < 1 || enc < 64 || enc > 65536 || sv < 1024 || sv > (1u << 24) ||
-            (sel != 256 && sel != 512 && sel != 1024))
+            (sel != 0 && sel != 256 && sel != 512 && sel != 1024))
             return fail(MDR_ERR_CORRUPT_STREAM, "tuning entry out of range in " + path + ": " + line);
         TuneEntry e;
         e.key[0] = (uint32_t)d, e.key[1] = (uint32_t)B, e.key[2] = (uint32_t)m, e.key[3] = (uint32_t)vb,
@@ -293,8 +293,8 @@ extern "C" {
 mdr_status mdr_context_set_select_threads(mdr_context* ctx, uint32_t threads)
 {
     if (!ctx) return fail(MDR_ERR_INVALID_ARG, "ctx is NULL");
-    if (threads != 256 && threads != 512 && threads != 1024)
-        return fail(MDR_ERR_INVALID_ARG, "select_threads must be 256, 512 or 1024");
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return fail(MDR_ERR_INVALID_ARG, "select_threads must be 0 (by the pass), 256, 512 or 1024");
     ctx->select_threads = threads;
     return MDR_OK;
 }
