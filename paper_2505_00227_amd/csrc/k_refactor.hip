@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kStatsThreads) void k_stats(const StatsJob* __restr
         const auto xv4 = gmem(reinterpret_cast<const u32x4*>(job.x));
 #pragma unroll 4
         for (uint64_t i = tid0; i < nvec; i += stride) {
-            const u32x4 q = xv4[i];
+            const u32x4 q = __builtin_nontemporal_load(&xv4[i]);
             if constexpr (F64) {
                 acc.add(((uint64_t)q.y << 32) | q.x);
                 acc.add(((uint64_t)q.w << 32) | q.z);

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
 #pragma unroll
         for (int t = 0; t < 32; ++t) v[t] = T(0);
     } else {
-        const uint32_t sgn = gmem(s_rows[0])[blk];
+        const uint32_t sgn = __builtin_nontemporal_load(&gmem(s_rows[0])[blk]);
         uint32_t lo[32];
         uint32_t hi[F64 ? 32 : 1];
         // bit c lives in plane p = B-1-c, present when p < k, i.e. c >= B-k
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
 #pragma unroll
         for (int c = 0; c < 32; ++c) {
             const bool held = c < (int)B && c >= (int)(B - k);
-            const uint32_t w = gmem(s_rows[held ? B - c : 0])[blk];
+            const uint32_t w = __builtin_nontemporal_load(&gmem(s_rows[held ? B - c : 0])[blk]);
             lo[c] = held ? w : 0u;
         }
         transpose32(lo);
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
 #pragma unroll
             for (int c = 0; c < 32; ++c) {
                 const bool held = 32 + c < (int)B && 32 + c >= (int)(B - k);
-                const uint32_t w = gmem(s_rows[held ? B - 32 - c : 0])[blk];
+                const uint32_t w = __builtin_nontemporal_load(&gmem(s_rows[held ? B - 32 - c : 0])[blk]);
                 hi[c] = held ? w : 0u;
             }
             transpose32(hi);
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(kThreads) void k_reconstruct(const ReconJob* __rest
                 for (int q = 0; q < 8; ++q) {
                     const uint32_t i2 = q * 64 + lane;            // 16-byte slot of the half
                     const uint32_t b = i2 >> 3, t = (i2 & 7) * 2;  // its block and first value
-                    p[b * 16 + h * 8 + (i2 & 7)] = f64x2{so[b * 17 + t], so[b * 17 + t + 1]};
+                    __builtin_nontemporal_store(f64x2{so[b * 17 + t], so[b * 17 + t + 1]}, &p[b * 16 + h * 8 + (i2 & 7)]);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
