@@ -203,8 +203,9 @@ struct ReconJob {
     uint32_t vec;      // out is 16-byte aligned
 };
 // reconstruction of many levels (one dtype) in one launch; kThreads blocks per workgroup
+// streaming: the launch reads most of its levels' planes (streaming loads and stores)
 hipError_t launch_reconstruct_batch(const ReconJob* jobs, const uint32_t* wg_job, uint32_t grid,
-                                   bool f64, hipStream_t s);
+                                   bool f64, bool streaming, hipStream_t s);
 // V_total estimate of many (request, level) jobs of one dtype; acc must hold 0 first
 // QoI families, as mdr_qoi_kind numbers them
 constexpr uint32_t kQoiSumsq = 0, kQoiMagnitude = 1, kQoiProduct = 2;

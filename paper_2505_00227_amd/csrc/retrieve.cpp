@@ -324,10 +324,16 @@ mdr_status retrieve_many(mdr_context* ctx, RetrieveTask* tasks, size_t ntasks, h
         }
         for (int d = 0; d < 2; ++d) {
             if (map_r[d].empty()) continue;
+            // streaming loads and stores when the launch reads at least half of its planes
+            uint64_t held = 0, all = 0;
+            for (const ReconJob& j : rj[d]) {
+                held += (uint64_t)j.k * j.nbd;
+                all += (uint64_t)j.B * j.nbd;
+            }
             StageTimer tm(ctx, MDR_STAGE_RECONSTRUCT, s);
             MDR_HIP(launch_reconstruct_batch(reinterpret_cast<const ReconJob*>(dv + (d ? o_r1 : o_r0)),
                                              reinterpret_cast<const uint32_t*>(dv + (d ? o_m1 : o_m0)),
-                                             (uint32_t)map_r[d].size(), d == 1, s));
+                                             (uint32_t)map_r[d].size(), d == 1, 2 * held >= all, s));
         }
         MDR_HIP(hipEventRecord(slot->done, s));
         slot->pending = true;

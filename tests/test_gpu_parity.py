@@ -134,7 +134,9 @@ def test_multilevel_tolerances_and_incremental(mdr, ctx):
     r, orc = run_case(mdr, ctx, levels, 32, params, ks=[0, 32])
     outs = gpu_outputs(levels)
     inc = mdr.Retriever(ctx, r)
-    for rel in [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6]:
+    # 1e-13 and 0 lie below what every plane reaches (1e-9 near it): the
+    # planner's shortcut to every plane must give the greedy's planes and bound
+    for rel in [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-9, 1e-13, 0.0]:
         vals, k, bound, met = oracle.retrieve_to(orc, rel)
         fresh = mdr.Retriever(ctx, r)
         info = fresh.retrieve(rel, outs)
